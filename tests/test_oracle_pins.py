@@ -1,0 +1,445 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+None of these re-types an oracle formula: each compares the oracle with an
+independent statement (stated moments, conservation laws, a linearised
+continuum model built from the kinetic equation's coefficients, exact
+symmetries, lattice marginalisation, textbook lattice weights).
+"""
+import math
+import os
+from dataclasses import replace
+from types import SimpleNamespace
+
+import numpy as np
+import pytest
+
+from oracle import lbm_oracle as lo
+from workloads import synth
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _rng(seed=0):
+    return np.random.default_rng(seed)
+
+
+# --------------------------------------------------------------------------
+# Lattice / product form
+# --------------------------------------------------------------------------
+
+def test_d3q27_weights_golden():
+    """Product form at (xi=0, P=1/3) gives the textbook D3Q27 weights."""
+    rows = [l.split() for l in open(os.path.join(HERE, "golden", "d3q27_weights.txt"))
+            if l.strip() and not l.startswith("#")]
+    ref = {int(a): float(b) for a, b in rows}
+    c = lo.lattice_velocities(3)
+    w = lo.lattice_weights(c)
+    for i in range(27):
+        nnz = int(np.count_nonzero(c[i]))
+        assert abs(w[i] - ref[nnz]) < 1e-15
+    assert abs(w.sum() - 1.0) < 1e-15
+
+
+@pytest.mark.parametrize("D", [1, 2, 3])
+def test_species_equilibrium_moments(D):
+    """eq 27eq: sum f^eq = phi rho_a, sum f^eq c = rho_a u, sum f^eq c c = phi rho_a (v v + R_a T I)."""
+    r = _rng(D)
+    n = 50
+    c = lo.lattice_velocities(D)
+    phi = r.uniform(0.3, 1.0, n)
+    rho = r.uniform(0.5, 3.0, n)
+    RaT = r.uniform(0.02, 0.3, n)
+    v = r.uniform(-0.1, 0.1, (D, n))
+    f = lo.species_equilibrium(c, phi * rho, v, RaT)
+    assert np.allclose(f.sum(0), phi * rho, rtol=1e-14, atol=0)
+    for a in range(D):
+        m1 = (f * c[:, a, None]).sum(0)
+        assert np.allclose(m1, rho * phi * v[a], rtol=1e-13, atol=1e-16)
+        for b in range(D):
+            m2 = (f * (c[:, a] * c[:, b])[:, None]).sum(0)
+            exp = phi * rho * (v[a] * v[b] + (RaT if a == b else 0.0))
+            assert np.allclose(m2, exp, rtol=1e-13, atol=1e-16)
+
+
+@pytest.mark.parametrize("D", [1, 2, 3])
+def test_energy_equilibrium_moments(D):
+    """eqs g0momTotalEnergy, geq1mom, geq2mom: zeroth phi rho E, first (H + u^2/2phi^2) rho u,
+    second (H + u^2/2phi^2) P^eq + (P/phi) u u, with P^eq = phi rho v v + phi P I (eq Peq)."""
+    r = _rng(10 + D)
+    n = 40
+    c = lo.lattice_velocities(D)
+    phi = r.uniform(0.3, 1.0, n)
+    rho = r.uniform(0.5, 3.0, n)
+    RT = r.uniform(0.02, 0.3, n)
+    U = r.uniform(0.1, 2.0, n)
+    u = r.uniform(-0.05, 0.05, (D, n))
+    v = u / phi
+    g = lo.energy_equilibrium(c, phi * rho, U, RT, v)
+    u2 = (u * u).sum(0)
+    E = U + u2 / (2 * phi ** 2)
+    H = U + RT
+    P = rho * RT
+    assert np.allclose(g.sum(0), phi * rho * E, rtol=1e-13)
+    for a in range(D):
+        q = (g * c[:, a, None]).sum(0)
+        assert np.allclose(q, (H + u2 / (2 * phi ** 2)) * rho * u[a], rtol=1e-12, atol=1e-15)
+        for b in range(D):
+            R = (g * (c[:, a] * c[:, b])[:, None]).sum(0)
+            Peq = phi * rho * (u[a] / phi) * (u[b] / phi) + (phi * P if a == b else 0.0)
+            exp = (H + u2 / (2 * phi ** 2)) * Peq + (P / phi) * u[a] * u[b]
+            assert np.allclose(R, exp, rtol=1e-12, atol=1e-15)
+
+
+def test_reaction_population_moments():
+    """eqs Dotfr, m1fDotc: the source population carries rho_dot and rho_dot u / phi."""
+    r = _rng(3)
+    c = lo.lattice_velocities(3)
+    n = 30
+    phi = r.uniform(0.3, 1.0, n)
+    u = r.uniform(-0.05, 0.05, (3, n))
+    RaT = r.uniform(0.02, 0.3, n)
+    rdot = r.normal(size=n)
+    fr = rdot * lo.product_form(c, u / phi, (u / phi) ** 2 + RaT)
+    assert np.allclose(fr.sum(0), rdot, rtol=1e-13, atol=1e-15)
+    for a in range(3):
+        assert np.allclose((fr * c[:, a, None]).sum(0), rdot * u[a] / phi, rtol=1e-12, atol=1e-15)
+
+
+# --------------------------------------------------------------------------
+# Conservation (eq finalNumericalEquationsReactive, eq f)
+# --------------------------------------------------------------------------
+
+def test_conservation_without_drag():
+    w = synth.config1(nx=32, ny=16, pore_radius=float("inf"))
+    o = lo.Oracle(w)
+    m0 = o.fa.sum(axis=(1, 2))
+    M0 = o.f.sum()
+    scale = (o.f.sum(0) * np.sqrt(o.macro()["RT"])).sum()
+    o.step(300)
+    assert np.all(np.abs(o.fa.sum(axis=(1, 2)) - m0) / m0 < 1e-13)
+    assert abs(o.f.sum() - M0) / M0 < 1e-13
+    j = np.array([(o.f * o.c[:, d, None]).sum() for d in range(2)])
+    assert np.all(np.abs(j) / scale < 1e-13)
+
+
+def test_momentum_change_equals_knudsen_force():
+    """With the Knudsen drag on, the mixture momentum changes by exactly sum_x F^k per step."""
+    w = synth.config1(nx=32, ny=16)
+    o = lo.Oracle(w)
+    o.step(20)
+    for _ in range(5):
+        mac = o.macro()
+        j0 = mac["j"].sum(axis=1)
+        Fk = mac["Fk"].sum(axis=1)
+        o.step(1)
+        j1 = o.macro()["j"].sum(axis=1)
+        scale = np.abs(mac["Fk"]).sum() + 1e-300
+        assert np.all(np.abs((j1 - j0) - Fk) / scale < 1e-11)
+
+
+# --------------------------------------------------------------------------
+# Hydrodynamic limit (eqs dtrhoa, constit2; Appendix A)
+# --------------------------------------------------------------------------
+
+def _x1_mode(o, nx):
+    X = o.moments()["X"][0].reshape(-1, nx).mean(axis=0)
+    return np.fft.fft(X)[1] / (nx / 2)
+
+
+def test_binary_diffusion_decay_matches_D12():
+    """Knudsen off: the first Fourier mode of x_1 decays at D_12 k^2 (from eqs dtrhoa and
+    constit2 linearised at uniform pressure).  Diffusivity reduced 20x so the diffusive
+    mode separates from the acoustic and viscous ones."""
+    scale = 0.05
+    w = synth.config1(nx=64, ny=1, pore_radius=float("inf"))
+    w = replace(w, D_ref_lat=w.D_ref_lat * scale)
+    o = lo.Oracle(w)
+    ts, amps = [], []
+    o.step(1000)
+    for _ in range(10):
+        o.step(500)
+        ts.append(o.step_count)
+        amps.append(abs(_x1_mode(o, 64)))
+    rate = -np.polyfit(ts, np.log(amps), 1)[0]
+    k = 2 * math.pi / 64
+    D12 = 0.2 * scale    # synthetic binary diffusivity of the (2, 28) pair at the reference state
+    assert abs(rate / (D12 * k * k) - 1.0) < 3e-3
+
+
+def _dgm_linear_prediction(m, X, D12, Dk, phi, k, RaT, ts):
+    """Linearised continuum dusty-gas model written from the kinetic equation's
+    coefficients (eq stefanMaxwell): friction P X_a X_b / D_ab, Knudsen drag P X_a / D^k_a,
+    partial pressure phi rho_a R_a T, continuity phi d rho_a/dt + div(rho_a u_a) = 0."""
+    from scipy.linalg import expm
+    rho_a = X * 1.0 / RaT          # P = 1 in pressure units
+    P = (rho_a * RaT).sum()
+    A = np.zeros((4, 4), complex)
+    A[0, 2] = -1j * k / phi
+    A[1, 3] = -1j * k / phi
+    A[2, 0] = -1j * k * phi * RaT[0]
+    A[3, 1] = -1j * k * phi * RaT[1]
+    K12 = P * X[0] * X[1] / D12
+    # d(rho_a u_a)/dt += K12 (u_b - u_a) - P X_a / D^k_a u_a
+    A[2, 2] = -K12 / rho_a[0] - P * X[0] / Dk[0] / rho_a[0]
+    A[2, 3] = K12 / rho_a[1]
+    A[3, 3] = -K12 / rho_a[1] - P * X[1] / Dk[1] / rho_a[1]
+    A[3, 2] = K12 / rho_a[0]
+    x0 = np.array([0.01 / RaT[0], -0.01 / RaT[1], 0, 0], complex)   # isobaric x_1 perturbation
+    out = []
+    for t in ts:
+        s = expm(A * t) @ x0
+        cbar = rho_a / m
+        cp = s[:2] / m
+        out.append((cp[0] - X[0] * cp.sum()) / cbar.sum())
+    return np.array(out)
+
+
+def test_knudsen_decay_matches_linear_dusty_gas_model():
+    scale = 0.05
+    w = synth.config1(nx=64, ny=1, pore_radius=1e-6 * scale)
+    w = replace(w, D_ref_lat=w.D_ref_lat * scale)
+    o = lo.Oracle(w)
+    m = np.array([2.0, 28.0])
+    RaT = (1.0 / 3.0) * 2.0 / m
+    phi, tort = 0.4, 3.0
+    Dk = (phi / tort) * (2e-6 * scale / (3 * 1e-6)) * np.sqrt(8 * RaT / math.pi)   # Section 5.1, d_0 = 2 r_p
+    ts, amps = [], []
+    for _ in range(8):
+        o.step(500)
+        ts.append(o.step_count)
+        amps.append(_x1_mode(o, 64))
+    pred = _dgm_linear_prediction(m, np.array([0.5, 0.5]), 0.2 * scale, Dk, phi, 2 * math.pi / 64, RaT, ts)
+    ratio = np.abs(np.array(amps)) / np.abs(pred)
+    assert np.all(np.abs(ratio - 1.0) < 2e-3), ratio
+
+
+# --------------------------------------------------------------------------
+# Porosity placement: exact mean-field symmetry f(phi) = phi f(1)
+# --------------------------------------------------------------------------
+
+def _periodic_energy_workload(nx=16, ny=8, phi=1.0, seed=0):
+    r = _rng(seed)
+    w = synth.config2(nx=nx, ny=ny)
+    N = nx * ny
+    x1 = 0.5 + 0.05 * r.standard_normal(N)
+    T0 = 1073.0 * (1.0 + 0.02 * r.standard_normal(N))
+    P0 = synth.P_ATM * (1.0 + 0.01 * r.standard_normal(N))
+    return replace(w, bc_lo=synth.BC_PERIODIC, bc_hi=synth.BC_PERIODIC, pore_radius=float("inf"),
+                   X0=np.stack([x1, 1 - x1]), T0=T0, P0=P0, phi=np.full(N, phi))
+
+
+def test_porosity_scaling_symmetry_isothermal():
+    """Knudsen off, uniform phi: every phi-placement in the equilibria, the Galilean
+    correction and the extended velocity makes populations scale exactly as phi * f(phi=1)."""
+    base = synth.config1(nx=16, ny=8, pore_radius=float("inf"))
+    r = _rng(1)
+    x1 = 0.5 + 0.05 * r.standard_normal(base.N)
+    base = replace(base, X0=np.stack([x1, 1 - x1]), P0=synth.P_ATM * (1 + 0.01 * r.standard_normal(base.N)))
+    o1 = lo.Oracle(replace(base, phi=np.full(base.N, 1.0)))
+    o2 = lo.Oracle(replace(base, phi=np.full(base.N, 0.4)))
+    o1.step(60)
+    o2.step(60)
+    assert np.max(np.abs(o2.fa - 0.4 * o1.fa)) / np.max(np.abs(o1.fa)) < 1e-13
+    assert np.max(np.abs(o2.f - 0.4 * o1.f)) / np.max(np.abs(o1.f)) < 1e-13
+    assert np.max(np.abs(o2.macro()["u"] - 0.4 * o1.macro()["u"])) < 1e-13 * np.max(np.abs(o1.macro()["u"])) + 1e-20
+
+
+def test_porosity_scaling_symmetry_energy():
+    o1 = lo.Oracle(_periodic_energy_workload(phi=1.0))
+    o2 = lo.Oracle(_periodic_energy_workload(phi=0.5))
+    o1.step(40)
+    o2.step(40)
+    for a, b in ((o2.fa, o1.fa), (o2.f, o1.f), (o2.g, o1.g)):
+        assert np.max(np.abs(a - 0.5 * b)) / np.max(np.abs(b)) < 1e-12
+
+
+# --------------------------------------------------------------------------
+# Lattice reduction: the product form marginalises (Section 2.2)
+# --------------------------------------------------------------------------
+
+def _marginal(pop, c_hi, D_lo):
+    """Sum populations of the higher lattice over the last velocity component."""
+    Q_lo = 3 ** D_lo
+    out = np.zeros(pop.shape[:-2] + (Q_lo,) + pop.shape[-1:])
+    for i in range(c_hi.shape[0]):
+        i_lo = sum((c_hi[i, a] + 1) * 3 ** a for a in range(D_lo))
+        out[..., i_lo, :] += pop[..., i, :]
+    return out
+
+
+def test_d2q9_y_uniform_reduces_to_d1q3_with_energy():
+    nx = 24
+    w2 = _periodic_energy_workload(nx=nx, ny=3, phi=0.45, seed=4)
+    # make every y-row identical
+    for arr in ("X0", "T0", "P0", "phi"):
+        a = getattr(w2, arr)
+        a = a.reshape(a.shape[:-1] + (3, nx))
+        a[..., :, :] = a[..., :1, :]
+    w2 = replace(w2, pore_radius=1e-6, tort=np.full(w2.N, 2.0))
+    w1 = replace(w2, lattice=1, ny=1, X0=w2.X0[:, :nx], T0=w2.T0[:nx], P0=w2.P0[:nx],
+                 phi=w2.phi[:nx], tort=w2.tort[:nx])
+    o2, o1 = lo.Oracle(w2), lo.Oracle(w1)
+    o2.step(50)
+    o1.step(50)
+    for p2, p1 in ((o2.fa, o1.fa), (o2.f, o1.f), (o2.g, o1.g)):
+        mg = _marginal(p2, o2.c, 1)[..., :nx]
+        assert np.max(np.abs(mg - p1)) / np.max(np.abs(p1)) < 1e-13
+
+
+def test_d3q27_z_uniform_reduces_to_d2q9():
+    w2 = synth.config1(nx=12, ny=6)
+    r = _rng(7)
+    x1 = 0.5 + 0.05 * r.standard_normal(w2.N)
+    phi = r.uniform(0.3, 0.6, w2.N)
+    w2 = replace(w2, X0=np.stack([x1, 1 - x1]), phi=phi, tort=phi ** -0.5)
+    rep = lambda a: np.concatenate([a, a], axis=-1)
+    w3 = replace(w2, lattice=3, nz=2, X0=rep(w2.X0), P0=rep(w2.P0), T0=rep(w2.T0), phi=rep(w2.phi),
+                 tort=rep(w2.tort))
+    o3, o2 = lo.Oracle(w3), lo.Oracle(w2)
+    o3.step(40)
+    o2.step(40)
+    for p3, p2 in ((o3.fa, o2.fa), (o3.f, o2.f)):
+        mg = _marginal(p3, o3.c, 2)[..., :w2.N]
+        assert np.max(np.abs(mg - p2)) / np.max(np.abs(p2)) < 1e-13
+
+
+# --------------------------------------------------------------------------
+# Species velocity system (eqs transform1, stefanMaxwell)
+# --------------------------------------------------------------------------
+
+def test_species_solve_equals_paper_system_without_knudsen():
+    """R4 reduces to the printed V-form system when 1/tau^k = 0."""
+    w = synth.config5(nx=24, ny=6)
+    w = replace(w, pore_radius=float("inf"), bc_lo=0, bc_hi=0)
+    o = lo.Oracle(w)
+    o.step(30)
+    mac = o.macro()
+    M = o.M
+    for n in range(0, o.N, 7):
+        A = np.zeros((M, M))
+        for a in range(M):
+            A[a, a] = 1.0 + 0.5 * mac["inv_tau_a"][a, n]
+            for b in range(M):
+                if b != a:
+                    A[a, b] = -0.5 * mac["inv_tau_ab"][a, b, n] * mac["Y"][b, n]
+        for d in range(2):
+            rhs = mac["jt"][:, d, n] / mac["rho_a"][:, n] - mac["u"][d, n]
+            V = np.linalg.solve(A, rhs)
+            assert np.allclose(V, mac["Va"][:, d, n], rtol=1e-10, atol=1e-16)
+
+
+def test_lb_momentum_is_trapezoidal_shift_of_kinetic_momentum():
+    """The LB first moment equals rho_a u_a - 1/2 (first moment of the kinetic collision
+    term of eq stefanMaxwell), with the kinetic coefficients P X_a X_b / D_ab and
+    P X_a / D^k_a taken straight from the paper (Knudsen on, 3 species), P X_a being the
+    partial pressure rho_a R_a T of Section 2.1."""
+    w = synth.config5(nx=24, ny=6)
+    w = replace(w, bc_lo=0, bc_hi=0)
+    o = lo.Oracle(w)
+    o.step(30)
+    mac = o.macro()
+    M, D = o.M, 2
+    X, T = mac["X"], mac["T"]
+    RaT = mac["RaT"]
+    Pa = mac["rho_a"] * RaT                        # Dalton partial pressures
+    P = Pa.sum(0)
+    Dab = w.D_ref_lat[:, :, None] * ((T / w.T_ref) ** 1.5 / P)[None, None, :]
+    Dk = (o.phi / o.tort)[None, :] * (2 * w.pore_radius / (3 * w.dx)) * np.sqrt(8 * RaT / math.pi)
+    for d in range(D):
+        for a in range(M):
+            ua = mac["ja"][a, d] / mac["rho_a"][a]
+            om = -Pa[a] / Dk[a] * ua
+            for b in range(M):
+                if b != a:
+                    ub = mac["ja"][b, d] / mac["rho_a"][b]
+                    om = om + Pa[a] * X[b] / Dab[a, b] * (ub - ua)
+            lhs = mac["jt"][a, d]
+            rhs = mac["ja"][a, d] - 0.5 * om
+            assert np.allclose(lhs, rhs, rtol=1e-10, atol=1e-14 * np.abs(mac["ja"]).max())
+
+
+# --------------------------------------------------------------------------
+# Surface chemistry (Section 4 with reading R13)
+# --------------------------------------------------------------------------
+
+def _chem_oracle(steps=3):
+    w = synth.config4_column(length=12, phi=0.4, current_A_cm2=0.0, n_sub=2, n_newton=4)
+    w = replace(w, faradaic_rate=None)
+    o = lo.Oracle(w)
+    o.step(steps)
+    return o
+
+
+def test_chemistry_conserves_sites_and_mass():
+    o = _chem_oracle()
+    mac = o.macro()
+    src, th = o.chemistry(mac)
+    mech = o.mech
+    assert np.all(np.abs(th.sum(0) - 1.0) < 1e-13)
+    gas = (src * o.rho_unit).sum(0)                                          # kg/m^3 total volume
+    surf = mech.a_s * mech.gamma * ((th - o.theta) * mech.surf_mass[:, None]).sum(0)
+    scale = (o.phi * mac["rho_a"].sum(0)) * o.rho_unit
+    assert np.all(np.abs(gas + surf) / scale < 1e-13)
+    assert np.any(np.abs(gas) / scale > 1e-8)          # chemistry actually did something
+
+
+def test_coverages_stay_valid_over_run():
+    o = _chem_oracle(steps=25)
+    assert np.all(np.abs(o.theta.sum(0) - 1.0) < 1e-12)
+    assert np.all(o.theta > -1e-12)
+
+
+def test_langmuir_isotherm():
+    """One reaction G + V <-> A(s) with the gas held fixed reaches
+    theta_A = K c / (1 + K c), K = kf / kb."""
+    m = np.array([0.002, 0.028])
+    nu_f = np.array([[1, 0, 1, 0]], dtype=np.int32)
+    nu_b = np.array([[0, 0, 0, 1]], dtype=np.int32)
+    mech = synth.Mechanism(K=2, nu_f=nu_f, nu_b=nu_b, A_f=np.array([3e11]), Ea_f=np.array([60e3]),
+                           A_b=np.array([2e14]), Ea_b=np.array([90e3]), gamma=2.6e-5, a_s=1e7,
+                           surf_mass=np.array([0.0, 0.002]), theta0=np.array([1.0, 0.0]),
+                           n_sub=2, n_newton=5)
+    N = 4
+    w = synth.Workload(name="langmuir", lattice=1, nx=N, ny=1, nz=1, molar_mass=m,
+                       D_ref_lat=synth.synthetic_D_ref(np.array([2.0, 28.0])),
+                       X0=np.array([[0.3] * N, [0.7] * N]), P0=np.full(N, synth.P_ATM),
+                       T0=np.full(N, 1073.0), phi=np.full(N, 0.5), tort=np.ones(N),
+                       pore_radius=float("inf"), steps=1, mech=mech)
+    o = lo.Oracle(w)
+    mac = o.macro()
+    for _ in range(400):
+        src, th = o.chemistry(mac)
+        o.theta = th                      # gas composition held at its initial value
+    c = mac["rho_a"][0] * o.rho_unit / m[0]
+    R_U = 8.314462618
+    K = (3e11 * math.exp(-60e3 / (R_U * 1073.0))) / (2e14 * math.exp(-90e3 / (R_U * 1073.0)))
+    theta_A = K * c / (1 + K * c)
+    assert np.allclose(o.theta[1], theta_A, rtol=1e-10)
+
+
+# --------------------------------------------------------------------------
+# Energy lattice: isobaric thermal decay (eqs dtE, qneq, lambda)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("x1", [1.0, 0.5])
+def test_thermal_decay_matches_thermal_diffusivity(x1):
+    """An isobaric temperature sine decays at alpha k^2 with alpha = lambda/(rho C_p)
+    = (1/omega_1 - 1/2) R T = nu / Pr, independent of the composition."""
+    nx = 64
+    x = np.arange(nx)
+    w = synth.config2(nx=nx, ny=1)
+    X = np.array([x1, 1.0 - x1])
+    w = replace(w, bc_lo=synth.BC_PERIODIC, bc_hi=synth.BC_PERIODIC, pore_radius=float("inf"),
+                X0=np.repeat(X[:, None], nx, axis=1), T0=1073.0 * (1 + 0.01 * np.sin(2 * np.pi * x / nx)),
+                P0=np.full(nx, synth.P_ATM))
+    o = lo.Oracle(w)
+    ts, amps = [], []
+    o.step(200)
+    for _ in range(6):
+        o.step(100)
+        ts.append(o.step_count)
+        amps.append(abs(np.fft.fft(o.moments()["T"])[1]))
+    rate = -np.polyfit(ts, np.log(amps), 1)[0]
+    k = 2 * math.pi / nx
+    alpha = w.nu_lat / w.prandtl
+    assert abs(rate / (alpha * k * k) - 1.0) < 0.03
