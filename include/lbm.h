@@ -1,0 +1,191 @@
+/*
+ * lbm.h -- C ABI of the MI355X (gfx950) mean-field lattice Boltzmann library for
+ * reacting multicomponent gas mixtures in porous media (Sawant & Karlin, "Mean
+ * field lattice Boltzmann model for reactive mixtures in porous media").
+ *
+ * One time step advances, on every node:
+ *   - M species populations with Stefan-Maxwell cross relaxation and Knudsen
+ *     (dusty-gas) relaxation: Section 2, eqs finalNumericalEquationsReactive,
+ *     betaa, tauab, taua, fStar, tauak, transform1;
+ *   - the mixture momentum populations with the porosity-dependent extended
+ *     equilibrium and the Knudsen force: Section 3.2, eqs f, feqmix, Pex, Peq,
+ *     netKnudsenForce, f_source;
+ *   - optionally the mixture energy populations: Section 3.3, eqs g, geq_i,
+ *     gstar, gstareq1mom, interdiffusion, corrFourier, qex;
+ *   - optionally the local heterogeneous surface-reaction source that couples
+ *     gas and adsorbed species: Section 4, eqs totalFluidReactionRate,
+ *     molarToMassRates, surfaceMoleFractions, totalSurfaceReactionRate,
+ *     rho_pc, fsourceHetero.
+ *
+ * Conventions
+ *   - Every entry point returns an lbm_status; nothing throws or aborts across
+ *     the ABI.  lbm_last_error() returns a text for the last failure on a ctx.
+ *   - Input arrays are host pointers and are copied; the caller keeps them.
+ *     Output buffers are owned by the caller (host or device, as flagged).
+ *   - The context owns every device allocation it makes (hipMalloc at init and
+ *     set-up calls only; lbm_step allocates nothing).
+ *   - A context is not thread-safe.  Work is queued on the HIP stream given in
+ *     the configuration (NULL = the null stream); lbm_moments synchronises it.
+ *   - Node index n = x + nx * (y + ny * z).  Field arrays are [component][node].
+ *   - Lattice units delta_x = delta_t = 1; physical inputs are SI.
+ *   - Population layout in HBM: [lattice][direction][node] FP64, lattices
+ *     0..M-1 species, M momentum, M+1 energy; direction
+ *     i = sum_a (c_ia + 1) 3^a.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_ctx lbm_ctx;
+
+typedef enum {
+  LBM_OK = 0,
+  LBM_EINVAL = -1,     /* invalid argument (sizes, ranges, positivity of the product form) */
+  LBM_ENOMEM = -2,     /* device allocation failed */
+  LBM_EHIP = -3,       /* a HIP runtime call failed */
+  LBM_ESTATE = -4,     /* call-order violation (e.g. set-up after the first step) */
+  LBM_EUNSTABLE = -5   /* health check found a non-finite value */
+} lbm_status;
+
+/* x-axis boundary kinds; y and z are periodic. */
+enum { LBM_BC_PERIODIC = 0, LBM_BC_BOUNCEBACK = 1, LBM_BC_INLET = 2, LBM_BC_OUTFLOW = 3 };
+
+/* lbm_moments field mask; rows are written in this order, each [rows][N] FP64. */
+enum {
+  LBM_MOM_RHO_SPECIES = 1 << 0, /* M rows: rho_a = sum_i f_ai / phi (eq density1)          */
+  LBM_MOM_VELOCITY    = 1 << 1, /* D rows: u = j / rho of the momentum lattice             */
+  LBM_MOM_TEMPERATURE = 1 << 2, /* 1 row : T in kelvin                                     */
+  LBM_MOM_PRESSURE    = 1 << 3, /* 1 row : P = rho R T in units of P_ref (eq eosIdealGas)  */
+  LBM_MOM_SPECIES_FLUX= 1 << 4, /* M*D rows [a][d]: second-order species momentum j_a     */
+  LBM_MOM_COVERAGE    = 1 << 5, /* K rows: surface coverages theta_s                      */
+  LBM_MOM_DENSITY     = 1 << 6, /* 1 row : rho = sum_i f_i / phi (eq fdensity)            */
+  LBM_MOM_MOLE_FRACTION=1 << 7  /* M rows: X_a                                             */
+};
+
+typedef struct {
+  int32_t dim;             /* 1, 2 or 3: D1Q3, D2Q9, D3Q27 (Section 2.2 product form)     */
+  int32_t nx, ny, nz;      /* grid; unused trailing extents must be 1                      */
+  int32_t n_species;       /* M, 2..5                                                      */
+  int32_t energy_on;       /* 1: energy lattice and temperature from eq temperature        */
+  int32_t bc_lo_x, bc_hi_x;/* LBM_BC_* at x = 0 and x = nx-1 (periodic must be both)       */
+  int32_t reserved;
+  double dx_m;             /* lattice spacing, m                                            */
+  double T_ref_K;          /* reference (maximum) temperature of the unit system, K         */
+  double P_ref_Pa;         /* pressure unit, Pa                                             */
+  double theta_ref;        /* lattice R T of the lightest species at T_ref (1/3 typical)   */
+  double nu_lat;           /* kinematic viscosity, lattice units (eq mu with mu = rho nu)  */
+  double prandtl;          /* Prandtl number (eq lambda)                                    */
+  const double *molar_mass;/* [M] kg/mol                                                     */
+  const double *D_ref_lat; /* [M*M] binary diffusivities, lattice units at (T_ref, P_ref);
+                              symmetric, diagonal ignored; D_ab scales as T^1.5 / P         */
+  const double *cv;        /* [M] J/(kg K), energy_on only (U_a = u_form_a + cv_a T)        */
+  const double *u_form;    /* [M] J/kg,     energy_on only                                  */
+  const double *inlet_lo_X;/* [M] inlet mole fractions at x = 0, or NULL                    */
+  const double *inlet_hi_X;/* [M] inlet mole fractions at x = nx-1, or NULL                 */
+  double inlet_P_Pa;       /* inlet pressure, Pa                                            */
+  double inlet_T_K;        /* inlet temperature, K                                          */
+  void *hip_stream;        /* hipStream_t of the caller, or NULL                            */
+} lbm_config;
+
+/* Surface mechanism on one reactive surface (Section 4): K surface species
+ * (index 0 of the surface block is the vacancy), R reversible mass-action
+ * reactions q_r = kf prod C^nu_f - kb prod C^nu_b [mol m^-2 s^-1] with C the gas
+ * concentration [mol m^-3] or Gamma theta [mol m^-2]; k = A exp(-Ea / (R_U T)).
+ * The local update is backward Euler over n_sub sub-steps, each with n_newton
+ * Newton iterations (dense LU with partial pivoting), followed by an
+ * extent-based conservative update of gas and coverages. */
+typedef struct {
+  int32_t n_surface;       /* K (2..10)                                                    */
+  int32_t n_reactions;     /* R (1..24)                                                    */
+  int32_t n_sub, n_newton; /* fixed iteration counts (>= 1)                                */
+  const int32_t *nu_f;     /* [R*(M+K)] reactant coefficients, 0..3                        */
+  const int32_t *nu_b;     /* [R*(M+K)] product coefficients, 0..3                         */
+  const double *A_f, *Ea_f;/* [R] SI (mol-based) pre-factor, J/mol                         */
+  const double *A_b, *Ea_b;
+  double gamma;            /* site density Gamma, mol/m^2 (eq surfaceMoleFractions)        */
+  double a_s;              /* specific surface area a^(s), 1/m (eq totalFluidReactionRate) */
+  const double *surf_mass; /* [K] kg/mol (mass bookkeeping only)                           */
+  const double *theta0;    /* [K] initial coverages, applied to every node                 */
+} lbm_mechanism;
+
+/* Creates a context for a rectangular grid.  X0 [M][N] mole fractions, P0 [N]
+ * pressure (Pa) or NULL for P_ref, T0 [N] temperature (K; the prescribed field
+ * when energy_on == 0).  Populations are set to the equilibria of Section 2.2
+ * and 3 at zero velocity with porosity 1 (lbm_set_porous_field rebuilds them).
+ * Fails with LBM_EINVAL when the product form would not be positive
+ * (R_a T > 1 for some species), when a mole fraction row does not sum to 1 or
+ * when sizes are inconsistent. */
+int lbm_init(const lbm_config *cfg, const double *X0, const double *P0, const double *T0,
+             lbm_ctx **out);
+
+/* Same as lbm_init for dim == 1 on n_cols independent packed columns of lengths
+ * col_len[c] (N = sum col_len).  Every column gets the x boundary kinds of cfg at
+ * its own ends (periodic is not allowed).  Used for batched 1-D button cells. */
+int lbm_init_columns(const lbm_config *cfg, int32_t n_cols, const int32_t *col_len,
+                     const double *X0, const double *P0, const double *T0, lbm_ctx **out);
+
+/* Porosity phi [N] in (0,1], tortuosity tort [N] (NULL = 1) and the pore radius
+ * r_p (m) of the Knudsen diffusivity D^k_a = (phi/tort)(2 r_p/3) sqrt(8 R_U T /(pi m_a))
+ * (Section 5.1); r_p <= 0 or infinite switches Knudsen diffusion off.  Rebuilds
+ * the initial populations; only valid before the first lbm_step (LBM_ESTATE). */
+int lbm_set_porous_field(lbm_ctx *ctx, const double *phi, const double *tort, double pore_radius_m);
+
+/* Installs the surface mechanism (NULL removes it) and sets the coverages to
+ * theta0.  Only valid before the first lbm_step. */
+int lbm_set_mechanism(lbm_ctx *ctx, const lbm_mechanism *mech);
+
+/* Prescribed volumetric Faradaic source rate [N] (mol m^-3 s^-1) that consumes
+ * species `fuel` and produces species `product` (explicit, added to the
+ * chemistry source; NULL removes it).  Only valid before the first lbm_step. */
+int lbm_set_faradaic_source(lbm_ctx *ctx, const double *rate, int32_t fuel, int32_t product);
+
+/* Advances n_steps time steps, asynchronously on the configured stream. */
+int lbm_step(lbm_ctx *ctx, int64_t n_steps);
+
+/* Writes the macroscopic fields selected by `mask` at the current time level,
+ * SoA FP64 in mask-bit order, into out (device pointer if out_on_device != 0,
+ * else host).  Synchronises the stream.  Returns LBM_EINVAL for an empty mask. */
+int lbm_moments(lbm_ctx *ctx, uint32_t mask, double *out, int32_t out_on_device);
+
+/* Number of rows lbm_moments writes for `mask` (so the caller can size out). */
+int lbm_moment_rows(const lbm_ctx *ctx, uint32_t mask, int32_t *rows);
+
+/* Conservation and health reduction (deterministic, fixed-order): per species
+ * total sum_x sum_i f_ai, momentum-lattice mass and momentum, energy total,
+ * minimum population and the count of non-finite populations. */
+typedef struct {
+  double species_mass[8];
+  double mixture_mass;
+  double mixture_momentum[3];
+  double energy_total;
+  double min_population;
+  int64_t n_nonfinite;
+  int64_t steps_done;
+} lbm_diag;
+int lbm_get_diagnostics(lbm_ctx *ctx, lbm_diag *out);
+
+/* Kernel time of the last lbm_step call's launches, measured with HIP events
+ * on the configured stream: total ms and the per-kernel averages (species,
+ * chemistry, mixture) in ms per launch.  Enabled with lbm_set_timing(ctx, 1). */
+int lbm_set_timing(lbm_ctx *ctx, int32_t enable);
+int lbm_get_timing(lbm_ctx *ctx, double *total_ms, double *species_ms, double *chem_ms,
+                   double *mixture_ms);
+
+/* Snapshot of the complete state (populations, pending source, records,
+ * coverages, step counter): call with buf == NULL to query *size. */
+int lbm_save(lbm_ctx *ctx, void *buf, size_t *size);
+int lbm_load(lbm_ctx *ctx, const void *buf, size_t size);
+
+const char *lbm_last_error(const lbm_ctx *ctx);
+void lbm_destroy(lbm_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBM_H */

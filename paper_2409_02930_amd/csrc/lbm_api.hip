@@ -1,0 +1,791 @@
+// Host side of the C ABI declared in include/lbm.h: validation, the lattice
+// unit system, device allocations, the per-step launch sequence, moments,
+// diagnostics, timing and snapshots.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <vector>
+
+#include "lbm.h"
+#include "lbm_internal.h"
+
+namespace {
+
+constexpr double kRU = 8.314462618;      // J/(mol K)
+constexpr int kTimingRing = 64;          // steps of per-kernel events kept
+
+struct Buf {
+  double *p = nullptr;
+  size_t n = 0;
+};
+
+}  // namespace
+
+struct lbm_ctx {
+  // configuration
+  int dim, nx, ny, nz, N, M, L, Q, energy, bc_lo, bc_hi;
+  int n_cols;
+  hipStream_t stream;
+  double dx, T_ref, P_ref, theta_ref, nu, prandtl;
+  double m[LBM_MMAX], m_min;
+  double Dref[LBM_MMAX * LBM_MMAX];
+  double cv_lat[LBM_MMAX], uf_lat[LBM_MMAX];
+  double c2, dt, rho_unit;
+  InletState inlet[2];
+  bool have_inlet[2];
+  // device buffers
+  double *pop[2] = {nullptr, nullptr};
+  double *phi = nullptr, *kfac = nullptr, *Tfield = nullptr;
+  double *X0 = nullptr, *Plat = nullptr;
+  int8_t *colflag = nullptr;
+  double *rA = nullptr, *rRT = nullptr, *rFk = nullptr, *rrho = nullptr, *rY = nullptr, *rqd = nullptr;
+  double *v[2] = {nullptr, nullptr};
+  double *T[2] = {nullptr, nullptr};
+  double *src[2] = {nullptr, nullptr};
+  double *srcsum = nullptr;
+  double *theta = nullptr;
+  double *faradaic = nullptr;
+  double *macro = nullptr;
+  double *partials = nullptr;
+  int diag_blocks = 0;
+  // state
+  int cur = 0;
+  int first_step = 1;
+  int has_src = 0;
+  long long steps_done = 0;
+  int knudsen = 0;
+  double pore_radius = 0.0;
+  int has_mech = 0, has_faradaic = 0;
+  ChemParams chem;
+  int K = 0;
+  // timing
+  int timing = 0;
+  hipEvent_t ev[kTimingRing][4];
+  int ev_count = 0;
+  int ev_ready = 0;
+  double t_total_ms = 0.0;
+  hipEvent_t ev_all[2];
+  char err[512];
+};
+
+namespace {
+
+int fail(lbm_ctx *c, int code, const char *fmt, ...) {
+  if (c) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(c->err, sizeof(c->err), fmt, ap);
+    va_end(ap);
+  }
+  return code;
+}
+
+#define HIPCHK(ctx, expr)                                                                  \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      return fail(ctx, LBM_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_));           \
+  } while (0)
+
+int dalloc(lbm_ctx *c, double **p, size_t n) {
+  if (n == 0) n = 1;
+  hipError_t e = hipMalloc((void **)p, n * sizeof(double));
+  if (e != hipSuccess) {
+    *p = nullptr;
+    return fail(c, LBM_ENOMEM, "hipMalloc of %zu doubles failed: %s", n, hipGetErrorString(e));
+  }
+  return LBM_OK;
+}
+
+void dfree(void *p) {
+  if (p) (void)hipFree(p);
+}
+
+// Equilibrium state of an inlet mixture (X, P, T) in lattice units.
+InletState make_inlet(const lbm_ctx *c, const double *X, double P_Pa, double T_K) {
+  InletState s;
+  memset(&s, 0, sizeof(s));
+  const double Pl = P_Pa / c->P_ref;
+  double rho = 0.0;
+  for (int a = 0; a < c->M; ++a) {
+    s.RaT[a] = c->theta_ref * (c->m_min / c->m[a]) * (T_K / c->T_ref);
+    s.rho_a[a] = X[a] * Pl / s.RaT[a];
+    rho += s.rho_a[a];
+  }
+  s.rho = rho;
+  double RT = 0.0, U = 0.0;
+  for (int a = 0; a < c->M; ++a) {
+    const double Y = s.rho_a[a] / rho;
+    RT += Y * s.RaT[a];
+    U += Y * (c->uf_lat[a] + c->cv_lat[a] * T_K);
+  }
+  s.RT = RT;
+  s.U = U;
+  return s;
+}
+
+KParams base_params(const lbm_ctx *c) {
+  KParams p;
+  memset(&p, 0, sizeof(p));
+  p.N = c->N;
+  p.nx = c->nx;
+  p.ny = c->ny;
+  p.nz = c->nz;
+  p.M = c->M;
+  p.energy = c->energy;
+  p.bc_lo = c->bc_lo;
+  p.bc_hi = c->bc_hi;
+  p.knudsen = c->knudsen;
+  p.colflag = c->colflag;
+  p.theta_ref = c->theta_ref;
+  p.inv_T_ref = 1.0 / c->T_ref;
+  p.nu = c->nu;
+  p.prandtl = c->prandtl;
+  for (int a = 0; a < c->M; ++a) {
+    p.mmin_over_m[a] = c->m_min / c->m[a];
+    p.inv_m[a] = 1.0 / c->m[a];
+    p.cv[a] = c->cv_lat[a];
+    p.uf[a] = c->uf_lat[a];
+  }
+  memcpy(p.Dref, c->Dref, sizeof(p.Dref));
+  p.inlet[0] = c->inlet[0];
+  p.inlet[1] = c->inlet[1];
+  p.phi = c->phi;
+  p.kfac = c->kfac;
+  p.Tfield = c->Tfield;
+  p.rA = c->rA;
+  p.rRT = c->rRT;
+  p.rFk = c->rFk;
+  p.rrho = c->rrho;
+  p.rY = c->rY;
+  p.rqd = c->rqd;
+  return p;
+}
+
+bool needs_v(const lbm_ctx *c) {
+  return c->has_mech || c->has_faradaic || c->bc_lo == BC_INLET || c->bc_hi == BC_INLET;
+}
+
+// Parameters for reading the state at the current time level (the pull of the
+// next step): records of the last completed step.
+void fill_prev(const lbm_ctx *c, KParams &p) {
+  const int q_last = (int)((c->steps_done + 1) & 1);   // parity of the last completed step
+  p.pin = c->pop[c->cur];
+  p.first_step = c->first_step;
+  p.has_src = c->has_src;
+  p.v_prev = c->v[q_last];
+  p.src_prev = c->src[q_last];
+  p.T_prev = c->energy ? c->T[q_last] : c->Tfield;
+}
+
+int rebuild_populations(lbm_ctx *c) {
+  InitParams ip;
+  memset(&ip, 0, sizeof(ip));
+  ip.N = c->N;
+  ip.M = c->M;
+  ip.energy = c->energy;
+  ip.theta_ref = c->theta_ref;
+  ip.inv_T_ref = 1.0 / c->T_ref;
+  for (int a = 0; a < c->M; ++a) {
+    ip.mmin_over_m[a] = c->m_min / c->m[a];
+    ip.inv_m[a] = 1.0 / c->m[a];
+    ip.cv[a] = c->cv_lat[a];
+    ip.uf[a] = c->uf_lat[a];
+  }
+  ip.X0 = c->X0;
+  ip.Plat = c->Plat;
+  ip.T0 = c->Tfield;
+  ip.phi = c->phi;
+  ip.pop = c->pop[0];
+  HIPCHK(c, launch_init(c->dim, ip, c->stream));
+  c->cur = 0;
+  c->first_step = 1;
+  c->has_src = 0;
+  c->steps_done = 0;
+  return LBM_OK;
+}
+
+int check_config(const lbm_config *cfg, lbm_ctx *c) {
+  if (!cfg) return LBM_EINVAL;
+  if (cfg->dim < 1 || cfg->dim > 3) return fail(c, LBM_EINVAL, "dim must be 1, 2 or 3");
+  if (cfg->n_species < 2 || cfg->n_species > LBM_MMAX)
+    return fail(c, LBM_EINVAL, "n_species must be in [2, %d]", LBM_MMAX);
+  if (cfg->nx < 1 || cfg->ny < 1 || cfg->nz < 1) return fail(c, LBM_EINVAL, "grid extents must be >= 1");
+  if ((cfg->dim < 2 && cfg->ny != 1) || (cfg->dim < 3 && cfg->nz != 1))
+    return fail(c, LBM_EINVAL, "unused grid extents must be 1");
+  if ((cfg->bc_lo_x == LBM_BC_PERIODIC) != (cfg->bc_hi_x == LBM_BC_PERIODIC))
+    return fail(c, LBM_EINVAL, "periodic x must be set on both ends");
+  for (int s = 0; s < 2; ++s) {
+    const int k = s ? cfg->bc_hi_x : cfg->bc_lo_x;
+    if (k < 0 || k > 3) return fail(c, LBM_EINVAL, "unknown boundary kind %d", k);
+    if (k == LBM_BC_INLET && !(s ? cfg->inlet_hi_X : cfg->inlet_lo_X))
+      return fail(c, LBM_EINVAL, "inlet boundary needs its mole fractions");
+  }
+  if (!cfg->molar_mass || !cfg->D_ref_lat) return fail(c, LBM_EINVAL, "molar_mass and D_ref_lat are required");
+  if (cfg->energy_on && (!cfg->cv || !cfg->u_form)) return fail(c, LBM_EINVAL, "energy lattice needs cv and u_form");
+  if (!(cfg->dx_m > 0) || !(cfg->T_ref_K > 0) || !(cfg->P_ref_Pa > 0) || !(cfg->theta_ref > 0) ||
+      !(cfg->theta_ref <= 1.0) || !(cfg->nu_lat > 0) || !(cfg->prandtl > 0))
+    return fail(c, LBM_EINVAL, "dx, T_ref, P_ref, theta_ref in (0,1], nu and Pr must be positive");
+  const int M = cfg->n_species;
+  for (int a = 0; a < M; ++a)
+    if (!(cfg->molar_mass[a] > 0)) return fail(c, LBM_EINVAL, "molar masses must be positive");
+  for (int a = 0; a < M; ++a)
+    for (int b = 0; b < M; ++b)
+      if (a != b) {
+        const double d = cfg->D_ref_lat[a * M + b];
+        if (!(d > 0) || fabs(d - cfg->D_ref_lat[b * M + a]) > 1e-12 * d)
+          return fail(c, LBM_EINVAL, "D_ref_lat must be positive and symmetric");
+      }
+  return LBM_OK;
+}
+
+int common_init(const lbm_config *cfg, int N, const double *X0, const double *P0, const double *T0,
+                lbm_ctx *c) {
+  c->dim = cfg->dim;
+  c->N = N;
+  c->M = cfg->n_species;
+  c->energy = cfg->energy_on ? 1 : 0;
+  c->L = c->M + 1 + c->energy;
+  c->Q = cfg->dim == 1 ? 3 : (cfg->dim == 2 ? 9 : 27);
+  c->bc_lo = cfg->bc_lo_x;
+  c->bc_hi = cfg->bc_hi_x;
+  c->stream = (hipStream_t)cfg->hip_stream;
+  c->dx = cfg->dx_m;
+  c->T_ref = cfg->T_ref_K;
+  c->P_ref = cfg->P_ref_Pa;
+  c->theta_ref = cfg->theta_ref;
+  c->nu = cfg->nu_lat;
+  c->prandtl = cfg->prandtl;
+  c->m_min = 1e300;
+  memset(c->Dref, 0, sizeof(c->Dref));
+  for (int a = 0; a < c->M; ++a) {
+    c->m[a] = cfg->molar_mass[a];
+    c->m_min = fmin(c->m_min, c->m[a]);
+    for (int b = 0; b < c->M; ++b) c->Dref[a * LBM_MMAX + b] = (a == b) ? 1.0 : cfg->D_ref_lat[a * c->M + b];
+  }
+  // lattice unit system: R T of the lightest species at T_ref equals theta_ref
+  c->c2 = kRU * c->T_ref / (c->m_min * c->theta_ref);
+  c->dt = c->dx / sqrt(c->c2);
+  c->rho_unit = c->P_ref / c->c2;
+  for (int a = 0; a < c->M; ++a) {
+    c->cv_lat[a] = c->energy ? cfg->cv[a] / c->c2 : 0.0;
+    c->uf_lat[a] = c->energy ? cfg->u_form[a] / c->c2 : 0.0;
+  }
+  // host-side validation of the fields
+  if (!X0 || !T0) return fail(c, LBM_EINVAL, "X0 and T0 are required");
+  double Tmax = 0.0;
+  for (int n = 0; n < N; ++n) {
+    double sx = 0.0;
+    for (int a = 0; a < c->M; ++a) {
+      const double x = X0[(size_t)a * N + n];
+      if (!(x >= 0.0)) return fail(c, LBM_EINVAL, "negative mole fraction at node %d", n);
+      sx += x;
+    }
+    if (fabs(sx - 1.0) > 1e-9) return fail(c, LBM_EINVAL, "mole fractions at node %d sum to %.17g", n, sx);
+    if (!(T0[n] > 0)) return fail(c, LBM_EINVAL, "temperature must be positive");
+    if (P0 && !(P0[n] > 0)) return fail(c, LBM_EINVAL, "pressure must be positive");
+    Tmax = fmax(Tmax, T0[n]);
+  }
+  // positivity of the product form at rest: the lightest species R T <= 1
+  if (c->theta_ref * Tmax / c->T_ref > 1.0) return fail(c, LBM_EINVAL, "R_a T exceeds 1 (product form not positive)");
+  for (int s = 0; s < 2; ++s) {
+    const double *X = s ? cfg->inlet_hi_X : cfg->inlet_lo_X;
+    c->have_inlet[s] = X != nullptr;
+    if (X) {
+      double sx = 0.0;
+      for (int a = 0; a < c->M; ++a) sx += X[a];
+      if (fabs(sx - 1.0) > 1e-9 || !(cfg->inlet_P_Pa > 0) || !(cfg->inlet_T_K > 0))
+        return fail(c, LBM_EINVAL, "inlet state invalid");
+      if (c->theta_ref * cfg->inlet_T_K / c->T_ref > 1.0) return fail(c, LBM_EINVAL, "inlet R_a T exceeds 1");
+      c->inlet[s] = make_inlet(c, X, cfg->inlet_P_Pa, cfg->inlet_T_K);
+    } else {
+      memset(&c->inlet[s], 0, sizeof(InletState));
+    }
+  }
+  // device allocations
+  const size_t popn = (size_t)c->L * c->Q * N;
+  int rc;
+  if ((rc = dalloc(c, &c->pop[0], popn)) || (rc = dalloc(c, &c->pop[1], popn))) return rc;
+  if ((rc = dalloc(c, &c->phi, N)) || (rc = dalloc(c, &c->kfac, N)) || (rc = dalloc(c, &c->Tfield, N)) ||
+      (rc = dalloc(c, &c->X0, (size_t)c->M * N)) || (rc = dalloc(c, &c->Plat, N)))
+    return rc;
+  const int D = c->dim;
+  if ((rc = dalloc(c, &c->rA, (size_t)D * N)) || (rc = dalloc(c, &c->rRT, N)) ||
+      (rc = dalloc(c, &c->rFk, (size_t)D * N)) || (rc = dalloc(c, &c->rrho, (size_t)c->M * N)) ||
+      (rc = dalloc(c, &c->v[0], (size_t)D * N)) || (rc = dalloc(c, &c->v[1], (size_t)D * N)) ||
+      (rc = dalloc(c, &c->src[0], (size_t)c->M * N)) || (rc = dalloc(c, &c->src[1], (size_t)c->M * N)) ||
+      (rc = dalloc(c, &c->srcsum, N)))
+    return rc;
+  if (c->energy) {
+    if ((rc = dalloc(c, &c->rY, (size_t)c->M * N)) || (rc = dalloc(c, &c->rqd, (size_t)D * N)) ||
+        (rc = dalloc(c, &c->T[0], N)) || (rc = dalloc(c, &c->T[1], N)))
+      return rc;
+  }
+  const size_t mrows = (size_t)(c->M + D + 2 + c->M * D + 1 + c->M);
+  if ((rc = dalloc(c, &c->macro, mrows * N))) return rc;
+  c->diag_blocks = (N + 255) / 256;
+  if ((rc = dalloc(c, &c->partials, (size_t)c->diag_blocks * (c->L + D + 2)))) return rc;
+  // upload fields
+  std::vector<double> Plat(N), ones(N, 1.0), zeros((size_t)D * N, 0.0);
+  for (int n = 0; n < N; ++n) Plat[n] = (P0 ? P0[n] : c->P_ref) / c->P_ref;
+  HIPCHK(c, hipMemcpy(c->X0, X0, sizeof(double) * c->M * N, hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(c->Plat, Plat.data(), sizeof(double) * N, hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(c->Tfield, T0, sizeof(double) * N, hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(c->phi, ones.data(), sizeof(double) * N, hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(c->kfac, zeros.data(), sizeof(double) * N, hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(c->v[0], zeros.data(), sizeof(double) * D * N, hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(c->v[1], zeros.data(), sizeof(double) * D * N, hipMemcpyHostToDevice));
+  if (c->energy) {
+    HIPCHK(c, hipMemcpy(c->T[0], T0, sizeof(double) * N, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->T[1], T0, sizeof(double) * N, hipMemcpyHostToDevice));
+  }
+  c->knudsen = 0;
+  memset(&c->chem, 0, sizeof(c->chem));
+  rc = rebuild_populations(c);
+  if (rc) return rc;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return LBM_OK;
+}
+
+int enqueue_step(lbm_ctx *c, int record_slot) {
+  const int q = (int)(c->steps_done & 1);
+  KParams p = base_params(c);
+  p.pin = c->pop[c->cur];
+  p.pout = c->pop[1 - c->cur];
+  p.first_step = c->first_step;
+  p.has_src = c->has_src;
+  const int chem = c->has_mech || c->has_faradaic;
+  p.chem = chem;
+  p.need_v = needs_v(c) ? 1 : 0;
+  p.v_prev = c->v[1 - q];
+  p.v_cur = c->v[q];
+  p.src_prev = c->src[1 - q];
+  p.T_prev = c->energy ? c->T[1 - q] : c->Tfield;
+  p.T_cur = c->energy ? c->T[q] : nullptr;
+  p.srcsum_cur = c->srcsum;
+  hipEvent_t *ev = record_slot >= 0 ? c->ev[record_slot] : nullptr;
+  if (ev) HIPCHK(c, hipEventRecord(ev[0], c->stream));
+  HIPCHK(c, launch_species(c->dim, p, c->stream));
+  if (ev) HIPCHK(c, hipEventRecord(ev[1], c->stream));
+  if (chem) {
+    ChemParams cp = c->chem;
+    cp.N = c->N;
+    cp.M = c->M;
+    cp.K = c->has_mech ? c->K : 0;
+    cp.rrho = c->rrho;
+    cp.T = c->energy ? c->T[q] : c->Tfield;
+    cp.phi = c->phi;
+    cp.faradaic = c->has_faradaic ? c->faradaic : nullptr;
+    cp.theta = c->theta;
+    cp.src = c->src[q];
+    cp.srcsum = c->srcsum;
+    cp.dt = c->dt;
+    cp.rho_unit = c->rho_unit;
+    cp.R_U = kRU;
+    for (int a = 0; a < c->M; ++a) cp.m[a] = c->m[a];
+    HIPCHK(c, launch_chem(cp, c->stream));
+  }
+  if (ev) HIPCHK(c, hipEventRecord(ev[2], c->stream));
+  HIPCHK(c, launch_mixture(c->dim, p, c->stream));
+  if (ev) HIPCHK(c, hipEventRecord(ev[3], c->stream));
+  c->cur = 1 - c->cur;
+  c->first_step = 0;
+  c->has_src = chem;
+  c->steps_done += 1;
+  return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm_init(const lbm_config *cfg, const double *X0, const double *P0, const double *T0, lbm_ctx **out) {
+  if (!out) return LBM_EINVAL;
+  *out = nullptr;
+  lbm_ctx *c = new (std::nothrow) lbm_ctx();
+  if (!c) return LBM_ENOMEM;
+  c->err[0] = 0;
+  int rc = check_config(cfg, c);
+  if (rc) {
+    *out = c;   // caller can read the message, then destroy
+    return rc;
+  }
+  c->nx = cfg->nx;
+  c->ny = cfg->ny;
+  c->nz = cfg->nz;
+  c->n_cols = 0;
+  rc = common_init(cfg, cfg->nx * cfg->ny * cfg->nz, X0, P0, T0, c);
+  *out = c;
+  return rc;
+}
+
+int lbm_init_columns(const lbm_config *cfg, int32_t n_cols, const int32_t *col_len, const double *X0,
+                     const double *P0, const double *T0, lbm_ctx **out) {
+  if (!out) return LBM_EINVAL;
+  *out = nullptr;
+  lbm_ctx *c = new (std::nothrow) lbm_ctx();
+  if (!c) return LBM_ENOMEM;
+  c->err[0] = 0;
+  *out = c;
+  int rc = check_config(cfg, c);
+  if (rc) return rc;
+  if (cfg->dim != 1) return fail(c, LBM_EINVAL, "packed columns need dim == 1");
+  if (cfg->bc_lo_x == LBM_BC_PERIODIC) return fail(c, LBM_EINVAL, "packed columns cannot be periodic");
+  if (n_cols < 1 || !col_len) return fail(c, LBM_EINVAL, "need at least one column");
+  long long N = 0;
+  for (int k = 0; k < n_cols; ++k) {
+    if (col_len[k] < 2) return fail(c, LBM_EINVAL, "columns need at least 2 nodes");
+    N += col_len[k];
+  }
+  if (N > (1LL << 30)) return fail(c, LBM_EINVAL, "too many nodes");
+  c->nx = (int)N;
+  c->ny = c->nz = 1;
+  c->n_cols = n_cols;
+  rc = common_init(cfg, (int)N, X0, P0, T0, c);
+  if (rc) return rc;
+  std::vector<int8_t> flag(N, 0);
+  long long o = 0;
+  for (int k = 0; k < n_cols; ++k) {
+    flag[o] |= 1;
+    flag[o + col_len[k] - 1] |= 2;
+    o += col_len[k];
+  }
+  hipError_t e = hipMalloc((void **)&c->colflag, N);
+  if (e != hipSuccess) return fail(c, LBM_ENOMEM, "hipMalloc colflag");
+  HIPCHK(c, hipMemcpy(c->colflag, flag.data(), N, hipMemcpyHostToDevice));
+  return LBM_OK;
+}
+
+int lbm_set_porous_field(lbm_ctx *c, const double *phi, const double *tort, double pore_radius_m) {
+  if (!c) return LBM_EINVAL;
+  if (c->steps_done) return fail(c, LBM_ESTATE, "lbm_set_porous_field after the first step");
+  if (!phi) return fail(c, LBM_EINVAL, "phi is required");
+  const int N = c->N;
+  const bool kn = pore_radius_m > 0.0 && isfinite(pore_radius_m);
+  std::vector<double> kf(N, 0.0);
+  const double pref = kn ? (2.0 * pore_radius_m / (3.0 * c->dx)) * sqrt(8.0 / M_PI) : 0.0;
+  for (int n = 0; n < N; ++n) {
+    if (!(phi[n] > 0.0 && phi[n] <= 1.0)) return fail(c, LBM_EINVAL, "porosity at node %d not in (0,1]", n);
+    const double t = tort ? tort[n] : 1.0;
+    if (!(t > 0.0)) return fail(c, LBM_EINVAL, "tortuosity must be positive");
+    kf[n] = kn ? (phi[n] / t) * pref : 0.0;
+  }
+  HIPCHK(c, hipMemcpy(c->phi, phi, sizeof(double) * N, hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(c->kfac, kf.data(), sizeof(double) * N, hipMemcpyHostToDevice));
+  c->knudsen = kn ? 1 : 0;
+  c->pore_radius = pore_radius_m;
+  int rc = rebuild_populations(c);
+  if (rc) return rc;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return LBM_OK;
+}
+
+int lbm_set_mechanism(lbm_ctx *c, const lbm_mechanism *mech) {
+  if (!c) return LBM_EINVAL;
+  if (c->steps_done) return fail(c, LBM_ESTATE, "lbm_set_mechanism after the first step");
+  if (!mech) {
+    c->has_mech = 0;
+    c->K = 0;
+    return LBM_OK;
+  }
+  const int M = c->M, K = mech->n_surface, R = mech->n_reactions, S = M + K;
+  if (K < 2 || K > LBM_KMAX || R < 1 || R > LBM_RMAX) return fail(c, LBM_EINVAL, "mechanism sizes out of range");
+  if (!chem_supported(M, K)) return fail(c, LBM_EINVAL, "no chemistry kernel for (M, K) = (%d, %d)", M, K);
+  if (mech->n_sub < 1 || mech->n_newton < 1) return fail(c, LBM_EINVAL, "n_sub and n_newton must be >= 1");
+  if (!mech->nu_f || !mech->nu_b || !mech->A_f || !mech->Ea_f || !mech->A_b || !mech->Ea_b || !mech->theta0)
+    return fail(c, LBM_EINVAL, "mechanism arrays missing");
+  if (!(mech->gamma > 0) || !(mech->a_s > 0)) return fail(c, LBM_EINVAL, "gamma and a_s must be positive");
+  const int fuel = c->chem.fuel, product = c->chem.product;
+  ChemParams &cp = c->chem;
+  memset(&cp, 0, sizeof(cp));
+  cp.R = R;
+  cp.n_sub = mech->n_sub;
+  cp.n_newton = mech->n_newton;
+  for (int r = 0; r < R; ++r) {
+    for (int s = 0; s < S; ++s) {
+      const int ef = mech->nu_f[r * S + s], eb = mech->nu_b[r * S + s];
+      if (ef < 0 || ef > 3 || eb < 0 || eb > 3) return fail(c, LBM_EINVAL, "stoichiometric coefficients must be 0..3");
+      cp.nu_f[r][s] = (int8_t)ef;
+      cp.nu_b[r][s] = (int8_t)eb;
+    }
+    cp.A_f[r] = mech->A_f[r];
+    cp.Ea_f[r] = mech->Ea_f[r];
+    cp.A_b[r] = mech->A_b[r];
+    cp.Ea_b[r] = mech->Ea_b[r];
+  }
+  cp.gamma = mech->gamma;
+  cp.a_s = mech->a_s;
+  cp.fuel = fuel;
+  cp.product = product;
+  double st = 0.0;
+  for (int s = 0; s < K; ++s) st += mech->theta0[s];
+  if (fabs(st - 1.0) > 1e-9) return fail(c, LBM_EINVAL, "theta0 must sum to 1");
+  dfree(c->theta);
+  c->theta = nullptr;
+  int rc = dalloc(c, &c->theta, (size_t)K * c->N);
+  if (rc) return rc;
+  std::vector<double> th((size_t)K * c->N);
+  for (int s = 0; s < K; ++s)
+    for (int n = 0; n < c->N; ++n) th[(size_t)s * c->N + n] = mech->theta0[s];
+  HIPCHK(c, hipMemcpy(c->theta, th.data(), sizeof(double) * th.size(), hipMemcpyHostToDevice));
+  c->K = K;
+  c->has_mech = 1;
+  return LBM_OK;
+}
+
+int lbm_set_faradaic_source(lbm_ctx *c, const double *rate, int32_t fuel, int32_t product) {
+  if (!c) return LBM_EINVAL;
+  if (c->steps_done) return fail(c, LBM_ESTATE, "lbm_set_faradaic_source after the first step");
+  if (!rate) {
+    c->has_faradaic = 0;
+    return LBM_OK;
+  }
+  if (fuel < 0 || fuel >= c->M || product < 0 || product >= c->M || fuel == product)
+    return fail(c, LBM_EINVAL, "fuel/product species out of range");
+  if (!c->faradaic) {
+    int rc = dalloc(c, &c->faradaic, c->N);
+    if (rc) return rc;
+  }
+  HIPCHK(c, hipMemcpy(c->faradaic, rate, sizeof(double) * c->N, hipMemcpyHostToDevice));
+  c->chem.fuel = fuel;
+  c->chem.product = product;
+  c->has_faradaic = 1;
+  return LBM_OK;
+}
+
+int lbm_step(lbm_ctx *c, int64_t n_steps) {
+  if (!c) return LBM_EINVAL;
+  if (n_steps < 0) return fail(c, LBM_EINVAL, "negative step count");
+  if (c->timing) {
+    HIPCHK(c, hipEventRecord(c->ev_all[0], c->stream));
+  }
+  const int64_t first_timed = n_steps > kTimingRing ? n_steps - kTimingRing : 0;
+  int slot = 0;
+  for (int64_t s = 0; s < n_steps; ++s) {
+    const int rec = (c->timing && s >= first_timed) ? slot++ : -1;
+    int rc = enqueue_step(c, rec);
+    if (rc) return rc;
+  }
+  if (c->timing) {
+    HIPCHK(c, hipEventRecord(c->ev_all[1], c->stream));
+    c->ev_count = slot;
+    c->ev_ready = 1;
+  }
+  return LBM_OK;
+}
+
+int lbm_moment_rows(const lbm_ctx *c, uint32_t mask, int32_t *rows) {
+  if (!c || !rows) return LBM_EINVAL;
+  const int M = c->M, D = c->dim;
+  int r = 0;
+  if (mask & LBM_MOM_RHO_SPECIES) r += M;
+  if (mask & LBM_MOM_VELOCITY) r += D;
+  if (mask & LBM_MOM_TEMPERATURE) r += 1;
+  if (mask & LBM_MOM_PRESSURE) r += 1;
+  if (mask & LBM_MOM_SPECIES_FLUX) r += M * D;
+  if (mask & LBM_MOM_COVERAGE) r += c->has_mech ? c->K : 0;
+  if (mask & LBM_MOM_DENSITY) r += 1;
+  if (mask & LBM_MOM_MOLE_FRACTION) r += M;
+  *rows = r;
+  return LBM_OK;
+}
+
+int lbm_moments(lbm_ctx *c, uint32_t mask, double *out, int32_t out_on_device) {
+  if (!c) return LBM_EINVAL;
+  if (!mask || !out) return fail(c, LBM_EINVAL, "empty mask or NULL output");
+  KParams p = base_params(c);
+  fill_prev(c, p);
+  HIPCHK(c, launch_moments(c->dim, p, c->macro, c->stream));
+  const int M = c->M, D = c->dim, N = c->N;
+  const hipMemcpyKind kind = out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  size_t o = 0;
+  auto copy_rows = [&](size_t row0, size_t nrows, const double *base) -> int {
+    HIPCHK(c, hipMemcpyAsync(out + o * N, base + row0 * N, sizeof(double) * nrows * N, kind, c->stream));
+    o += nrows;
+    return LBM_OK;
+  };
+  const size_t r_rho = 0, r_u = M, r_T = M + D, r_P = M + D + 1, r_j = M + D + 2, r_rhom = M + D + 2 + M * D,
+               r_X = r_rhom + 1;
+  int rc = LBM_OK;
+  if (mask & LBM_MOM_RHO_SPECIES) rc |= copy_rows(r_rho, M, c->macro);
+  if (mask & LBM_MOM_VELOCITY) rc |= copy_rows(r_u, D, c->macro);
+  if (mask & LBM_MOM_TEMPERATURE) rc |= copy_rows(r_T, 1, c->macro);
+  if (mask & LBM_MOM_PRESSURE) rc |= copy_rows(r_P, 1, c->macro);
+  if (mask & LBM_MOM_SPECIES_FLUX) rc |= copy_rows(r_j, (size_t)M * D, c->macro);
+  if ((mask & LBM_MOM_COVERAGE) && c->has_mech) rc |= copy_rows(0, c->K, c->theta);
+  if (mask & LBM_MOM_DENSITY) rc |= copy_rows(r_rhom, 1, c->macro);
+  if (mask & LBM_MOM_MOLE_FRACTION) rc |= copy_rows(r_X, M, c->macro);
+  if (rc) return rc;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return LBM_OK;
+}
+
+int lbm_get_diagnostics(lbm_ctx *c, lbm_diag *out) {
+  if (!c || !out) return LBM_EINVAL;
+  memset(out, 0, sizeof(*out));
+  const int W = c->L + c->dim + 2;
+  HIPCHK(c, launch_diag(c->L, c->dim, c->M, c->N, c->pop[c->cur], c->partials, c->diag_blocks, c->stream));
+  std::vector<double> h((size_t)c->diag_blocks * W);
+  HIPCHK(c, hipMemcpyAsync(h.data(), c->partials, sizeof(double) * h.size(), hipMemcpyDeviceToHost, c->stream));
+  std::vector<double> srch;
+  if (c->has_src) {
+    const int q_last = (int)((c->steps_done + 1) & 1);
+    srch.resize((size_t)c->M * c->N);
+    HIPCHK(c, hipMemcpyAsync(srch.data(), c->src[q_last], sizeof(double) * srch.size(), hipMemcpyDeviceToHost,
+                             c->stream));
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  double mn = INFINITY, bad = 0.0;
+  for (int b = 0; b < c->diag_blocks; ++b) {
+    const double *r = &h[(size_t)b * W];
+    for (int a = 0; a < c->M && a < 8; ++a) out->species_mass[a] += r[a];
+    out->mixture_mass += r[c->M];
+    if (c->energy) out->energy_total += r[c->M + 1];
+    for (int d = 0; d < c->dim; ++d) out->mixture_momentum[d] += r[c->L + d];
+    mn = fmin(mn, r[c->L + c->dim]);
+    bad += r[c->L + c->dim + 1];
+  }
+  if (c->has_src)
+    for (int a = 0; a < c->M && a < 8; ++a)
+      for (int n = 0; n < c->N; ++n) out->species_mass[a] += srch[(size_t)a * c->N + n];
+  out->min_population = mn;
+  out->n_nonfinite = (int64_t)bad;
+  out->steps_done = c->steps_done;
+  if (bad > 0) return fail(c, LBM_EUNSTABLE, "%lld non-finite populations", (long long)bad);
+  return LBM_OK;
+}
+
+int lbm_set_timing(lbm_ctx *c, int32_t enable) {
+  if (!c) return LBM_EINVAL;
+  if (enable && !c->timing) {
+    for (int s = 0; s < kTimingRing; ++s)
+      for (int k = 0; k < 4; ++k) HIPCHK(c, hipEventCreate(&c->ev[s][k]));
+    HIPCHK(c, hipEventCreate(&c->ev_all[0]));
+    HIPCHK(c, hipEventCreate(&c->ev_all[1]));
+    c->timing = 1;
+  } else if (!enable && c->timing) {
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (int s = 0; s < kTimingRing; ++s)
+      for (int k = 0; k < 4; ++k) (void)hipEventDestroy(c->ev[s][k]);
+    (void)hipEventDestroy(c->ev_all[0]);
+    (void)hipEventDestroy(c->ev_all[1]);
+    c->timing = 0;
+  }
+  c->ev_ready = 0;
+  return LBM_OK;
+}
+
+int lbm_get_timing(lbm_ctx *c, double *total_ms, double *species_ms, double *chem_ms, double *mixture_ms) {
+  if (!c) return LBM_EINVAL;
+  if (!c->timing || !c->ev_ready || c->ev_count == 0) return fail(c, LBM_ESTATE, "no timed step recorded");
+  HIPCHK(c, hipEventSynchronize(c->ev_all[1]));
+  float t = 0.f;
+  HIPCHK(c, hipEventElapsedTime(&t, c->ev_all[0], c->ev_all[1]));
+  double s1 = 0, s2 = 0, s3 = 0;
+  for (int s = 0; s < c->ev_count; ++s) {
+    float a = 0, b = 0, d = 0;
+    HIPCHK(c, hipEventElapsedTime(&a, c->ev[s][0], c->ev[s][1]));
+    HIPCHK(c, hipEventElapsedTime(&b, c->ev[s][1], c->ev[s][2]));
+    HIPCHK(c, hipEventElapsedTime(&d, c->ev[s][2], c->ev[s][3]));
+    s1 += a;
+    s2 += b;
+    s3 += d;
+  }
+  if (total_ms) *total_ms = t;
+  if (species_ms) *species_ms = s1 / c->ev_count;
+  if (chem_ms) *chem_ms = s2 / c->ev_count;
+  if (mixture_ms) *mixture_ms = s3 / c->ev_count;
+  return LBM_OK;
+}
+
+namespace {
+struct SnapHeader {
+  uint64_t magic, N, L, Q, M, K, D;
+  int64_t steps_done;
+  int32_t first_step, has_src, pad0, pad1;
+};
+constexpr uint64_t kMagic = 0x314d424c5844ull;
+}  // namespace
+
+int lbm_save(lbm_ctx *c, void *buf, size_t *size) {
+  if (!c || !size) return LBM_EINVAL;
+  const size_t N = c->N, D = c->dim, M = c->M;
+  const size_t npop = (size_t)c->L * c->Q * N;
+  const size_t nrec = D * N + M * N + (c->energy ? N : 0) + (c->has_mech ? (size_t)c->K * N : 0);
+  const size_t need = sizeof(SnapHeader) + sizeof(double) * (npop + nrec);
+  if (!buf) {
+    *size = need;
+    return LBM_OK;
+  }
+  if (*size < need) return fail(c, LBM_EINVAL, "snapshot buffer too small (%zu < %zu)", *size, need);
+  SnapHeader h = {kMagic, N, (uint64_t)c->L, (uint64_t)c->Q, M, (uint64_t)c->K, D, c->steps_done,
+                  c->first_step, c->has_src, 0, 0};
+  memcpy(buf, &h, sizeof(h));
+  double *o = (double *)((char *)buf + sizeof(h));
+  const int q_last = (int)((c->steps_done + 1) & 1);
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, hipMemcpy(o, c->pop[c->cur], sizeof(double) * npop, hipMemcpyDeviceToHost));
+  o += npop;
+  HIPCHK(c, hipMemcpy(o, c->v[q_last], sizeof(double) * D * N, hipMemcpyDeviceToHost));
+  o += D * N;
+  HIPCHK(c, hipMemcpy(o, c->src[q_last], sizeof(double) * M * N, hipMemcpyDeviceToHost));
+  o += M * N;
+  if (c->energy) {
+    HIPCHK(c, hipMemcpy(o, c->T[q_last], sizeof(double) * N, hipMemcpyDeviceToHost));
+    o += N;
+  }
+  if (c->has_mech) HIPCHK(c, hipMemcpy(o, c->theta, sizeof(double) * c->K * N, hipMemcpyDeviceToHost));
+  *size = need;
+  return LBM_OK;
+}
+
+int lbm_load(lbm_ctx *c, const void *buf, size_t size) {
+  if (!c || !buf || size < sizeof(SnapHeader)) return LBM_EINVAL;
+  SnapHeader h;
+  memcpy(&h, buf, sizeof(h));
+  const size_t N = c->N, D = c->dim, M = c->M;
+  if (h.magic != kMagic || h.N != N || h.L != (uint64_t)c->L || h.Q != (uint64_t)c->Q || h.M != M ||
+      h.D != D || h.K != (uint64_t)c->K)
+    return fail(c, LBM_EINVAL, "snapshot does not match this context");
+  const size_t npop = (size_t)c->L * c->Q * N;
+  const size_t nrec = D * N + M * N + (c->energy ? N : 0) + (c->has_mech ? (size_t)c->K * N : 0);
+  if (size < sizeof(SnapHeader) + sizeof(double) * (npop + nrec)) return fail(c, LBM_EINVAL, "snapshot truncated");
+  c->steps_done = h.steps_done;
+  c->first_step = h.first_step;
+  c->has_src = h.has_src;
+  c->cur = 0;
+  const int q_last = (int)((c->steps_done + 1) & 1);
+  const double *o = (const double *)((const char *)buf + sizeof(h));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, hipMemcpy(c->pop[0], o, sizeof(double) * npop, hipMemcpyHostToDevice));
+  o += npop;
+  HIPCHK(c, hipMemcpy(c->v[q_last], o, sizeof(double) * D * N, hipMemcpyHostToDevice));
+  o += D * N;
+  HIPCHK(c, hipMemcpy(c->src[q_last], o, sizeof(double) * M * N, hipMemcpyHostToDevice));
+  o += M * N;
+  if (c->energy) {
+    HIPCHK(c, hipMemcpy(c->T[q_last], o, sizeof(double) * N, hipMemcpyHostToDevice));
+    o += N;
+  }
+  if (c->has_mech) HIPCHK(c, hipMemcpy(c->theta, o, sizeof(double) * c->K * N, hipMemcpyHostToDevice));
+  return LBM_OK;
+}
+
+const char *lbm_last_error(const lbm_ctx *c) { return c ? c->err : "null context"; }
+
+void lbm_destroy(lbm_ctx *c) {
+  if (!c) return;
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  else (void)hipDeviceSynchronize();
+  if (c->timing) lbm_set_timing(c, 0);
+  double *bufs[] = {c->pop[0], c->pop[1], c->phi, c->kfac, c->Tfield, c->X0, c->Plat, c->rA, c->rRT, c->rFk,
+                    c->rrho, c->rY, c->rqd, c->v[0], c->v[1], c->T[0], c->T[1], c->src[0], c->src[1],
+                    c->srcsum, c->theta, c->faradaic, c->macro, c->partials};
+  for (double *b : bufs) dfree(b);
+  dfree(c->colflag);
+  delete c;
+}
+
+}  // extern "C"

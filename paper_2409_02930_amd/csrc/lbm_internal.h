@@ -1,0 +1,106 @@
+// Internal declarations shared by the kernels and the host side of the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define LBM_MMAX 5          // gas species
+#define LBM_KMAX 10         // surface species (vacancy included)
+#define LBM_RMAX 24         // surface reactions
+#define LBM_SMAX (LBM_MMAX + LBM_KMAX)
+
+enum { BC_PERIODIC = 0, BC_BOUNCEBACK = 1, BC_INLET = 2, BC_OUTFLOW = 3 };
+
+// Equilibrium state of a prescribed inlet mixture (lattice units).
+struct InletState {
+  double rho_a[LBM_MMAX];   // species densities X_a P / (R_a T)
+  double RaT[LBM_MMAX];     // R_a T
+  double rho;               // sum of rho_a
+  double RT;                // mixture R T
+  double U;                 // mixture internal energy (energy lattice)
+};
+
+// Everything the per-node stream/collide kernels read.  Passed by value.
+struct KParams {
+  int N, nx, ny, nz;
+  int M, energy, bc_lo, bc_hi;
+  int first_step;           // populations are stored post-stream: identity pull
+  int has_src;              // species source of the previous step still to be streamed
+  int knudsen;              // Knudsen relaxation on
+  int chem;                 // a chemistry source is computed this step
+  int need_v;               // node velocities are needed by the next step
+  int pad0;
+  const int8_t *colflag;    // packed 1-D columns: bit0 = left end, bit1 = right end; NULL = grid
+  double theta_ref, inv_T_ref, nu, prandtl;
+  double mmin_over_m[LBM_MMAX];   // m_min / m_a
+  double inv_m[LBM_MMAX];         // 1 / m_a
+  double Dref[LBM_MMAX * LBM_MMAX];
+  double cv[LBM_MMAX], uf[LBM_MMAX];   // lattice units (per kelvin, absolute)
+  InletState inlet[2];            // x = 0 and x = nx - 1
+  // populations [lattice][direction][node]
+  const double *pin;
+  double *pout;
+  // static per-node fields
+  const double *phi;        // porosity
+  const double *kfac;       // (phi/tort) (d0 / 3 dx) sqrt(8/pi); D^k_a = kfac sqrt(R_a T)
+  const double *Tfield;     // prescribed temperature (isothermal)
+  // records written by the species kernel for the mixture / chemistry kernels
+  double *rA;               // [D][N] rho u (1 - 3RT) - rho u^3 / phi^2
+  double *rRT;              // [N] mixture R T
+  double *rFk;              // [D][N] Knudsen force
+  double *rrho;             // [M][N] species densities (chemistry input)
+  double *rY;               // [M][N] mass fractions (energy lattice)
+  double *rqd;              // [D][N] sum_a H_a Y_a (u_a - u_bar) (energy lattice)
+  // ping-pong records between consecutive steps
+  const double *v_prev;     // [D][N] v = u/phi of the previous step
+  const double *T_prev;     // [N] temperature of the previous step (energy) or Tfield
+  const double *src_prev;   // [M][N] species source of the previous step (rho_dot dt, lattice)
+  double *v_cur;
+  double *T_cur;            // energy only
+  const double *srcsum_cur; // [N] sum_a source of this step (mixture mass source)
+};
+
+struct ChemParams {
+  int N, M, K, R;
+  int n_sub, n_newton;
+  int fuel, product;
+  int8_t nu_f[LBM_RMAX][LBM_SMAX];
+  int8_t nu_b[LBM_RMAX][LBM_SMAX];
+  double A_f[LBM_RMAX], Ea_f[LBM_RMAX], A_b[LBM_RMAX], Ea_b[LBM_RMAX];
+  double m[LBM_MMAX];       // kg/mol
+  double gamma, a_s, rho_unit, dt, R_U;
+  const double *rrho;       // [M][N]
+  const double *T;          // [N]
+  const double *phi;        // [N]
+  const double *faradaic;   // [N] mol m^-3 s^-1 or NULL
+  double *theta;            // [K][N] in place
+  double *src;              // [M][N]
+  double *srcsum;           // [N]
+};
+
+struct InitParams {
+  int N, M, energy, pad;
+  double theta_ref, inv_T_ref;
+  double mmin_over_m[LBM_MMAX];
+  double inv_m[LBM_MMAX];
+  double cv[LBM_MMAX], uf[LBM_MMAX];
+  const double *X0, *Plat, *T0, *phi;
+  double *pop;
+};
+
+// Macroscopic output set of the moments kernel: rows
+//   rho_a (M), u (D), T, P, j_a (M*D), rho, X_a (M)
+struct MomParams {
+  KParams k;
+  double *out;
+};
+
+// launchers (lbm_kernels.hip)
+hipError_t launch_init(int dim, const InitParams &ip, hipStream_t s);
+hipError_t launch_species(int dim, const KParams &p, hipStream_t s);
+hipError_t launch_mixture(int dim, const KParams &p, hipStream_t s);
+hipError_t launch_chem(const ChemParams &cp, hipStream_t s);
+hipError_t launch_moments(int dim, const KParams &p, double *out, hipStream_t s);
+hipError_t launch_diag(int L, int D, int Mmom, int N, const double *pop, double *partials, int nblocks,
+                       hipStream_t s);
+int chem_supported(int M, int K);

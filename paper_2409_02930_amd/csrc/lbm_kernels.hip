@@ -1,0 +1,1185 @@
+// HIP kernels of the mean-field reactive porous-media lattice Boltzmann step (gfx950).
+//
+// One time step is three launches:
+//   k_species  : pull-stream of every lattice, moments, composition, relaxation
+//                rates, the M x M species-momentum solve, the species collision
+//                (Section 2.3, eq finalNumericalEquationsReactive) and the small
+//                per-node records the next two kernels need;
+//   k_chem     : the local surface-chemistry update (Section 4.2), only when a
+//                mechanism or a Faradaic source is installed;
+//   k_mixture  : momentum (eqs f_source, feqmix, Pex) and energy (eqs g_source,
+//                geq_i, gstar) collisions, which need gradients of node records.
+// The species source rho_dot_a dt of step t is added while the next step pulls
+// the species populations (same streaming path, same value), which keeps the
+// chemistry out of the bandwidth-bound species kernel.
+//
+// Populations are FP64 SoA [lattice][direction][node], one thread per node,
+// node index x-fastest so every direction is a coalesced (shifted) stream.
+#include "lbm_internal.h"
+
+#include <math.h>
+
+namespace {
+
+template <int D> struct LQ { static constexpr int Q = (D == 1) ? 3 : (D == 2 ? 9 : 27); };
+
+// velocity component a of direction i: i = sum_a (c_ia + 1) 3^a
+__host__ __device__ constexpr int cdir(int i, int a) {
+  return (a == 0 ? i : (a == 1 ? i / 3 : i / 9)) % 3 - 1;
+}
+
+template <int D> __host__ __device__ constexpr int cnorm2(int i) {
+  return (cdir(i, 0) != 0) + (D > 1 ? (cdir(i, 1) != 0) : 0) + (D > 2 ? (cdir(i, 2) != 0) : 0);
+}
+
+// lattice weight: product form at xi = 0, P = 1/3
+template <int D> __device__ constexpr double wdir(int i) {
+  double w = 1.0;
+  for (int a = 0; a < D; ++a) w *= (cdir(i, a) == 0) ? (2.0 / 3.0) : (1.0 / 6.0);
+  return w;
+}
+
+// Section 2.2: Psi_0 = 1 - P, Psi_{+1} = (xi + P)/2, Psi_{-1} = (-xi + P)/2
+__device__ __forceinline__ double psi1(int c, double xi, double P) {
+  return c == 0 ? (1.0 - P) : (c > 0 ? 0.5 * (xi + P) : 0.5 * (-xi + P));
+}
+
+// product form Psi_i for one direction (i may be a run-time value)
+template <int D>
+__device__ __forceinline__ double psi_dir(int i, const double *xi, const double *P) {
+  double r = psi1(cdir(i, 0), xi[0], P[0]);
+  if (D > 1) r *= psi1(cdir(i, 1), xi[1], P[1]);
+  if (D > 2) r *= psi1(cdir(i, 2), xi[2], P[2]);
+  return r;
+}
+
+// Energy equilibrium (Section 3.3 with O_a = RT d/dv_a + v_a): per direction
+//   a(c) = Psi_c(v, RT + v^2),
+//   e(0) = v^2/2 - (RT^2 + 5/2 RT v^2 + v^4/2),
+//   e(+-1) = (+-(RT v + v^3/2) + RT^2 + 5/2 RT v^2 + v^4/2) / 2,
+//   g_i = phi rho [U prod_a a_a + sum_b e_b prod_{a != b} a_a].
+template <int D>
+__device__ __forceinline__ double geq_dir(int i, double phirho, double U, double RT, const double *v) {
+  double av[3], ev[3];
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    const int c = cdir(i, d);
+    const double vd = v[d];
+    const double P1 = RT + vd * vd;
+    const double xiE = RT * vd + 0.5 * vd * vd * vd;
+    const double PE = RT * RT + 2.5 * RT * vd * vd + 0.5 * vd * vd * vd * vd;
+    av[d] = psi1(c, vd, P1);
+    ev[d] = (c == 0) ? (0.5 * vd * vd - PE) : (c > 0 ? 0.5 * (xiE + PE) : 0.5 * (-xiE + PE));
+  }
+  double pa = av[0];
+#pragma unroll
+  for (int d = 1; d < D; ++d) pa *= av[d];
+  double acc = U * pa;
+#pragma unroll
+  for (int b = 0; b < D; ++b) {
+    double t = ev[b];
+#pragma unroll
+    for (int d = 0; d < D; ++d)
+      if (d != b) t *= av[d];
+    acc += t;
+  }
+  return phirho * acc;
+}
+
+struct Node {
+  int n, x, y, z;
+  int flag;   // bit0: x-low boundary node, bit1: x-high boundary node
+};
+
+// XCD-aware block order: hardware hands block b to XCD b % 8; give each XCD a
+// contiguous range of the domain so neighbouring rows share that XCD's L2.
+__device__ __forceinline__ bool get_node(const KParams &p, Node &nd) {
+  const unsigned nb = gridDim.x;               // multiple of 8 (host pads)
+  const unsigned per = nb >> 3;
+  const unsigned b = blockIdx.x;
+  const unsigned lb = (b & 7u) * per + (b >> 3);
+  const int n = (int)(lb * blockDim.x + threadIdx.x);
+  if (n >= p.N) return false;
+  nd.n = n;
+  if (p.colflag) {
+    nd.x = nd.y = nd.z = 0;
+    nd.flag = p.colflag[n];
+  } else {
+    nd.x = n % p.nx;
+    const int r = n / p.nx;
+    nd.y = r % p.ny;
+    nd.z = r / p.ny;
+    nd.flag = (nd.x == 0 ? 1 : 0) | (nd.x == p.nx - 1 ? 2 : 0);
+  }
+  return true;
+}
+
+struct Src {
+  int kind;   // 0: read stored population, 1: inlet at x-low, 2: inlet at x-high
+  int node;
+  int dir;
+};
+
+// Where the post-stream population of direction i at node nd comes from.
+template <int D>
+__device__ __forceinline__ Src pull_src(const KParams &p, const Node &nd, int i) {
+  Src s;
+  s.kind = 0;
+  s.dir = i;
+  if (p.first_step) {
+    s.node = nd.n;
+    return s;
+  }
+  const int cx = cdir(i, 0);
+  const int cy = D > 1 ? cdir(i, 1) : 0;
+  const int cz = D > 2 ? cdir(i, 2) : 0;
+  const bool lo_miss = (cx == 1) && (nd.flag & 1) && p.bc_lo != BC_PERIODIC;
+  const bool hi_miss = (cx == -1) && (nd.flag & 2) && p.bc_hi != BC_PERIODIC;
+  int ys = nd.y, zs = nd.z;
+  if (D > 1) { ys -= cy; ys += (ys < 0) ? p.ny : 0; ys -= (ys >= p.ny) ? p.ny : 0; }
+  if (D > 2) { zs -= cz; zs += (zs < 0) ? p.nz : 0; zs -= (zs >= p.nz) ? p.nz : 0; }
+  if (lo_miss || hi_miss) {
+    const int kind = lo_miss ? p.bc_lo : p.bc_hi;
+    if (kind == BC_BOUNCEBACK) {
+      s.node = nd.n;
+      s.dir = LQ<D>::Q - 1 - i;
+    } else if (kind == BC_OUTFLOW) {
+      s.node = p.colflag ? nd.n : nd.x + p.nx * (ys + p.ny * zs);
+    } else {
+      s.kind = lo_miss ? 1 : 2;
+      s.node = nd.n;
+    }
+    return s;
+  }
+  if (p.colflag) {
+    s.node = nd.n - cx;
+  } else {
+    int xs = nd.x - cx;
+    xs += (xs < 0) ? p.nx : 0;
+    xs -= (xs >= p.nx) ? p.nx : 0;
+    s.node = xs + p.nx * (ys + p.ny * zs);
+  }
+  return s;
+}
+
+// Node at x + c for the gradient stencil: periodic wrap, mirror ghost (the node
+// itself) across non-periodic x ends.
+template <int D>
+__device__ __forceinline__ int nb_node(const KParams &p, const Node &nd, int i) {
+  const int cx = cdir(i, 0);
+  const int cy = D > 1 ? cdir(i, 1) : 0;
+  const int cz = D > 2 ? cdir(i, 2) : 0;
+  const bool nonper = p.bc_lo != BC_PERIODIC;
+  if (nonper && ((cx == -1 && (nd.flag & 1)) || (cx == 1 && (nd.flag & 2)))) return nd.n;
+  if (p.colflag) return nd.n + cx;
+  int xs = nd.x + cx, ys = nd.y, zs = nd.z;
+  xs += (xs < 0) ? p.nx : 0;
+  xs -= (xs >= p.nx) ? p.nx : 0;
+  if (D > 1) { ys += cy; ys += (ys < 0) ? p.ny : 0; ys -= (ys >= p.ny) ? p.ny : 0; }
+  if (D > 2) { zs += cz; zs += (zs < 0) ? p.nz : 0; zs -= (zs >= p.nz) ? p.nz : 0; }
+  return xs + p.nx * (ys + p.ny * zs);
+}
+
+// ---------------------------------------------------------------------------
+// Species front half: pull, moments, composition, coefficients, solve.
+// Shared by the step kernel and the moments kernel.
+// ---------------------------------------------------------------------------
+template <int D, int M>
+struct SpeciesState {
+  static constexpr int Q = LQ<D>::Q;
+  double f[M][Q];
+  double rho_a[M], jt[M][D], ja[M][D];
+  double rho, u[D], v[D];
+  double Y[M], inv_mix, T, RaT[M], RT;
+  double inv_tau_ab[M][M], beta[M], inv_tk[M];
+  double Fk[D];
+  double sumg;
+};
+
+template <int D, int M, bool ENERGY>
+__device__ __forceinline__ void species_front(const KParams &p, const Node &nd, double phi,
+                                              SpeciesState<D, M> &S) {
+  constexpr int Q = LQ<D>::Q;
+  const int N = p.N;
+  const int n = nd.n;
+  // velocity of this node at the previous step (inlet equilibria)
+  double vb[D];
+  const bool inlet_node = !p.first_step &&
+      (((nd.flag & 1) && p.bc_lo == BC_INLET) || ((nd.flag & 2) && p.bc_hi == BC_INLET));
+#pragma unroll
+  for (int d = 0; d < D; ++d) vb[d] = inlet_node ? p.v_prev[(size_t)d * N + n] : 0.0;
+
+  // ---- momentum lattice: sum f = phi rho (eq fdensity), sum f c = rho u
+  double sf = 0.0, jf[D];
+#pragma unroll
+  for (int d = 0; d < D; ++d) jf[d] = 0.0;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const Src s = pull_src<D>(p, nd, i);
+    double val;
+    if (s.kind == 0) {
+      val = p.pin[(size_t)(M * Q + s.dir) * N + s.node];
+    } else {
+      const InletState &in = p.inlet[s.kind - 1];
+      double P[D];
+#pragma unroll
+      for (int d = 0; d < D; ++d) P[d] = in.RT + vb[d] * vb[d];
+      val = phi * in.rho * psi_dir<D>(i, vb, P);
+    }
+    sf += val;
+#pragma unroll
+    for (int d = 0; d < D; ++d) jf[d] += cdir(i, d) * val;
+  }
+  S.rho = sf / phi;
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    S.u[d] = jf[d] / S.rho;
+    S.v[d] = S.u[d] / phi;
+  }
+  // ---- energy lattice zeroth moment (eq g0momTotalEnergy)
+  S.sumg = 0.0;
+  if (ENERGY) {
+    double sg = 0.0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const Src s = pull_src<D>(p, nd, i);
+      double val;
+      if (s.kind == 0) {
+        val = p.pin[(size_t)((M + 1) * Q + s.dir) * N + s.node];
+      } else {
+        const InletState &in = p.inlet[s.kind - 1];
+        val = geq_dir<D>(i, phi * in.rho, in.U, in.RT, vb);
+      }
+      sg += val;
+    }
+    S.sumg = sg;
+  }
+  // ---- species lattices (+ the source of the previous step, streamed along)
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const Src s = pull_src<D>(p, nd, i);
+    if (s.kind == 0) {
+      double vs[D], Ts = 0.0;
+      if (p.has_src) {
+#pragma unroll
+        for (int d = 0; d < D; ++d) vs[d] = p.v_prev[(size_t)d * N + s.node];
+        Ts = p.T_prev[s.node];
+      }
+#pragma unroll
+      for (int a = 0; a < M; ++a) {
+        double val = p.pin[(size_t)(a * Q + s.dir) * N + s.node];
+        if (p.has_src) {
+          const double sa = p.src_prev[(size_t)a * N + s.node];
+          const double RaTs = p.theta_ref * p.mmin_over_m[a] * (Ts * p.inv_T_ref);
+          double P[D];
+#pragma unroll
+          for (int d = 0; d < D; ++d) P[d] = vs[d] * vs[d] + RaTs;
+          val += sa * psi_dir<D>(s.dir, vs, P);     // eq fsourceHetero
+        }
+        S.f[a][i] = val;
+      }
+    } else {
+      const InletState &in = p.inlet[s.kind - 1];
+#pragma unroll
+      for (int a = 0; a < M; ++a) {
+        double P[D];
+#pragma unroll
+        for (int d = 0; d < D; ++d) P[d] = vb[d] * vb[d] + in.RaT[a];
+        S.f[a][i] = phi * in.rho_a[a] * psi_dir<D>(i, vb, P);
+      }
+    }
+  }
+  // ---- species moments (eqs density1, momentum1)
+#pragma unroll
+  for (int a = 0; a < M; ++a) {
+    double s0 = 0.0, s1[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) s1[d] = 0.0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      s0 += S.f[a][i];
+#pragma unroll
+      for (int d = 0; d < D; ++d) s1[d] += cdir(i, d) * S.f[a][i];
+    }
+    S.rho_a[a] = s0 / phi;
+#pragma unroll
+    for (int d = 0; d < D; ++d) S.jt[a][d] = s1[d];
+  }
+  // ---- composition (Section 2.1)
+  double rs = 0.0;
+#pragma unroll
+  for (int a = 0; a < M; ++a) rs += S.rho_a[a];
+  double im = 0.0;
+#pragma unroll
+  for (int a = 0; a < M; ++a) {
+    S.Y[a] = S.rho_a[a] / rs;
+    im += S.Y[a] * p.inv_m[a];
+  }
+  S.inv_mix = im;
+  // ---- temperature (eq temperature with E - v^2/2, constant heat capacities)
+  if (ENERGY) {
+    const double E = S.sumg / (phi * S.rho);
+    double v2 = 0.0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) v2 += S.v[d] * S.v[d];
+    double cvm = 0.0, u0m = 0.0;
+#pragma unroll
+    for (int a = 0; a < M; ++a) {
+      cvm += S.Y[a] * p.cv[a];
+      u0m += S.Y[a] * p.uf[a];
+    }
+    S.T = (E - 0.5 * v2 - u0m) / cvm;
+  } else {
+    S.T = p.Tfield[n];
+  }
+  double RT = 0.0, Ps = 0.0;
+#pragma unroll
+  for (int a = 0; a < M; ++a) {
+    S.RaT[a] = p.theta_ref * p.mmin_over_m[a] * (S.T * p.inv_T_ref);
+    RT += S.Y[a] * S.RaT[a];
+    Ps += S.rho_a[a] * S.RaT[a];
+  }
+  S.RT = RT;
+  // ---- relaxation rates (eqs tauab, taua, betaa, tauak with the dimensional
+  //      readings tau_ab = D_ab m_a m_b / (m R_U T), tau^k_a = D^k_a m_a / (R_U T))
+  const double Tr = S.T * p.inv_T_ref;
+  const double dfac = Tr * sqrt(Tr) / Ps;        // D_ab(T, P) = D_ab^ref (T/T_ref)^1.5 / P
+#pragma unroll
+  for (int a = 0; a < M; ++a) {
+    double it = 0.0;
+#pragma unroll
+    for (int b = 0; b < M; ++b) {
+      if (b == a) {
+        S.inv_tau_ab[a][b] = 0.0;
+        continue;
+      }
+      // 1/tau_ab = R_a T m / (D_ab m_b)
+      const double iab = S.RaT[a] / (p.Dref[a * LBM_MMAX + b] * dfac * (im / p.inv_m[b]));
+      S.inv_tau_ab[a][b] = iab;
+      it += S.Y[b] * iab;
+    }
+    S.beta[a] = it / (2.0 + it);                 // 1/(2 tau_a + 1)
+    if (p.knudsen) {
+      const double kf = p.kfac[n];
+      S.inv_tk[a] = S.RaT[a] / (kf * sqrt(S.RaT[a]));
+    } else {
+      S.inv_tk[a] = 0.0;
+    }
+  }
+  // ---- second-order species momenta: (1 + 1/2tau_a + 1/2tau^k_a) j_a
+  //      - sum_{b != a} Y_a / (2 tau_ab) j_b = j~_a  (eq transform1 with the
+  //      Knudsen terms); column diagonally dominant -> elimination without pivoting
+  double A[M][M];
+#pragma unroll
+  for (int a = 0; a < M; ++a) {
+    double it = 0.0;
+#pragma unroll
+    for (int b = 0; b < M; ++b) it += (b != a) ? S.Y[b] * S.inv_tau_ab[a][b] : 0.0;
+#pragma unroll
+    for (int b = 0; b < M; ++b)
+      A[a][b] = (a == b) ? (1.0 + 0.5 * it + 0.5 * S.inv_tk[a]) : (-0.5 * S.Y[a] * S.inv_tau_ab[a][b]);
+  }
+  double rhs[M][D];
+#pragma unroll
+  for (int a = 0; a < M; ++a)
+#pragma unroll
+    for (int d = 0; d < D; ++d) rhs[a][d] = S.jt[a][d];
+#pragma unroll
+  for (int k = 0; k < M; ++k) {
+    const double inv = 1.0 / A[k][k];
+#pragma unroll
+    for (int r = k + 1; r < M; ++r) {
+      const double l = A[r][k] * inv;
+#pragma unroll
+      for (int c = k + 1; c < M; ++c) A[r][c] -= l * A[k][c];
+#pragma unroll
+      for (int d = 0; d < D; ++d) rhs[r][d] -= l * rhs[k][d];
+    }
+  }
+#pragma unroll
+  for (int k = M - 1; k >= 0; --k) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      double s = rhs[k][d];
+#pragma unroll
+      for (int c = k + 1; c < M; ++c) s -= A[k][c] * S.ja[c][d];
+      S.ja[k][d] = s / A[k][k];
+    }
+  }
+  // ---- Knudsen force on the mixture (eq netKnudsenForce): F^k = -sum_b j_b / tau^k_b
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    double fk = 0.0;
+#pragma unroll
+    for (int b = 0; b < M; ++b) fk -= S.ja[b][d] * S.inv_tk[b];
+    S.Fk[d] = fk;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// k_species
+// ---------------------------------------------------------------------------
+template <int D, int M, bool ENERGY>
+__global__ __launch_bounds__(256) void k_species(const KParams p) {
+  constexpr int Q = LQ<D>::Q;
+  Node nd;
+  if (!get_node(p, nd)) return;
+  const int N = p.N;
+  const int n = nd.n;
+  const double phi = p.phi[n];
+  SpeciesState<D, M> S;
+  species_front<D, M, ENERGY>(p, nd, phi, S);
+
+  // ---- species collision (eqs finalNumericalEquationsReactive, 27eq, 27qeq,
+  //      fKnudsen, fStar); the source term is added when streaming next step
+  double xs[M][D], Peq[M][D], Pst[M][D], Pk[M][D];
+  const double zero3[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int a = 0; a < M; ++a) {
+    const bool pos = S.rho_a[a] > 0.0;
+    const double den = pos ? phi * S.rho_a[a] : 1.0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      xs[a][d] = pos ? S.ja[a][d] / den : 0.0;
+      Peq[a][d] = S.v[d] * S.v[d] + S.RaT[a];
+      Pst[a][d] = xs[a][d] * xs[a][d] + S.RaT[a];
+      Pk[a][d] = S.RaT[a];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    double diff[M], fst[M], feq[M];
+#pragma unroll
+    for (int a = 0; a < M; ++a) {
+      const double pr = phi * S.rho_a[a];
+      feq[a] = pr * psi_dir<D>(i, S.v, Peq[a]);
+      fst[a] = (S.rho_a[a] > 0.0) ? pr * psi_dir<D>(i, xs[a], Pst[a]) : 0.0;
+      diff[a] = feq[a] - fst[a];
+    }
+#pragma unroll
+    for (int a = 0; a < M; ++a) {
+      double F = 0.0;
+#pragma unroll
+      for (int b = 0; b < M; ++b)
+        if (b != a) F += S.inv_tau_ab[a][b] * diff[b];
+      const double fk = phi * S.rho_a[a] * psi_dir<D>(i, zero3, Pk[a]);
+      F = S.Y[a] * F + S.inv_tk[a] * (fst[a] - fk);
+      const double f0 = S.f[a][i];
+      const double beta = S.beta[a];
+      p.pout[(size_t)(a * Q + i) * N + n] = f0 + 2.0 * beta * (feq[a] - f0) + (beta - 1.0) * F;
+    }
+  }
+
+  // ---- records for the mixture and chemistry kernels
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    const double ud = S.u[d];
+    p.rA[(size_t)d * N + n] = S.rho * ud * (1.0 - 3.0 * S.RT) - S.rho * ud * ud * ud / (phi * phi);
+    if (p.knudsen) p.rFk[(size_t)d * N + n] = S.Fk[d];
+    if (p.need_v) p.v_cur[(size_t)d * N + n] = S.v[d];
+  }
+  p.rRT[n] = S.RT;
+  if (p.chem) {
+#pragma unroll
+    for (int a = 0; a < M; ++a) p.rrho[(size_t)a * N + n] = S.rho_a[a];
+  }
+  if (ENERGY) {
+    p.T_cur[n] = S.T;
+    double ub[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      double s = 0.0;
+#pragma unroll
+      for (int b = 0; b < M; ++b) s += S.Y[b] * ((S.rho_a[b] > 0.0) ? S.ja[b][d] / S.rho_a[b] : S.u[d]);
+      ub[d] = s;
+    }
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      double s = 0.0;
+#pragma unroll
+      for (int a = 0; a < M; ++a) {
+        const double ua = (S.rho_a[a] > 0.0) ? S.ja[a][d] / S.rho_a[a] : S.u[d];
+        const double Ha = p.uf[a] + p.cv[a] * S.T + S.RaT[a];
+        s += Ha * S.Y[a] * (ua - ub[d]);
+      }
+      p.rqd[(size_t)d * N + n] = s;
+    }
+#pragma unroll
+    for (int a = 0; a < M; ++a) p.rY[(size_t)a * N + n] = S.Y[a];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// k_mixture: momentum lattice with the extended equilibrium, energy lattice
+// ---------------------------------------------------------------------------
+template <int D, int M, bool ENERGY>
+__global__ __launch_bounds__(256) void k_mixture(const KParams p) {
+  constexpr int Q = LQ<D>::Q;
+  Node nd;
+  if (!get_node(p, nd)) return;
+  const int N = p.N;
+  const int n = nd.n;
+  const double phi = p.phi[n];
+  double vb[D];
+  const bool inlet_node = !p.first_step &&
+      (((nd.flag & 1) && p.bc_lo == BC_INLET) || ((nd.flag & 2) && p.bc_hi == BC_INLET));
+#pragma unroll
+  for (int d = 0; d < D; ++d) vb[d] = inlet_node ? p.v_prev[(size_t)d * N + n] : 0.0;
+
+  double f[Q];
+  double sf = 0.0, jf[D];
+#pragma unroll
+  for (int d = 0; d < D; ++d) jf[d] = 0.0;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const Src s = pull_src<D>(p, nd, i);
+    double val;
+    if (s.kind == 0) {
+      val = p.pin[(size_t)(M * Q + s.dir) * N + s.node];
+    } else {
+      const InletState &in = p.inlet[s.kind - 1];
+      double P[D];
+#pragma unroll
+      for (int d = 0; d < D; ++d) P[d] = in.RT + vb[d] * vb[d];
+      val = phi * in.rho * psi_dir<D>(i, vb, P);
+    }
+    f[i] = val;
+    sf += val;
+#pragma unroll
+    for (int d = 0; d < D; ++d) jf[d] += cdir(i, d) * val;
+  }
+  const double rho = sf / phi;
+  double u[D], v[D];
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    u[d] = jf[d] / rho;
+    v[d] = u[d] / phi;
+  }
+  const double RT = p.rRT[n];
+  const double omega = 1.0 / (p.nu / RT + 0.5);
+
+  // Galilean correction: G_a = d_a (rho u_a (1 - 3RT) - rho u_a^3 / phi^2), isotropic stencil
+  double G[D];
+#pragma unroll
+  for (int d = 0; d < D; ++d) G[d] = 0.0;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    if (cnorm2<D>(i) == 0) continue;
+    const int m = nb_node<D>(p, nd, i);
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      const int c = cdir(i, d);
+      if (c != 0) G[d] += wdir<D>(i) * c * p.rA[(size_t)d * N + m];
+    }
+  }
+  double Pex[D], xi[D];
+  const double gfac = (2.0 - omega) / (2.0 * phi * rho * omega);
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    G[d] *= 3.0;
+    Pex[d] = RT + v[d] * v[d] + gfac * G[d];
+    const double Fk = p.knudsen ? p.rFk[(size_t)d * N + n] : 0.0;
+    xi[d] = (u[d] + Fk / (omega * rho)) / phi;          // u^ex / phi
+  }
+  const double ratio = p.chem ? p.srcsum_cur[n] / (phi * rho) : 0.0;   // rho_pc / rho - 1
+  const double phirho = phi * rho;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const double fex = phirho * psi_dir<D>(i, xi, Pex);
+    p.pout[(size_t)(M * Q + i) * N + n] = f[i] + omega * (fex - f[i]) + ratio * fex;
+  }
+
+  if (ENERGY) {
+    // second moment of the pre-collision momentum populations
+    double Pab[D][D];
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+      for (int b = 0; b < D; ++b) Pab[a][b] = 0.0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i)
+#pragma unroll
+      for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int b = 0; b < D; ++b) Pab[a][b] += (cdir(i, a) * cdir(i, b)) * f[i];
+    const double T = p.T_cur[n];
+    double Y[M], Ha[M];
+    double U = 0.0;
+#pragma unroll
+    for (int a = 0; a < M; ++a) {
+      Y[a] = p.rY[(size_t)a * N + n];
+      const double Ua = p.uf[a] + p.cv[a] * T;
+      U += Y[a] * Ua;
+      Ha[a] = Ua + p.theta_ref * p.mmin_over_m[a] * (T * p.inv_T_ref);
+    }
+    const double Hmix = U + RT;
+    const double P = rho * RT;
+    const double omega1 = 1.0 / (p.nu / (p.prandtl * RT) + 0.5);
+    double v2 = 0.0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) v2 += v[d] * v[d];
+    // sum_a H_a d_a Y_a (isotropic stencil on the mass fractions)
+    double four[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) four[d] = 0.0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      if (cnorm2<D>(i) == 0) continue;
+      const int m = nb_node<D>(p, nd, i);
+      double hy = 0.0;
+#pragma unroll
+      for (int a = 0; a < M; ++a) hy += Ha[a] * p.rY[(size_t)a * N + m];
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        const int c = cdir(i, d);
+        if (c != 0) four[d] += wdir<D>(i) * c * hy;
+      }
+    }
+    double g[Q], q[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) q[d] = 0.0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const Src s = pull_src<D>(p, nd, i);
+      double val;
+      if (s.kind == 0) {
+        val = p.pin[(size_t)((M + 1) * Q + s.dir) * N + s.node];
+      } else {
+        const InletState &in = p.inlet[s.kind - 1];
+        val = geq_dir<D>(i, phi * in.rho, in.U, in.RT, vb);
+      }
+      g[i] = val;
+#pragma unroll
+      for (int d = 0; d < D; ++d) q[d] += cdir(i, d) * val;
+    }
+    // Q_a = (omega - omega1) (q* - q^eq), expanded (eqs gstareq1mom, interdiffusion,
+    //       corrFourier, qex; natural bulk viscosity)
+    double Qv[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      const double qeq = rho * u[a] * (Hmix + 0.5 * v2);
+      double corr = 0.0;
+#pragma unroll
+      for (int b = 0; b < D; ++b) {
+        const double Peq = phirho * v[a] * v[b] + (a == b ? phi * P : 0.0);
+        corr += v[b] * (Pab[a][b] - Peq);
+      }
+      const double qd = p.rqd[(size_t)a * N + n];
+      Qv[a] = (omega - omega1) * (q[a] - qeq - corr) + omega1 * rho * qd +
+              0.5 * (2.0 - omega1) * P * phi * (3.0 * four[a]) - 0.5 * (omega - omega1) * v[a] * G[a];
+    }
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const double ge = geq_dir<D>(i, phirho, U, RT, v);
+      double out = g[i] + omega * (ge - g[i]);
+      if (cnorm2<D>(i) == 1) {
+        double cq = 0.0;
+#pragma unroll
+        for (int d = 0; d < D; ++d) cq += cdir(i, d) * Qv[d];
+        out += 0.5 * cq;
+      }
+      p.pout[(size_t)((M + 1) * Q + i) * N + n] = out;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// moments kernel: macroscopic fields at the current time level
+// ---------------------------------------------------------------------------
+template <int D, int M, bool ENERGY>
+__global__ __launch_bounds__(256) void k_moments(const KParams p, double *out) {
+  Node nd;
+  if (!get_node(p, nd)) return;
+  const int N = p.N;
+  const int n = nd.n;
+  const double phi = p.phi[n];
+  SpeciesState<D, M> S;
+  species_front<D, M, ENERGY>(p, nd, phi, S);
+  size_t r = 0;
+  double rs = 0.0;
+#pragma unroll
+  for (int a = 0; a < M; ++a) out[(r++) * N + n] = S.rho_a[a];
+#pragma unroll
+  for (int d = 0; d < D; ++d) out[(r++) * N + n] = S.u[d];
+  out[(r++) * N + n] = S.T;
+  out[(r++) * N + n] = S.rho * S.RT;
+#pragma unroll
+  for (int a = 0; a < M; ++a)
+#pragma unroll
+    for (int d = 0; d < D; ++d) out[(r++) * N + n] = S.ja[a][d];
+  out[(r++) * N + n] = S.rho;
+#pragma unroll
+  for (int a = 0; a < M; ++a) rs += S.Y[a] * p.inv_m[a];
+#pragma unroll
+  for (int a = 0; a < M; ++a) out[(r++) * N + n] = (S.Y[a] * p.inv_m[a]) / rs;
+}
+
+// ---------------------------------------------------------------------------
+// initial equilibria at zero velocity (stored post-stream)
+// ---------------------------------------------------------------------------
+template <int D, int M>
+__global__ __launch_bounds__(256) void k_init(const InitParams ip) {
+  constexpr int Q = LQ<D>::Q;
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= ip.N) return;
+  const int N = ip.N;
+  const double phi = ip.phi[n];
+  const double T = ip.T0[n];
+  const double Pl = ip.Plat[n];
+  double rho_a[M], RaT[M];
+  double rho = 0.0;
+#pragma unroll
+  for (int a = 0; a < M; ++a) {
+    RaT[a] = ip.theta_ref * ip.mmin_over_m[a] * (T * ip.inv_T_ref);
+    rho_a[a] = ip.X0[(size_t)a * N + n] * Pl / RaT[a];     // P_a = X_a P = rho_a R_a T
+    rho += rho_a[a];
+  }
+  double RT = 0.0, U = 0.0;
+#pragma unroll
+  for (int a = 0; a < M; ++a) {
+    const double Y = rho_a[a] / rho;
+    RT += Y * RaT[a];
+    U += Y * (ip.uf[a] + ip.cv[a] * T);
+  }
+  const double zero[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+#pragma unroll
+    for (int a = 0; a < M; ++a) {
+      double P[3] = {RaT[a], RaT[a], RaT[a]};
+      ip.pop[(size_t)(a * Q + i) * N + n] = phi * rho_a[a] * psi_dir<D>(i, zero, P);
+    }
+    double P[3] = {RT, RT, RT};
+    ip.pop[(size_t)(M * Q + i) * N + n] = phi * rho * psi_dir<D>(i, zero, P);
+    if (ip.energy) ip.pop[(size_t)((M + 1) * Q + i) * N + n] = geq_dir<D>(i, phi * rho, U, RT, zero);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Surface chemistry (Section 4): backward Euler on gas concentrations and
+// coverages, Newton with dense LU (partial pivoting), extent-based update.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double ipow(double x, int e) {
+  return e == 0 ? 1.0 : (e == 1 ? x : (e == 2 ? x * x : x * x * x));
+}
+
+template <int M, int K>
+__device__ __forceinline__ void chem_rates(const ChemParams &cp, double T, const double *C, double *q) {
+  constexpr int S = M + K;
+#pragma unroll
+  for (int r = 0; r < LBM_RMAX; ++r) {
+    q[r] = 0.0;
+    if (r < cp.R) {
+      const double kf = cp.A_f[r] * exp(-cp.Ea_f[r] / (cp.R_U * T));
+      const double kb = cp.A_b[r] * exp(-cp.Ea_b[r] / (cp.R_U * T));
+      double pf = kf, pb = kb;
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        const int ef = cp.nu_f[r][s], eb = cp.nu_b[r][s];
+        if (ef) pf *= ipow(C[s], ef);
+        if (eb) pb *= ipow(C[s], eb);
+      }
+      q[r] = pf - pb;
+    }
+  }
+}
+
+template <int M, int K>
+__global__ __launch_bounds__(64) void k_chem(const ChemParams cp) {
+  constexpr int S = M + K;
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= cp.N) return;
+  const int N = cp.N;
+  const double T = cp.T[n];
+  const double phi = cp.phi[n];
+  const double gam = cp.gamma;
+  double y0[S];
+#pragma unroll
+  for (int a = 0; a < M; ++a) y0[a] = cp.rrho[(size_t)a * N + n] * cp.rho_unit / cp.m[a];
+#pragma unroll
+  for (int s = 0; s < K; ++s) y0[M + s] = cp.theta[(size_t)s * N + n];
+  double src[M];
+#pragma unroll
+  for (int a = 0; a < M; ++a) src[a] = 0.0;
+  const double h = cp.dt / cp.n_sub;
+  for (int sub = 0; sub < cp.n_sub; ++sub) {
+    double y[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) y[s] = y0[s];
+    for (int it = 0; it < cp.n_newton; ++it) {
+      double C[S];
+#pragma unroll
+      for (int s = 0; s < S; ++s) C[s] = (s < M) ? y[s] : gam * y[s];
+      double J[S][S], b[S];
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        const double w = (s < M) ? phi : gam;
+        b[s] = -(w * (y[s] - y0[s]));
+#pragma unroll
+        for (int t = 0; t < S; ++t) J[s][t] = (s == t) ? w : 0.0;
+      }
+#pragma unroll
+      for (int r = 0; r < LBM_RMAX; ++r) {
+        if (r >= cp.R) continue;
+        const double kf = cp.A_f[r] * exp(-cp.Ea_f[r] / (cp.R_U * T));
+        const double kb = cp.A_b[r] * exp(-cp.Ea_b[r] / (cp.R_U * T));
+        double pf = kf, pb = kb;
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+          const int ef = cp.nu_f[r][s], eb = cp.nu_b[r][s];
+          if (ef) pf *= ipow(C[s], ef);
+          if (eb) pb *= ipow(C[s], eb);
+        }
+        const double q = pf - pb;
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+          const int st = cp.nu_b[r][s] - cp.nu_f[r][s];
+          if (st) b[s] += h * ((s < M) ? cp.a_s : 1.0) * st * q;
+        }
+#pragma unroll
+        for (int t = 0; t < S; ++t) {
+          const int ft = cp.nu_f[r][t], bt = cp.nu_b[r][t];
+          if (!(ft | bt)) continue;
+          double df = 0.0, db = 0.0;
+          if (ft) {
+            df = kf * ft * ipow(C[t], ft - 1);
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+              const int e = cp.nu_f[r][s];
+              if (s != t && e) df *= ipow(C[s], e);
+            }
+          }
+          if (bt) {
+            db = kb * bt * ipow(C[t], bt - 1);
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+              const int e = cp.nu_b[r][s];
+              if (s != t && e) db *= ipow(C[s], e);
+            }
+          }
+          const double dq = (df - db) * ((t < M) ? 1.0 : gam);
+#pragma unroll
+          for (int s = 0; s < S; ++s) {
+            const int st = cp.nu_b[r][s] - cp.nu_f[r][s];
+            if (st) J[s][t] -= h * ((s < M) ? cp.a_s : 1.0) * st * dq;
+          }
+        }
+      }
+      // LU with partial pivoting (first maximum on ties), then substitution
+#pragma unroll
+      for (int k = 0; k < S; ++k) {
+        int piv = k;
+        double amax = fabs(J[k][k]);
+#pragma unroll
+        for (int r = k + 1; r < S; ++r) {
+          const double av = fabs(J[r][k]);
+          if (av > amax) { amax = av; piv = r; }
+        }
+#pragma unroll
+        for (int r = k + 1; r < S; ++r) {
+          const bool sw = (piv == r);
+#pragma unroll
+          for (int c = k; c < S; ++c) {
+            const double tk = J[k][c];
+            J[k][c] = sw ? J[r][c] : tk;
+            J[r][c] = sw ? tk : J[r][c];
+          }
+          const double tb = b[k];
+          b[k] = sw ? b[r] : tb;
+          b[r] = sw ? tb : b[r];
+        }
+        const double inv = 1.0 / J[k][k];
+#pragma unroll
+        for (int r = k + 1; r < S; ++r) {
+          const double l = J[r][k] * inv;
+#pragma unroll
+          for (int c = k + 1; c < S; ++c) J[r][c] -= l * J[k][c];
+          b[r] -= l * b[k];
+        }
+      }
+#pragma unroll
+      for (int k = S - 1; k >= 0; --k) {
+        double s = b[k];
+#pragma unroll
+        for (int c = k + 1; c < S; ++c) s -= J[k][c] * b[c];
+        b[k] = s / J[k][k];
+      }
+#pragma unroll
+      for (int s = 0; s < S; ++s) y[s] += b[s];
+    }
+    // extents at the implicit state, conservative update of both phases
+    double C[S], q[LBM_RMAX];
+#pragma unroll
+    for (int s = 0; s < S; ++s) C[s] = (s < M) ? y[s] : gam * y[s];
+    chem_rates<M, K>(cp, T, C, q);
+    double dn[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) dn[s] = 0.0;
+#pragma unroll
+    for (int r = 0; r < LBM_RMAX; ++r) {
+      if (r >= cp.R) continue;
+      const double dxi = h * q[r];
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        const int st = cp.nu_b[r][s] - cp.nu_f[r][s];
+        if (st) dn[s] += st * dxi;
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < K; ++s) y0[M + s] += dn[M + s] / gam;
+#pragma unroll
+    for (int a = 0; a < M; ++a) {
+      const double dgas = cp.a_s * dn[a];
+      y0[a] += dgas / phi;
+      src[a] += dgas * cp.m[a] / cp.rho_unit;
+    }
+  }
+  if (cp.faradaic) {
+    const double r = cp.faradaic[n] * cp.dt;
+    src[cp.fuel] -= r * cp.m[cp.fuel] / cp.rho_unit;
+    src[cp.product] += r * cp.m[cp.product] / cp.rho_unit;
+  }
+  double ssum = 0.0;
+#pragma unroll
+  for (int a = 0; a < M; ++a) {
+    cp.src[(size_t)a * N + n] = src[a];
+    ssum += src[a];
+  }
+  cp.srcsum[n] = ssum;
+#pragma unroll
+  for (int s = 0; s < K; ++s) cp.theta[(size_t)s * N + n] = y0[M + s];
+}
+
+// Faradaic source only (no mechanism installed).
+template <int M>
+__global__ __launch_bounds__(256) void k_faradaic(const ChemParams cp) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= cp.N) return;
+  const int N = cp.N;
+  const double r = cp.faradaic[n] * cp.dt;
+  double ssum = 0.0;
+#pragma unroll
+  for (int a = 0; a < M; ++a) {
+    double s = 0.0;
+    if (a == cp.fuel) s -= r * cp.m[a] / cp.rho_unit;
+    if (a == cp.product) s += r * cp.m[a] / cp.rho_unit;
+    cp.src[(size_t)a * N + n] = s;
+    ssum += s;
+  }
+  cp.srcsum[n] = ssum;
+}
+
+// ---------------------------------------------------------------------------
+// Deterministic health/conservation reduction: per block, the zeroth moment of
+// every lattice, the first moment of the momentum lattice, the minimum
+// population and the count of non-finite values.  partials: [block][L + D + 2]
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double block_sum(double v, double *sh) {
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) sh[t] += sh[t + w];
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+__global__ __launch_bounds__(256) void k_diag(int L, int D, int Mmom, int N, const double *pop,
+                                              double *partials) {
+  __shared__ double sh[256];
+  const int Q = (D == 1) ? 3 : (D == 2 ? 9 : 27);
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  const int t = threadIdx.x;
+  const int W = L + D + 2;
+  double mn = INFINITY, bad = 0.0;
+  for (int l = 0; l < L; ++l) {
+    double s = 0.0;
+    if (n < N) {
+      for (int i = 0; i < Q; ++i) {
+        const double v = pop[(size_t)(l * Q + i) * N + n];
+        if (!isfinite(v)) bad += 1.0;
+        s += v;
+        mn = fmin(mn, v);
+      }
+    }
+    const double r = block_sum(s, sh);
+    if (t == 0) partials[(size_t)blockIdx.x * W + l] = r;
+  }
+  for (int d = 0; d < D; ++d) {
+    double s = 0.0;
+    if (n < N) {
+      for (int i = 0; i < Q; ++i) {
+        const int c = ((d == 0 ? i : (d == 1 ? i / 3 : i / 9)) % 3) - 1;
+        s += c * pop[(size_t)(Mmom * Q + i) * N + n];
+      }
+    }
+    const double r = block_sum(s, sh);
+    if (t == 0) partials[(size_t)blockIdx.x * W + L + d] = r;
+  }
+  sh[t] = mn;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) sh[t] = fmin(sh[t], sh[t + w]);
+    __syncthreads();
+  }
+  if (t == 0) partials[(size_t)blockIdx.x * W + L + D] = sh[0];
+  __syncthreads();
+  const double nb = block_sum(bad, sh);
+  if (t == 0) partials[(size_t)blockIdx.x * W + L + D + 1] = nb;
+}
+
+unsigned padded_blocks(int N, int bs) {
+  unsigned nb = (unsigned)((N + bs - 1) / bs);
+  return (nb + 7u) & ~7u;
+}
+
+template <int D, int M>
+hipError_t species_dispatch_e(const KParams &p, hipStream_t s) {
+  const unsigned nb = padded_blocks(p.N, 256);
+  if (p.energy)
+    hipLaunchKernelGGL((k_species<D, M, true>), dim3(nb), dim3(256), 0, s, p);
+  else
+    hipLaunchKernelGGL((k_species<D, M, false>), dim3(nb), dim3(256), 0, s, p);
+  return hipGetLastError();
+}
+
+template <int D, int M>
+hipError_t mixture_dispatch_e(const KParams &p, hipStream_t s) {
+  const unsigned nb = padded_blocks(p.N, 256);
+  if (p.energy)
+    hipLaunchKernelGGL((k_mixture<D, M, true>), dim3(nb), dim3(256), 0, s, p);
+  else
+    hipLaunchKernelGGL((k_mixture<D, M, false>), dim3(nb), dim3(256), 0, s, p);
+  return hipGetLastError();
+}
+
+template <int D, int M>
+hipError_t moments_dispatch_e(const KParams &p, double *out, hipStream_t s) {
+  const unsigned nb = padded_blocks(p.N, 256);
+  if (p.energy)
+    hipLaunchKernelGGL((k_moments<D, M, true>), dim3(nb), dim3(256), 0, s, p, out);
+  else
+    hipLaunchKernelGGL((k_moments<D, M, false>), dim3(nb), dim3(256), 0, s, p, out);
+  return hipGetLastError();
+}
+
+template <int D>
+hipError_t species_dispatch(const KParams &p, hipStream_t s) {
+  switch (p.M) {
+    case 2: return species_dispatch_e<D, 2>(p, s);
+    case 3: return species_dispatch_e<D, 3>(p, s);
+    case 4: return species_dispatch_e<D, 4>(p, s);
+    case 5: return species_dispatch_e<D, 5>(p, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int D>
+hipError_t mixture_dispatch(const KParams &p, hipStream_t s) {
+  switch (p.M) {
+    case 2: return mixture_dispatch_e<D, 2>(p, s);
+    case 3: return mixture_dispatch_e<D, 3>(p, s);
+    case 4: return mixture_dispatch_e<D, 4>(p, s);
+    case 5: return mixture_dispatch_e<D, 5>(p, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int D>
+hipError_t moments_dispatch(const KParams &p, double *out, hipStream_t s) {
+  switch (p.M) {
+    case 2: return moments_dispatch_e<D, 2>(p, out, s);
+    case 3: return moments_dispatch_e<D, 3>(p, out, s);
+    case 4: return moments_dispatch_e<D, 4>(p, out, s);
+    case 5: return moments_dispatch_e<D, 5>(p, out, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int D>
+hipError_t init_dispatch(const InitParams &ip, hipStream_t s) {
+  const unsigned nb = (unsigned)((ip.N + 255) / 256);
+  switch (ip.M) {
+    case 2: hipLaunchKernelGGL((k_init<D, 2>), dim3(nb), dim3(256), 0, s, ip); break;
+    case 3: hipLaunchKernelGGL((k_init<D, 3>), dim3(nb), dim3(256), 0, s, ip); break;
+    case 4: hipLaunchKernelGGL((k_init<D, 4>), dim3(nb), dim3(256), 0, s, ip); break;
+    case 5: hipLaunchKernelGGL((k_init<D, 5>), dim3(nb), dim3(256), 0, s, ip); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_init(int dim, const InitParams &ip, hipStream_t s) {
+  switch (dim) {
+    case 1: return init_dispatch<1>(ip, s);
+    case 2: return init_dispatch<2>(ip, s);
+    case 3: return init_dispatch<3>(ip, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_species(int dim, const KParams &p, hipStream_t s) {
+  switch (dim) {
+    case 1: return species_dispatch<1>(p, s);
+    case 2: return species_dispatch<2>(p, s);
+    case 3: return species_dispatch<3>(p, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_mixture(int dim, const KParams &p, hipStream_t s) {
+  switch (dim) {
+    case 1: return mixture_dispatch<1>(p, s);
+    case 2: return mixture_dispatch<2>(p, s);
+    case 3: return mixture_dispatch<3>(p, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_moments(int dim, const KParams &p, double *out, hipStream_t s) {
+  switch (dim) {
+    case 1: return moments_dispatch<1>(p, out, s);
+    case 2: return moments_dispatch<2>(p, out, s);
+    case 3: return moments_dispatch<3>(p, out, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+int chem_supported(int M, int K) {
+  return (M == 2 && K == 2) || (M == 5 && K == 10) || (M == 3 && K == 4);
+}
+
+hipError_t launch_chem(const ChemParams &cp, hipStream_t s) {
+  if (cp.K == 0) {
+    const unsigned nb = (unsigned)((cp.N + 255) / 256);
+    switch (cp.M) {
+      case 2: hipLaunchKernelGGL((k_faradaic<2>), dim3(nb), dim3(256), 0, s, cp); break;
+      case 3: hipLaunchKernelGGL((k_faradaic<3>), dim3(nb), dim3(256), 0, s, cp); break;
+      case 4: hipLaunchKernelGGL((k_faradaic<4>), dim3(nb), dim3(256), 0, s, cp); break;
+      case 5: hipLaunchKernelGGL((k_faradaic<5>), dim3(nb), dim3(256), 0, s, cp); break;
+      default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+  }
+  const unsigned nb = (unsigned)((cp.N + 63) / 64);
+  if (cp.M == 2 && cp.K == 2)
+    hipLaunchKernelGGL((k_chem<2, 2>), dim3(nb), dim3(64), 0, s, cp);
+  else if (cp.M == 3 && cp.K == 4)
+    hipLaunchKernelGGL((k_chem<3, 4>), dim3(nb), dim3(64), 0, s, cp);
+  else if (cp.M == 5 && cp.K == 10)
+    hipLaunchKernelGGL((k_chem<5, 10>), dim3(nb), dim3(64), 0, s, cp);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_diag(int L, int D, int Mmom, int N, const double *pop, double *partials, int nblocks,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_diag, dim3(nblocks), dim3(256), 0, s, L, D, Mmom, N, pop, partials);
+  return hipGetLastError();
+}
