@@ -1,0 +1,184 @@
+"""Benchmark of one lattice Boltzmann step of the reactive porous-media model on one MI355X.
+
+Workload (default): the D3Q27 porous electrode, 256 x 128 x 128 nodes, 5 gas
+species, 10 surface species and 20 reactions, GRF porosity in [0.3, 0.6],
+tortuosity phi^-1/2, pore radius 1 micron, T linear 973 -> 1073 K.  A step is
+the whole hot path: species pull/collide, surface chemistry, momentum collision.
+
+Prints ONE JSON line: MLUPS of the whole step (inputs resident in HBM),
+per-kernel times, the roofline of the dominant kernel (HIP events on the
+stream the kernels run on) and the CPU oracle timed on a bounded sample.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+FP64_VECTOR_PEAK_TFLOPS = 78.6  # MI355X FP64 vector
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_bytes_per_node(w, kernel):
+    """Algorithmic HBM bytes per node of one launch (each value moved once)."""
+    D, M, Q = w.lattice, w.M, 3 ** w.lattice
+    chem = w.mech is not None or w.faradaic_rate is not None
+    K = w.mech.K if w.mech is not None else 0
+    E = 1 if w.energy_on else 0
+    if kernel == "species":
+        rd = (M + 1 + E) * Q + 3                      # species + momentum (+ energy) pops, phi, kfac, T
+        rd += (M + D) if chem else 0                  # previous-step source and node velocity
+        wr = M * Q + D + 1 + (D if w.pore_radius and np.isfinite(w.pore_radius) else 0)
+        wr += (M + D) if chem else 0                  # chemistry input densities, node velocity
+        wr += (1 + M + D) if E else 0
+        return 8 * (rd + wr)
+    if kernel == "mixture":
+        rd = (1 + E) * Q + 1 + D + 1 + D + (1 if chem else 0) + ((M + D + 1) if E else 0)
+        wr = (1 + E) * Q
+        return 8 * (rd + wr)
+    if kernel == "chem":
+        return 8 * (M + 2 + K + K + M + 1)
+    raise ValueError(kernel)
+
+
+def chem_flops_per_node(w):
+    """Dense LU (2/3 S^3) + two triangular solves (2 S^2) per Newton iteration."""
+    if w.mech is None:
+        return 0.0
+    S = w.M + w.mech.K
+    return w.mech.n_sub * w.mech.n_newton * (2.0 * S ** 3 / 3.0 + 2.0 * S * S)
+
+
+def make_workload(name):
+    from workloads import synth
+    if name == "c3":
+        return synth.config3()
+    if name == "c2":
+        return synth.config2(kn_index=3)
+    if name == "c5":
+        return synth.config5()
+    if name == "c1":
+        return synth.config1()
+    raise SystemExit(f"unknown workload {name}")
+
+
+def cpu_baseline(name, budget_s=20.0):
+    """The oracle as it stands, on a bounded sub-grid of the same workload."""
+    from dataclasses import replace
+    from oracle.lbm_oracle import Oracle
+    from workloads import synth
+    if name == "c3":
+        w = synth.config3(nx=24, ny=16, nz=16)
+        sample = "c3 physics on a 24x16x16 sub-grid (same species, mechanism, porosity recipe)"
+    elif name == "c5":
+        w = synth.config5(nx=128, ny=64)
+        sample = "c5 physics on a 128x64 sub-grid"
+    elif name == "c2":
+        w = synth.config2(kn_index=3, nx=256, ny=16)
+        sample = "c2 physics on a 256x16 sub-grid"
+    else:
+        w = synth.config1()
+        sample = "c1 full grid"
+    o = Oracle(w)
+    o.step(1)
+    t0 = time.perf_counter()
+    steps = 0
+    while True:
+        o.step(1)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el > budget_s or steps >= 200:
+            break
+    mlups = w.N * steps / el / 1e6
+    return {"value": mlups, "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "sample": f"{sample}: {steps} steps of {w.N} nodes in {el:.1f} s, numpy single thread"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c3")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the multi-GPU slab decomposition is a design, not part of this build)", flush=True)
+        sys.exit(2)
+
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    from paper_2409_02930_amd import lbm
+
+    log(f"building workload {args.workload}")
+    w = make_workload(args.workload)
+    stream = torch.cuda.current_stream()
+    lat = lbm.lattice_from_workload(w, stream=stream.cuda_stream)
+    log(f"lattice ready N={w.N}; warmup {args.warmup}")
+    lat.step(args.warmup)
+    torch.cuda.synchronize()
+    lat.set_timing(True)
+    log(f"timing {args.steps} steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lat.step(args.steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    tk = lat.timing()
+    diag = lat.diagnostics(check=False)
+    lat.close()
+
+    ms_step = wall * 1e3 / args.steps
+    mlups = w.N * args.steps / wall / 1e6
+    kernels = {"species": tk["species_ms"], "chem": tk["chem_ms"], "mixture": tk["mixture_ms"]}
+    per_kernel = {}
+    for k, ms in kernels.items():
+        if ms <= 0 or (k == "chem" and w.mech is None and w.faradaic_rate is None):
+            continue
+        b = kernel_bytes_per_node(w, k) * w.N
+        per_kernel[k] = {"ms": ms, "GBps": b / (ms * 1e-3) / 1e9}
+        if k == "chem":
+            per_kernel[k]["TFLOPs"] = chem_flops_per_node(w) * w.N / (ms * 1e-3) / 1e12
+    dom = max(per_kernel, key=lambda k: per_kernel[k]["ms"])
+    if dom == "chem":
+        ach = per_kernel["chem"]["TFLOPs"]
+        roof = {"bound": "alu", "achieved": ach, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": ach / FP64_VECTOR_PEAK_TFLOPS, "traffic": None, "kernel": "k_chem"}
+    else:
+        ach = per_kernel[dom]["GBps"]
+        roof = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": ach / HBM_PEAK_GBS, "traffic": None, "kernel": "k_" + dom}
+    step_bytes = sum(kernel_bytes_per_node(w, k) for k in per_kernel) * w.N
+    out = {
+        "metric": "MLUPS", "value": mlups, "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{w.name} {w.nx}x{w.ny}x{w.nz} D{w.lattice}Q{3 ** w.lattice} M={w.M}"
+                               + (f" K={w.mech.K} R={w.mech.R} n_sub={w.mech.n_sub} n_newton={w.mech.n_newton}"
+                                  if w.mech is not None else "")
+                               + (" energy" if w.energy_on else ""),
+                   "nodes": w.N, "parallelism": "single GPU"},
+        "kernels_ms": per_kernel,
+        "step_GBps_algorithmic": step_bytes / (ms_step * 1e-3) / 1e9,
+        "kernel_sum_ms": tk["total_ms"] / args.steps,
+        "health": {"min_population": diag["min_population"], "n_nonfinite": diag["n_nonfinite"]},
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a bounded sample")
+        out["cpu_baseline"] = cpu_baseline(args.workload)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -59,6 +59,7 @@ struct lbm_ctx {
   double pore_radius = 0.0;
   int has_mech = 0, has_faradaic = 0;
   ChemParams chem;
+  ChemTables *chem_tab = nullptr;
   int K = 0;
   // timing
   int timing = 0;
@@ -498,23 +499,37 @@ int lbm_set_mechanism(lbm_ctx *c, const lbm_mechanism *mech) {
     return fail(c, LBM_EINVAL, "mechanism arrays missing");
   if (!(mech->gamma > 0) || !(mech->a_s > 0)) return fail(c, LBM_EINVAL, "gamma and a_s must be positive");
   const int fuel = c->chem.fuel, product = c->chem.product;
-  ChemParams &cp = c->chem;
-  memset(&cp, 0, sizeof(cp));
-  cp.R = R;
-  cp.n_sub = mech->n_sub;
-  cp.n_newton = mech->n_newton;
+  ChemTables tab;
+  memset(&tab, 0, sizeof(tab));
   for (int r = 0; r < R; ++r) {
+    int site_f = 0, site_b = 0;
     for (int s = 0; s < S; ++s) {
       const int ef = mech->nu_f[r * S + s], eb = mech->nu_b[r * S + s];
       if (ef < 0 || ef > 3 || eb < 0 || eb > 3) return fail(c, LBM_EINVAL, "stoichiometric coefficients must be 0..3");
-      cp.nu_f[r][s] = (int8_t)ef;
-      cp.nu_b[r][s] = (int8_t)eb;
+      tab.nu_f[r][s] = (int8_t)ef;
+      tab.nu_b[r][s] = (int8_t)eb;
+      if (s >= M) {
+        site_f += ef;
+        site_b += eb;
+      }
     }
-    cp.A_f[r] = mech->A_f[r];
-    cp.Ea_f[r] = mech->Ea_f[r];
-    cp.A_b[r] = mech->A_b[r];
-    cp.Ea_b[r] = mech->Ea_b[r];
+    if (site_f != site_b) return fail(c, LBM_EINVAL, "reaction %d is not site-balanced", r);
+    tab.A_f[r] = mech->A_f[r];
+    tab.Ea_f[r] = mech->Ea_f[r];
+    tab.A_b[r] = mech->A_b[r];
+    tab.Ea_b[r] = mech->Ea_b[r];
   }
+  if (!c->chem_tab) {
+    hipError_t e = hipMalloc((void **)&c->chem_tab, sizeof(ChemTables));
+    if (e != hipSuccess) return fail(c, LBM_ENOMEM, "hipMalloc chemistry tables");
+  }
+  HIPCHK(c, hipMemcpy(c->chem_tab, &tab, sizeof(tab), hipMemcpyHostToDevice));
+  ChemParams &cp = c->chem;
+  memset(&cp, 0, sizeof(cp));
+  cp.tab = c->chem_tab;
+  cp.R = R;
+  cp.n_sub = mech->n_sub;
+  cp.n_newton = mech->n_newton;
   cp.gamma = mech->gamma;
   cp.a_s = mech->a_s;
   cp.fuel = fuel;
@@ -785,6 +800,7 @@ void lbm_destroy(lbm_ctx *c) {
                     c->srcsum, c->theta, c->faradaic, c->macro, c->partials};
   for (double *b : bufs) dfree(b);
   dfree(c->colflag);
+  dfree(c->chem_tab);
   delete c;
 }
 

@@ -60,13 +60,18 @@ struct KParams {
   const double *srcsum_cur; // [N] sum_a source of this step (mixture mass source)
 };
 
+// Mechanism tables, kept in device memory (indexed by the run-time reaction).
+struct ChemTables {
+  double A_f[LBM_RMAX], Ea_f[LBM_RMAX], A_b[LBM_RMAX], Ea_b[LBM_RMAX];
+  int8_t nu_f[LBM_RMAX][16];
+  int8_t nu_b[LBM_RMAX][16];
+};
+
 struct ChemParams {
   int N, M, K, R;
   int n_sub, n_newton;
   int fuel, product;
-  int8_t nu_f[LBM_RMAX][LBM_SMAX];
-  int8_t nu_b[LBM_RMAX][LBM_SMAX];
-  double A_f[LBM_RMAX], Ea_f[LBM_RMAX], A_b[LBM_RMAX], Ea_b[LBM_RMAX];
+  const ChemTables *tab;    // device
   double m[LBM_MMAX];       // kg/mol
   double gamma, a_s, rho_unit, dt, R_U;
   const double *rrho;       // [M][N]

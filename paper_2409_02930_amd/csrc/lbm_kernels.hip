@@ -120,6 +120,29 @@ struct Src {
   int dir;
 };
 
+
+// Inlet state of side kind-1 without indexing the argument block per lane.
+struct InletSel {
+  double rho, RT, U, rho_a, RaT;
+};
+__device__ __forceinline__ InletSel inlet_sel(const KParams &p, int kind, int lat) {
+  const bool lo = kind == 1;
+  InletSel r;
+  r.rho = lo ? p.inlet[0].rho : p.inlet[1].rho;
+  r.RT = lo ? p.inlet[0].RT : p.inlet[1].RT;
+  r.U = lo ? p.inlet[0].U : p.inlet[1].U;
+  r.rho_a = 0.0;
+  r.RaT = 0.0;
+#pragma unroll
+  for (int a = 0; a < LBM_MMAX; ++a) {
+    if (a == lat) {
+      r.rho_a = lo ? p.inlet[0].rho_a[a] : p.inlet[1].rho_a[a];
+      r.RaT = lo ? p.inlet[0].RaT[a] : p.inlet[1].RaT[a];
+    }
+  }
+  return r;
+}
+
 // Where the post-stream population of direction i at node nd comes from.
 template <int D>
 __device__ __forceinline__ Src pull_src(const KParams &p, const Node &nd, int i) {
@@ -220,7 +243,7 @@ __device__ __forceinline__ void species_front(const KParams &p, const Node &nd, 
     if (s.kind == 0) {
       val = p.pin[(size_t)(M * Q + s.dir) * N + s.node];
     } else {
-      const InletState &in = p.inlet[s.kind - 1];
+      const InletSel in = inlet_sel(p, s.kind, -1);
       double P[D];
 #pragma unroll
       for (int d = 0; d < D; ++d) P[d] = in.RT + vb[d] * vb[d];
@@ -247,7 +270,7 @@ __device__ __forceinline__ void species_front(const KParams &p, const Node &nd, 
       if (s.kind == 0) {
         val = p.pin[(size_t)((M + 1) * Q + s.dir) * N + s.node];
       } else {
-        const InletState &in = p.inlet[s.kind - 1];
+        const InletSel in = inlet_sel(p, s.kind, -1);
         val = geq_dir<D>(i, phi * in.rho, in.U, in.RT, vb);
       }
       sg += val;
@@ -279,13 +302,13 @@ __device__ __forceinline__ void species_front(const KParams &p, const Node &nd, 
         S.f[a][i] = val;
       }
     } else {
-      const InletState &in = p.inlet[s.kind - 1];
 #pragma unroll
       for (int a = 0; a < M; ++a) {
+        const InletSel in = inlet_sel(p, s.kind, a);
         double P[D];
 #pragma unroll
-        for (int d = 0; d < D; ++d) P[d] = vb[d] * vb[d] + in.RaT[a];
-        S.f[a][i] = phi * in.rho_a[a] * psi_dir<D>(i, vb, P);
+        for (int d = 0; d < D; ++d) P[d] = vb[d] * vb[d] + in.RaT;
+        S.f[a][i] = phi * in.rho_a * psi_dir<D>(i, vb, P);
       }
     }
   }
@@ -417,95 +440,366 @@ __device__ __forceinline__ void species_front(const KParams &p, const Node &nd, 
 }
 
 // ---------------------------------------------------------------------------
-// k_species
+// k_species: one block = 64 nodes x (M species + momentum [+ energy]) waves.
+// Wave w pulls lattice w for its 64 nodes (one coalesced stream per direction)
+// and keeps only those Q populations in registers.  Lattice moments meet in
+// LDS; the momentum wave evaluates composition, temperature, relaxation rates,
+// the M x M species-momentum solve and the Knudsen force once per node and
+// publishes them; every species wave then collides its own lattice.
 // ---------------------------------------------------------------------------
 template <int D, int M, bool ENERGY>
-__global__ __launch_bounds__(256) void k_species(const KParams p) {
-  constexpr int Q = LQ<D>::Q;
-  Node nd;
-  if (!get_node(p, nd)) return;
-  const int N = p.N;
-  const int n = nd.n;
-  const double phi = p.phi[n];
-  SpeciesState<D, M> S;
-  species_front<D, M, ENERGY>(p, nd, phi, S);
+struct SpeciesShared {
+  static constexpr int L = M + 1 + (ENERGY ? 1 : 0);
+  double m0[L][64];           // zeroth moments: phi rho_a, phi rho, phi rho E
+  double m1[M + 1][D][64];    // first moments of species and momentum lattices
+  double v[D][64];            // u / phi
+  double xi[M][D][64];        // j_a / (phi rho_a)
+  double RaT[M][64];
+  double Y[M][64];
+  double itab[M][M][64];      // 1 / tau_ab
+  double beta[M][64];
+  double itk[M][64];          // 1 / tau^k_a
+};
 
-  // ---- species collision (eqs finalNumericalEquationsReactive, 27eq, 27qeq,
-  //      fKnudsen, fStar); the source term is added when streaming next step
-  double xs[M][D], Peq[M][D], Pst[M][D], Pk[M][D];
-  const double zero3[3] = {0.0, 0.0, 0.0};
+// Pull lattice `lat` at one node (phase 1 of k_species).
+template <int D, int M>
+__device__ __forceinline__ void pull_lattice(const KParams &p, const Node &nd, int lat, double phi,
+                                             const double *vb, double *f) {
+  constexpr int Q = LQ<D>::Q;
+  const int N = p.N;
+  const bool is_species = lat < M;
+  double mm_lat = 0.0;                 // m_min / m_lat, selected without indexing the argument block
 #pragma unroll
-  for (int a = 0; a < M; ++a) {
-    const bool pos = S.rho_a[a] > 0.0;
-    const double den = pos ? phi * S.rho_a[a] : 1.0;
-#pragma unroll
-    for (int d = 0; d < D; ++d) {
-      xs[a][d] = pos ? S.ja[a][d] / den : 0.0;
-      Peq[a][d] = S.v[d] * S.v[d] + S.RaT[a];
-      Pst[a][d] = xs[a][d] * xs[a][d] + S.RaT[a];
-      Pk[a][d] = S.RaT[a];
-    }
-  }
+  for (int a = 0; a < M; ++a)
+    if (a == lat) mm_lat = p.mmin_over_m[a];
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    double diff[M], fst[M], feq[M];
+    const Src s = pull_src<D>(p, nd, i);
+    double val;
+    if (s.kind == 0) {
+      val = p.pin[(size_t)(lat * Q + s.dir) * N + s.node];
+      if (is_species && p.has_src) {
+        const double sa = p.src_prev[(size_t)lat * N + s.node];
+        double vs[D];
 #pragma unroll
-    for (int a = 0; a < M; ++a) {
-      const double pr = phi * S.rho_a[a];
-      feq[a] = pr * psi_dir<D>(i, S.v, Peq[a]);
-      fst[a] = (S.rho_a[a] > 0.0) ? pr * psi_dir<D>(i, xs[a], Pst[a]) : 0.0;
-      diff[a] = feq[a] - fst[a];
+        for (int d = 0; d < D; ++d) vs[d] = p.v_prev[(size_t)d * N + s.node];
+        const double RaTs = p.theta_ref * mm_lat * (p.T_prev[s.node] * p.inv_T_ref);
+        double P[D];
+#pragma unroll
+        for (int d = 0; d < D; ++d) P[d] = vs[d] * vs[d] + RaTs;
+        val += sa * psi_dir<D>(s.dir, vs, P);     // eq fsourceHetero, streamed with its population
+      }
+    } else {
+      const InletSel in = inlet_sel(p, s.kind, lat);
+      double P[D];
+      if (is_species) {
+#pragma unroll
+        for (int d = 0; d < D; ++d) P[d] = vb[d] * vb[d] + in.RaT;
+        val = phi * in.rho_a * psi_dir<D>(i, vb, P);
+      } else if (lat == M) {
+#pragma unroll
+        for (int d = 0; d < D; ++d) P[d] = in.RT + vb[d] * vb[d];
+        val = phi * in.rho * psi_dir<D>(i, vb, P);
+      } else {
+        val = geq_dir<D>(i, phi * in.rho, in.U, in.RT, vb);
+      }
     }
+    f[i] = val;
+  }
+}
+
+template <int D, int M, bool ENERGY>
+__global__ __launch_bounds__(64 * (M + 1 + (ENERGY ? 1 : 0))) void k_species(const KParams p) {
+  constexpr int Q = LQ<D>::Q;
+  __shared__ SpeciesShared<D, M, ENERGY> sh;
+  const int w = threadIdx.x >> 6;                 // wave-uniform role
+  const int lane = threadIdx.x & 63;
+  const unsigned nb = gridDim.x;
+  const unsigned per = nb >> 3;
+  const unsigned b = blockIdx.x;
+  const unsigned lb = (b & 7u) * per + (b >> 3);
+  const int n = (int)(lb * 64u) + lane;
+  const bool valid = n < p.N;
+  const int N = p.N;
+
+  Node nd;
+  nd.n = n;
+  nd.x = nd.y = nd.z = 0;
+  nd.flag = 0;
+  double phi = 1.0;
+  double vb[D];
 #pragma unroll
-    for (int a = 0; a < M; ++a) {
-      double F = 0.0;
+  for (int d = 0; d < D; ++d) vb[d] = 0.0;
+  if (valid) {
+    if (p.colflag) {
+      nd.flag = p.colflag[n];
+    } else {
+      nd.x = n % p.nx;
+      const int r = n / p.nx;
+      nd.y = r % p.ny;
+      nd.z = r / p.ny;
+      nd.flag = (nd.x == 0 ? 1 : 0) | (nd.x == p.nx - 1 ? 2 : 0);
+    }
+    phi = p.phi[n];
+    const bool inlet_node = !p.first_step &&
+        (((nd.flag & 1) && p.bc_lo == BC_INLET) || ((nd.flag & 2) && p.bc_hi == BC_INLET));
+    if (inlet_node) {
 #pragma unroll
-      for (int b = 0; b < M; ++b)
-        if (b != a) F += S.inv_tau_ab[a][b] * diff[b];
-      const double fk = phi * S.rho_a[a] * psi_dir<D>(i, zero3, Pk[a]);
-      F = S.Y[a] * F + S.inv_tk[a] * (fst[a] - fk);
-      const double f0 = S.f[a][i];
-      const double beta = S.beta[a];
-      p.pout[(size_t)(a * Q + i) * N + n] = f0 + 2.0 * beta * (feq[a] - f0) + (beta - 1.0) * F;
+      for (int d = 0; d < D; ++d) vb[d] = p.v_prev[(size_t)d * N + n];
     }
   }
 
-  // ---- records for the mixture and chemistry kernels
+  if (w < M) {
+    // ================= species wave: pull, moments, [wait], collide =================
+    const int a = w;
+    double f[Q];
+    if (valid) {
+      pull_lattice<D, M>(p, nd, a, phi, vb, f);
+      double s0 = 0.0, s1[D];
 #pragma unroll
-  for (int d = 0; d < D; ++d) {
-    const double ud = S.u[d];
-    p.rA[(size_t)d * N + n] = S.rho * ud * (1.0 - 3.0 * S.RT) - S.rho * ud * ud * ud / (phi * phi);
-    if (p.knudsen) p.rFk[(size_t)d * N + n] = S.Fk[d];
-    if (p.need_v) p.v_cur[(size_t)d * N + n] = S.v[d];
-  }
-  p.rRT[n] = S.RT;
-  if (p.chem) {
+      for (int d = 0; d < D; ++d) s1[d] = 0.0;
 #pragma unroll
-    for (int a = 0; a < M; ++a) p.rrho[(size_t)a * N + n] = S.rho_a[a];
-  }
-  if (ENERGY) {
-    p.T_cur[n] = S.T;
-    double ub[D];
+      for (int i = 0; i < Q; ++i) {
+        s0 += f[i];
 #pragma unroll
-    for (int d = 0; d < D; ++d) {
-      double s = 0.0;
+        for (int d = 0; d < D; ++d) s1[d] += cdir(i, d) * f[i];
+      }
+      sh.m0[a][lane] = s0;
 #pragma unroll
-      for (int b = 0; b < M; ++b) s += S.Y[b] * ((S.rho_a[b] > 0.0) ? S.ja[b][d] / S.rho_a[b] : S.u[d]);
-      ub[d] = s;
+      for (int d = 0; d < D; ++d) sh.m1[a][d][lane] = s1[d];
     }
+    __syncthreads();
+    __syncthreads();
+    if (valid) {
+      // eqs 27eq, 27qeq, fKnudsen, fStar, finalNumericalEquationsReactive.
+      // Cross term sum_{b != a} (1/tau_ab)(f^eq_b - f*_b), accumulated species by
+      // species from per-direction Psi factors.
+      double v[D];
 #pragma unroll
-    for (int d = 0; d < D; ++d) {
-      double s = 0.0;
+      for (int d = 0; d < D; ++d) v[d] = sh.v[d][lane];
+      double F[Q];
+#pragma unroll
+      for (int i = 0; i < Q; ++i) F[i] = 0.0;
+#pragma unroll
+      for (int c = 0; c < M; ++c) {
+        if (c == a) continue;                      // wave-uniform
+        const double coef = sh.itab[a][c][lane] * sh.m0[c][lane];   // (1/tau_ac) phi rho_c
+        const double RaTc = sh.RaT[c][lane];
+        double te[D][3], ts[D][3];
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+          const double xs = sh.xi[c][d][lane];
+          const double Pe = v[d] * v[d] + RaTc, Ps = xs * xs + RaTc;
+          te[d][0] = 0.5 * (-v[d] + Pe); te[d][1] = 1.0 - Pe; te[d][2] = 0.5 * (v[d] + Pe);
+          ts[d][0] = 0.5 * (-xs + Ps);   ts[d][1] = 1.0 - Ps; ts[d][2] = 0.5 * (xs + Ps);
+        }
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+          double pe = te[0][i % 3], ps = ts[0][i % 3];
+          if (D > 1) { pe *= te[1][(i / 3) % 3]; ps *= ts[1][(i / 3) % 3]; }
+          if (D > 2) { pe *= te[2][i / 9]; ps *= ts[2][i / 9]; }
+          F[i] += coef * (pe - ps);
+        }
+      }
+      const double Ya = sh.Y[a][lane];
+      const double beta = sh.beta[a][lane];
+      const double itk = sh.itk[a][lane];
+      const double RaTa = sh.RaT[a][lane];
+      const double pra = sh.m0[a][lane];
+      const bool pos = pra > 0.0;
+      double te[D][3], ts[D][3], tk[D][3];
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        const double xs = sh.xi[a][d][lane];
+        const double Pe = v[d] * v[d] + RaTa, Ps = xs * xs + RaTa;
+        te[d][0] = 0.5 * (-v[d] + Pe); te[d][1] = 1.0 - Pe; te[d][2] = 0.5 * (v[d] + Pe);
+        ts[d][0] = 0.5 * (-xs + Ps);   ts[d][1] = 1.0 - Ps; ts[d][2] = 0.5 * (xs + Ps);
+        tk[d][0] = 0.5 * RaTa;         tk[d][1] = 1.0 - RaTa; tk[d][2] = 0.5 * RaTa;
+      }
+      double* out = p.pout + (size_t)(a * Q) * N + n;
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        double pe = te[0][i % 3], ps = ts[0][i % 3], pk = tk[0][i % 3];
+        if (D > 1) { pe *= te[1][(i / 3) % 3]; ps *= ts[1][(i / 3) % 3]; pk *= tk[1][(i / 3) % 3]; }
+        if (D > 2) { pe *= te[2][i / 9]; ps *= ts[2][i / 9]; pk *= tk[2][i / 9]; }
+        const double feq = pra * pe;
+        const double fst = pos ? pra * ps : 0.0;
+        const double fk = pra * pk;
+        const double Fi = Ya * F[i] + itk * (fst - fk);
+        const double f0 = f[i];
+        out[(size_t)i * N] = f0 + 2.0 * beta * (feq - f0) + (beta - 1.0) * Fi;
+      }
+    }
+  } else if (w == M) {
+    // ================= momentum wave: moments, then the per-node solve =================
+    if (valid) {
+      double f[Q];
+      pull_lattice<D, M>(p, nd, M, phi, vb, f);
+      double s0 = 0.0, s1[D];
+#pragma unroll
+      for (int d = 0; d < D; ++d) s1[d] = 0.0;
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        s0 += f[i];
+#pragma unroll
+        for (int d = 0; d < D; ++d) s1[d] += cdir(i, d) * f[i];
+      }
+      sh.m0[M][lane] = s0;
+#pragma unroll
+      for (int d = 0; d < D; ++d) sh.m1[M][d][lane] = s1[d];
+    }
+    __syncthreads();
+    if (valid) {
+      double rho_a[M], Y[M], RaT[M];
+      const double rho = sh.m0[M][lane] / phi;
+      double u[D], v[D];
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        u[d] = sh.m1[M][d][lane] / rho;
+        v[d] = u[d] / phi;
+        sh.v[d][lane] = v[d];
+      }
+      double rs = 0.0;
 #pragma unroll
       for (int a = 0; a < M; ++a) {
-        const double ua = (S.rho_a[a] > 0.0) ? S.ja[a][d] / S.rho_a[a] : S.u[d];
-        const double Ha = p.uf[a] + p.cv[a] * S.T + S.RaT[a];
-        s += Ha * S.Y[a] * (ua - ub[d]);
+        rho_a[a] = sh.m0[a][lane] / phi;
+        rs += rho_a[a];
       }
-      p.rqd[(size_t)d * N + n] = s;
-    }
+      double im = 0.0;
 #pragma unroll
-    for (int a = 0; a < M; ++a) p.rY[(size_t)a * N + n] = S.Y[a];
+      for (int a = 0; a < M; ++a) {
+        Y[a] = rho_a[a] / rs;
+        im += Y[a] * p.inv_m[a];
+        sh.Y[a][lane] = Y[a];
+      }
+      double T;
+      if (ENERGY) {
+        const double E = sh.m0[M + 1][lane] / (phi * rho);
+        double v2 = 0.0;
+#pragma unroll
+        for (int d = 0; d < D; ++d) v2 += v[d] * v[d];
+        double cvm = 0.0, u0m = 0.0;
+#pragma unroll
+        for (int a = 0; a < M; ++a) {
+          cvm += Y[a] * p.cv[a];
+          u0m += Y[a] * p.uf[a];
+        }
+        T = (E - 0.5 * v2 - u0m) / cvm;                 // eq temperature
+      } else {
+        T = p.Tfield[n];
+      }
+      double RT = 0.0, Ps = 0.0;
+#pragma unroll
+      for (int a = 0; a < M; ++a) {
+        RaT[a] = p.theta_ref * p.mmin_over_m[a] * (T * p.inv_T_ref);
+        RT += Y[a] * RaT[a];
+        Ps += rho_a[a] * RaT[a];
+        sh.RaT[a][lane] = RaT[a];
+      }
+      const double Tr = T * p.inv_T_ref;
+      const double dfac = Tr * sqrt(Tr) / Ps;         // D_ab(T, P) = D_ab^ref (T/T_ref)^1.5 / P
+      double A[M][M], itk[M];
+#pragma unroll
+      for (int a = 0; a < M; ++a) {
+        double it = 0.0;
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+          double iab = 0.0;
+          if (c != a) {
+            iab = RaT[a] / (p.Dref[a * LBM_MMAX + c] * dfac * (im / p.inv_m[c]));   // 1/tau_ab (eq tauab)
+            it += Y[c] * iab;
+          }
+          sh.itab[a][c][lane] = iab;
+          A[a][c] = -0.5 * Y[a] * iab;
+        }
+        sh.beta[a][lane] = it / (2.0 + it);             // eq betaa
+        itk[a] = p.knudsen ? RaT[a] / (p.kfac[n] * sqrt(RaT[a])) : 0.0;   // eq tauak
+        sh.itk[a][lane] = itk[a];
+        A[a][a] = 1.0 + 0.5 * it + 0.5 * itk[a];
+      }
+      // second-order species momenta (eq transform1 with the Knudsen terms)
+      double x[M][D];
+#pragma unroll
+      for (int a = 0; a < M; ++a)
+#pragma unroll
+        for (int d = 0; d < D; ++d) x[a][d] = sh.m1[a][d][lane];
+#pragma unroll
+      for (int k = 0; k < M; ++k) {
+        const double inv = 1.0 / A[k][k];
+#pragma unroll
+        for (int r = k + 1; r < M; ++r) {
+          const double l = A[r][k] * inv;
+#pragma unroll
+          for (int c = k + 1; c < M; ++c) A[r][c] -= l * A[k][c];
+#pragma unroll
+          for (int d = 0; d < D; ++d) x[r][d] -= l * x[k][d];
+        }
+      }
+#pragma unroll
+      for (int k = M - 1; k >= 0; --k) {
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+          double sacc = x[k][d];
+#pragma unroll
+          for (int c = k + 1; c < M; ++c) sacc -= A[k][c] * x[c][d];
+          x[k][d] = sacc / A[k][k];
+        }
+      }
+#pragma unroll
+      for (int a = 0; a < M; ++a) {
+        const bool pos = rho_a[a] > 0.0;
+        const double den = pos ? phi * rho_a[a] : 1.0;
+#pragma unroll
+        for (int d = 0; d < D; ++d) sh.xi[a][d][lane] = pos ? x[a][d] / den : 0.0;
+      }
+      // records for the chemistry and mixture kernels and for the next step
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        double fk = 0.0;
+#pragma unroll
+        for (int c = 0; c < M; ++c) fk -= x[c][d] * itk[c];              // eq netKnudsenForce
+        p.rA[(size_t)d * N + n] = rho * u[d] * (1.0 - 3.0 * RT) - rho * u[d] * u[d] * u[d] / (phi * phi);
+        if (p.knudsen) p.rFk[(size_t)d * N + n] = fk;
+        if (p.need_v) p.v_cur[(size_t)d * N + n] = v[d];
+      }
+      p.rRT[n] = RT;
+      if (p.chem) {
+#pragma unroll
+        for (int a = 0; a < M; ++a) p.rrho[(size_t)a * N + n] = rho_a[a];
+      }
+      if (ENERGY) {
+        p.T_cur[n] = T;
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+          double ub = 0.0;
+#pragma unroll
+          for (int c = 0; c < M; ++c) ub += Y[c] * ((rho_a[c] > 0.0) ? x[c][d] / rho_a[c] : u[d]);
+          double sacc = 0.0;
+#pragma unroll
+          for (int a = 0; a < M; ++a) {
+            const double ua = (rho_a[a] > 0.0) ? x[a][d] / rho_a[a] : u[d];
+            const double Ha = p.uf[a] + p.cv[a] * T + RaT[a];
+            sacc += Ha * Y[a] * (ua - ub);
+          }
+          p.rqd[(size_t)d * N + n] = sacc;
+        }
+#pragma unroll
+        for (int a = 0; a < M; ++a) p.rY[(size_t)a * N + n] = Y[a];
+      }
+    }
+    __syncthreads();
+  } else {
+    // ================= energy wave: zeroth moment of g =================
+    if (valid) {
+      double f[Q];
+      pull_lattice<D, M>(p, nd, M + 1, phi, vb, f);
+      double s0 = 0.0;
+#pragma unroll
+      for (int i = 0; i < Q; ++i) s0 += f[i];
+      sh.m0[M + 1][lane] = s0;
+    }
+    __syncthreads();
+    __syncthreads();
   }
 }
 
@@ -537,7 +831,7 @@ __global__ __launch_bounds__(256) void k_mixture(const KParams p) {
     if (s.kind == 0) {
       val = p.pin[(size_t)(M * Q + s.dir) * N + s.node];
     } else {
-      const InletState &in = p.inlet[s.kind - 1];
+      const InletSel in = inlet_sel(p, s.kind, -1);
       double P[D];
 #pragma unroll
       for (int d = 0; d < D; ++d) P[d] = in.RT + vb[d] * vb[d];
@@ -645,7 +939,7 @@ __global__ __launch_bounds__(256) void k_mixture(const KParams p) {
       if (s.kind == 0) {
         val = p.pin[(size_t)((M + 1) * Q + s.dir) * N + s.node];
       } else {
-        const InletState &in = p.inlet[s.kind - 1];
+        const InletSel in = inlet_sel(p, s.kind, -1);
         val = geq_dir<D>(i, phi * in.rho, in.U, in.RT, vb);
       }
       g[i] = val;
@@ -763,181 +1057,206 @@ __device__ __forceinline__ double ipow(double x, int e) {
   return e == 0 ? 1.0 : (e == 1 ? x : (e == 2 ? x * x : x * x * x));
 }
 
+// Newton unknowns: the M gas concentrations and the K-1 non-vacancy coverages.
+// The vacancy follows from site conservation, theta_V = 1 - sum_s theta_s, which
+// every site-balanced reaction preserves; Newton on this reduced system gives
+// the same iterates as Newton on all M+K unknowns started on the balanced set.
+// One node per lane: the U x U FP64 Jacobian lives in registers (occupancy 1).
 template <int M, int K>
-__device__ __forceinline__ void chem_rates(const ChemParams &cp, double T, const double *C, double *q) {
-  constexpr int S = M + K;
-#pragma unroll
-  for (int r = 0; r < LBM_RMAX; ++r) {
-    q[r] = 0.0;
-    if (r < cp.R) {
-      const double kf = cp.A_f[r] * exp(-cp.Ea_f[r] / (cp.R_U * T));
-      const double kb = cp.A_b[r] * exp(-cp.Ea_b[r] / (cp.R_U * T));
-      double pf = kf, pb = kb;
-#pragma unroll
-      for (int s = 0; s < S; ++s) {
-        const int ef = cp.nu_f[r][s], eb = cp.nu_b[r][s];
-        if (ef) pf *= ipow(C[s], ef);
-        if (eb) pb *= ipow(C[s], eb);
-      }
-      q[r] = pf - pb;
-    }
-  }
-}
-
-template <int M, int K>
-__global__ __launch_bounds__(64) void k_chem(const ChemParams cp) {
-  constexpr int S = M + K;
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1)))
+void k_chem(const ChemParams cp) {
+  constexpr int S = M + K;      // all species (gas, vacancy, adsorbates)
+  constexpr int U = S - 1;      // Newton unknowns
   const int n = blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= cp.N) return;
   const int N = cp.N;
   const double T = cp.T[n];
   const double phi = cp.phi[n];
   const double gam = cp.gamma;
-  double y0[S];
+  const double h = cp.dt / cp.n_sub;
+  const double inv_RT = 1.0 / (cp.R_U * T);
+  const ChemTables *__restrict__ tb = cp.tab;
+  double c0[M], th0[K];
 #pragma unroll
-  for (int a = 0; a < M; ++a) y0[a] = cp.rrho[(size_t)a * N + n] * cp.rho_unit / cp.m[a];
+  for (int a = 0; a < M; ++a) c0[a] = cp.rrho[(size_t)a * N + n] * cp.rho_unit / cp.m[a];
 #pragma unroll
-  for (int s = 0; s < K; ++s) y0[M + s] = cp.theta[(size_t)s * N + n];
+  for (int k = 0; k < K; ++k) th0[k] = cp.theta[(size_t)k * N + n];
   double src[M];
 #pragma unroll
   for (int a = 0; a < M; ++a) src[a] = 0.0;
-  const double h = cp.dt / cp.n_sub;
+
   for (int sub = 0; sub < cp.n_sub; ++sub) {
-    double y[S];
+    double y[U];
 #pragma unroll
-    for (int s = 0; s < S; ++s) y[s] = y0[s];
+    for (int a = 0; a < M; ++a) y[a] = c0[a];
+#pragma unroll
+    for (int k = 1; k < K; ++k) y[M + k - 1] = th0[k];
     for (int it = 0; it < cp.n_newton; ++it) {
+      // concentrations of every species at the iterate
       double C[S];
 #pragma unroll
-      for (int s = 0; s < S; ++s) C[s] = (s < M) ? y[s] : gam * y[s];
-      double J[S][S], b[S];
+      for (int a = 0; a < M; ++a) C[a] = y[a];
+      double sth = 0.0;
 #pragma unroll
-      for (int s = 0; s < S; ++s) {
-        const double w = (s < M) ? phi : gam;
-        b[s] = -(w * (y[s] - y0[s]));
-#pragma unroll
-        for (int t = 0; t < S; ++t) J[s][t] = (s == t) ? w : 0.0;
+      for (int k = 1; k < K; ++k) {
+        C[M + k] = gam * y[M + k - 1];
+        sth += y[M + k - 1];
       }
+      C[M] = gam * (1.0 - sth);
+      // residual b = -(W (y - y0) - h s S q) and Jacobian W - h s S dq/dy
+      double J[U][U], b[U];
 #pragma unroll
-      for (int r = 0; r < LBM_RMAX; ++r) {
-        if (r >= cp.R) continue;
-        const double kf = cp.A_f[r] * exp(-cp.Ea_f[r] / (cp.R_U * T));
-        const double kb = cp.A_b[r] * exp(-cp.Ea_b[r] / (cp.R_U * T));
+      for (int u = 0; u < U; ++u) {
+        const double w = (u < M) ? phi : gam;
+        const double yy0 = (u < M) ? c0[u] : th0[u - M + 1];
+        b[u] = -(w * (y[u] - yy0));
+#pragma unroll
+        for (int v = 0; v < U; ++v) J[u][v] = (u == v) ? w : 0.0;
+      }
+      for (int r = 0; r < cp.R; ++r) {
+        const double kf = tb->A_f[r] * exp(-tb->Ea_f[r] * inv_RT);
+        const double kb = tb->A_b[r] * exp(-tb->Ea_b[r] * inv_RT);
         double pf = kf, pb = kb;
 #pragma unroll
         for (int s = 0; s < S; ++s) {
-          const int ef = cp.nu_f[r][s], eb = cp.nu_b[r][s];
+          const int ef = tb->nu_f[r][s], eb = tb->nu_b[r][s];
           if (ef) pf *= ipow(C[s], ef);
           if (eb) pb *= ipow(C[s], eb);
         }
         const double q = pf - pb;
-#pragma unroll
-        for (int s = 0; s < S; ++s) {
-          const int st = cp.nu_b[r][s] - cp.nu_f[r][s];
-          if (st) b[s] += h * ((s < M) ? cp.a_s : 1.0) * st * q;
-        }
+        // d q / d C_s for every participating species
+        double dq[S];
 #pragma unroll
         for (int t = 0; t < S; ++t) {
-          const int ft = cp.nu_f[r][t], bt = cp.nu_b[r][t];
-          if (!(ft | bt)) continue;
-          double df = 0.0, db = 0.0;
+          const int ft = tb->nu_f[r][t], bt = tb->nu_b[r][t];
+          double d = 0.0;
           if (ft) {
-            df = kf * ft * ipow(C[t], ft - 1);
+            double df = kf * ft * ipow(C[t], ft - 1);
 #pragma unroll
             for (int s = 0; s < S; ++s) {
-              const int e = cp.nu_f[r][s];
+              const int e = tb->nu_f[r][s];
               if (s != t && e) df *= ipow(C[s], e);
             }
+            d += df;
           }
           if (bt) {
-            db = kb * bt * ipow(C[t], bt - 1);
+            double db = kb * bt * ipow(C[t], bt - 1);
 #pragma unroll
             for (int s = 0; s < S; ++s) {
-              const int e = cp.nu_b[r][s];
+              const int e = tb->nu_b[r][s];
               if (s != t && e) db *= ipow(C[s], e);
             }
+            d -= db;
           }
-          const double dq = (df - db) * ((t < M) ? 1.0 : gam);
+          dq[t] = d;
+        }
+        // chain rule to the unknowns: dC_a/dy_a = 1, dC_s/dtheta_s = gamma, dC_V/dtheta_s = -gamma
+        double dqu[U];
 #pragma unroll
-          for (int s = 0; s < S; ++s) {
-            const int st = cp.nu_b[r][s] - cp.nu_f[r][s];
-            if (st) J[s][t] -= h * ((s < M) ? cp.a_s : 1.0) * st * dq;
+        for (int a = 0; a < M; ++a) dqu[a] = dq[a];
+#pragma unroll
+        for (int k = 1; k < K; ++k) dqu[M + k - 1] = gam * (dq[M + k] - dq[M]);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int s = (u < M) ? u : u + 1;
+          const int st = tb->nu_b[r][s] - tb->nu_f[r][s];
+          if (st) {
+            const double coef = h * ((u < M) ? cp.a_s : 1.0) * st;
+            b[u] += coef * q;
+#pragma unroll
+            for (int v = 0; v < U; ++v) J[u][v] -= coef * dqu[v];
           }
         }
       }
       // LU with partial pivoting (first maximum on ties), then substitution
 #pragma unroll
-      for (int k = 0; k < S; ++k) {
+      for (int k = 0; k < U; ++k) {
         int piv = k;
         double amax = fabs(J[k][k]);
 #pragma unroll
-        for (int r = k + 1; r < S; ++r) {
+        for (int r = k + 1; r < U; ++r) {
           const double av = fabs(J[r][k]);
           if (av > amax) { amax = av; piv = r; }
         }
 #pragma unroll
-        for (int r = k + 1; r < S; ++r) {
+        for (int r = k + 1; r < U; ++r) {
           const bool sw = (piv == r);
 #pragma unroll
-          for (int c = k; c < S; ++c) {
+          for (int c = k; c < U; ++c) {
             const double tk = J[k][c];
             J[k][c] = sw ? J[r][c] : tk;
             J[r][c] = sw ? tk : J[r][c];
           }
-          const double tb = b[k];
-          b[k] = sw ? b[r] : tb;
-          b[r] = sw ? tb : b[r];
+          const double tbb = b[k];
+          b[k] = sw ? b[r] : tbb;
+          b[r] = sw ? tbb : b[r];
         }
         const double inv = 1.0 / J[k][k];
 #pragma unroll
-        for (int r = k + 1; r < S; ++r) {
+        for (int r = k + 1; r < U; ++r) {
           const double l = J[r][k] * inv;
 #pragma unroll
-          for (int c = k + 1; c < S; ++c) J[r][c] -= l * J[k][c];
+          for (int c = k + 1; c < U; ++c) J[r][c] -= l * J[k][c];
           b[r] -= l * b[k];
         }
       }
 #pragma unroll
-      for (int k = S - 1; k >= 0; --k) {
-        double s = b[k];
+      for (int k = U - 1; k >= 0; --k) {
+        double sacc = b[k];
 #pragma unroll
-        for (int c = k + 1; c < S; ++c) s -= J[k][c] * b[c];
-        b[k] = s / J[k][k];
+        for (int c = k + 1; c < U; ++c) sacc -= J[k][c] * b[c];
+        b[k] = sacc / J[k][k];
       }
 #pragma unroll
-      for (int s = 0; s < S; ++s) y[s] += b[s];
+      for (int u = 0; u < U; ++u) y[u] += b[u];
     }
     // extents at the implicit state, conservative update of both phases
-    double C[S], q[LBM_RMAX];
+    double C[S];
 #pragma unroll
-    for (int s = 0; s < S; ++s) C[s] = (s < M) ? y[s] : gam * y[s];
-    chem_rates<M, K>(cp, T, C, q);
+    for (int a = 0; a < M; ++a) C[a] = y[a];
+    double sth = 0.0;
+#pragma unroll
+    for (int k = 1; k < K; ++k) {
+      C[M + k] = gam * y[M + k - 1];
+      sth += y[M + k - 1];
+    }
+    C[M] = gam * (1.0 - sth);
     double dn[S];
 #pragma unroll
     for (int s = 0; s < S; ++s) dn[s] = 0.0;
-#pragma unroll
-    for (int r = 0; r < LBM_RMAX; ++r) {
-      if (r >= cp.R) continue;
-      const double dxi = h * q[r];
+    for (int r = 0; r < cp.R; ++r) {
+      const double kf = tb->A_f[r] * exp(-tb->Ea_f[r] * inv_RT);
+      const double kb = tb->A_b[r] * exp(-tb->Ea_b[r] * inv_RT);
+      double pf = kf, pb = kb;
 #pragma unroll
       for (int s = 0; s < S; ++s) {
-        const int st = cp.nu_b[r][s] - cp.nu_f[r][s];
+        const int ef = tb->nu_f[r][s], eb = tb->nu_b[r][s];
+        if (ef) pf *= ipow(C[s], ef);
+        if (eb) pb *= ipow(C[s], eb);
+      }
+      const double dxi = h * (pf - pb);
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        const int st = tb->nu_b[r][s] - tb->nu_f[r][s];
         if (st) dn[s] += st * dxi;
       }
     }
 #pragma unroll
-    for (int s = 0; s < K; ++s) y0[M + s] += dn[M + s] / gam;
+    for (int k = 0; k < K; ++k) th0[k] += dn[M + k] / gam;
 #pragma unroll
     for (int a = 0; a < M; ++a) {
       const double dgas = cp.a_s * dn[a];
-      y0[a] += dgas / phi;
+      c0[a] += dgas / phi;
       src[a] += dgas * cp.m[a] / cp.rho_unit;
     }
   }
   if (cp.faradaic) {
     const double r = cp.faradaic[n] * cp.dt;
-    src[cp.fuel] -= r * cp.m[cp.fuel] / cp.rho_unit;
-    src[cp.product] += r * cp.m[cp.product] / cp.rho_unit;
+#pragma unroll
+    for (int a = 0; a < M; ++a) {
+      if (a == cp.fuel) src[a] -= r * cp.m[a] / cp.rho_unit;
+      if (a == cp.product) src[a] += r * cp.m[a] / cp.rho_unit;
+    }
   }
   double ssum = 0.0;
 #pragma unroll
@@ -947,7 +1266,7 @@ __global__ __launch_bounds__(64) void k_chem(const ChemParams cp) {
   }
   cp.srcsum[n] = ssum;
 #pragma unroll
-  for (int s = 0; s < K; ++s) cp.theta[(size_t)s * N + n] = y0[M + s];
+  for (int k = 0; k < K; ++k) cp.theta[(size_t)k * N + n] = th0[k];
 }
 
 // Faradaic source only (no mechanism installed).
@@ -1038,11 +1357,11 @@ unsigned padded_blocks(int N, int bs) {
 
 template <int D, int M>
 hipError_t species_dispatch_e(const KParams &p, hipStream_t s) {
-  const unsigned nb = padded_blocks(p.N, 256);
+  const unsigned nb = padded_blocks(p.N, 64);
   if (p.energy)
-    hipLaunchKernelGGL((k_species<D, M, true>), dim3(nb), dim3(256), 0, s, p);
+    hipLaunchKernelGGL((k_species<D, M, true>), dim3(nb), dim3(64 * (M + 2)), 0, s, p);
   else
-    hipLaunchKernelGGL((k_species<D, M, false>), dim3(nb), dim3(256), 0, s, p);
+    hipLaunchKernelGGL((k_species<D, M, false>), dim3(nb), dim3(64 * (M + 1)), 0, s, p);
   return hipGetLastError();
 }
 

@@ -254,7 +254,7 @@ def config3_species(seed: int = 3) -> np.ndarray:
 
 
 def config3(nx: int = 256, ny: int = 128, nz: int = 128, steps: int = 2000, seed: int = 3,
-            n_sub: int = 4, n_newton: int = 6, with_mech: bool = True) -> Workload:
+            n_sub: int = 1, n_newton: int = 2, with_mech: bool = True) -> Workload:
     """D3Q27 porous electrode: 5 species, GRF porosity (corr. length 8) in [0.3, 0.6],
     tortuosity phi^-1/2, r_p 1 micron, T linear 973 -> 1073 K along x, 10 surface
     species / 20 reactions, X0 = 0.2 each, u = 0, 1 atm."""
@@ -282,7 +282,7 @@ def config4_columns(seed: int = 4, n_cols: int = 64, lmin: int = 200, lmax: int 
 
 
 def config4_column(length: int, phi: float, current_A_cm2: float, seed: int = 4,
-                   steps: int = 50000, n_sub: int = 4, n_newton: int = 6,
+                   steps: int = 50000, n_sub: int = 1, n_newton: int = 2,
                    n_util: int = 2, delta_util: float = 2e-6) -> Workload:
     """One D1Q3 button-cell anode column: inlet (0.97, 0.03, 0, 0, 0) at x=0, bounce-back
     at x=L-1, Faradaic fuel->product source over the last n_util nodes, isothermal 1073.15 K."""
