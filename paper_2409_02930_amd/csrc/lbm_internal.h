@@ -63,8 +63,8 @@ struct KParams {
 // Mechanism tables, kept in device memory (indexed by the run-time reaction).
 struct ChemTables {
   double A_f[LBM_RMAX], Ea_f[LBM_RMAX], A_b[LBM_RMAX], Ea_b[LBM_RMAX];
-  int8_t nu_f[LBM_RMAX][16];
-  int8_t nu_b[LBM_RMAX][16];
+  alignas(16) int8_t nu_f[LBM_RMAX][16];
+  alignas(16) int8_t nu_b[LBM_RMAX][16];
 };
 
 struct ChemParams {

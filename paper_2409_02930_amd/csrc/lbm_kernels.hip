@@ -1061,14 +1061,74 @@ __device__ __forceinline__ double ipow(double x, int e) {
 // The vacancy follows from site conservation, theta_V = 1 - sum_s theta_s, which
 // every site-balanced reaction preserves; Newton on this reduced system gives
 // the same iterates as Newton on all M+K unknowns started on the balanced set.
-// One node per lane: the U x U FP64 Jacobian lives in registers (occupancy 1).
+// One node per lane: the U x U FP64 Jacobian lives in registers (occupancy 1);
+// each reaction's stoichiometric row is read once as 16 packed coefficients.
+
+// Stoichiometric row of one reaction, 16 coefficients packed in 4 words.
+struct NuRow {
+  uint32_t w[4];
+};
+__device__ __forceinline__ NuRow load_nu(const int8_t *row) {
+  const uint4 v = *reinterpret_cast<const uint4 *>(row);
+  NuRow r;
+  r.w[0] = v.x; r.w[1] = v.y; r.w[2] = v.z; r.w[3] = v.w;
+  return r;
+}
+// coefficient of species s (compile-time s after unrolling)
+__device__ __forceinline__ int nu_of(const NuRow &r, int s) {
+  return (int)((r.w[s >> 2] >> (8 * (s & 3))) & 0xffu);
+}
+
+// Rate q = kf prod C^nu_f - kb prod C^nu_b and, when dq != nullptr, dq/dC_t for
+// every species (branches are on the reaction's coefficients, uniform per wave).
+template <int S>
+__device__ __forceinline__ double mass_action(const NuRow &NF, const NuRow &NB, double kf, double kb,
+                                              const double *C, double *dq) {
+  double pf = kf, pb = kb;
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    const int ef = nu_of(NF, s), eb = nu_of(NB, s);
+    if (ef) pf *= ipow(C[s], ef);
+    if (eb) pb *= ipow(C[s], eb);
+  }
+  if (dq) {
+#pragma unroll
+    for (int t = 0; t < S; ++t) {
+      const int ft = nu_of(NF, t), bt = nu_of(NB, t);
+      double d = 0.0;
+      if (ft) {
+        double df = kf * ft * ipow(C[t], ft - 1);
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+          const int e = nu_of(NF, s);
+          if (s != t && e) df *= ipow(C[s], e);
+        }
+        d += df;
+      }
+      if (bt) {
+        double db = kb * bt * ipow(C[t], bt - 1);
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+          const int e = nu_of(NB, s);
+          if (s != t && e) db *= ipow(C[s], e);
+        }
+        d -= db;
+      }
+      dq[t] = d;
+    }
+  }
+  return pf - pb;
+}
+
 template <int M, int K>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1)))
 void k_chem(const ChemParams cp) {
   constexpr int S = M + K;      // all species (gas, vacancy, adsorbates)
   constexpr int U = S - 1;      // Newton unknowns
+  __shared__ double s_k[2 * LBM_RMAX][64];    // kf, kb of every reaction at this lane's node
+  const int lane = threadIdx.x;
   const int n = blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= cp.N) return;
+  if (n >= cp.N) return;        // no block barrier below: early exit is safe
   const int N = cp.N;
   const double T = cp.T[n];
   const double phi = cp.phi[n];
@@ -1076,6 +1136,10 @@ void k_chem(const ChemParams cp) {
   const double h = cp.dt / cp.n_sub;
   const double inv_RT = 1.0 / (cp.R_U * T);
   const ChemTables *__restrict__ tb = cp.tab;
+  for (int r = 0; r < cp.R; ++r) {
+    s_k[2 * r][lane] = tb->A_f[r] * exp(-tb->Ea_f[r] * inv_RT);
+    s_k[2 * r + 1][lane] = tb->A_b[r] * exp(-tb->Ea_b[r] * inv_RT);
+  }
   double c0[M], th0[K];
 #pragma unroll
   for (int a = 0; a < M; ++a) c0[a] = cp.rrho[(size_t)a * N + n] * cp.rho_unit / cp.m[a];
@@ -1103,53 +1167,21 @@ void k_chem(const ChemParams cp) {
         sth += y[M + k - 1];
       }
       C[M] = gam * (1.0 - sth);
-      // residual b = -(W (y - y0) - h s S q) and Jacobian W - h s S dq/dy
+      // Newton system divided row-wise by W (rows equilibrated):
+      //   J = I - h W^-1 s S dq/dy,  b = -((y - y0) - h W^-1 s S q)
       double J[U][U], b[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const double w = (u < M) ? phi : gam;
         const double yy0 = (u < M) ? c0[u] : th0[u - M + 1];
-        b[u] = -(w * (y[u] - yy0));
+        b[u] = -(y[u] - yy0);
 #pragma unroll
-        for (int v = 0; v < U; ++v) J[u][v] = (u == v) ? w : 0.0;
+        for (int v = 0; v < U; ++v) J[u][v] = (u == v) ? 1.0 : 0.0;
       }
+      const double hg = h * cp.a_s / phi, hs = h / gam;   // h s / W for gas and surface rows
       for (int r = 0; r < cp.R; ++r) {
-        const double kf = tb->A_f[r] * exp(-tb->Ea_f[r] * inv_RT);
-        const double kb = tb->A_b[r] * exp(-tb->Ea_b[r] * inv_RT);
-        double pf = kf, pb = kb;
-#pragma unroll
-        for (int s = 0; s < S; ++s) {
-          const int ef = tb->nu_f[r][s], eb = tb->nu_b[r][s];
-          if (ef) pf *= ipow(C[s], ef);
-          if (eb) pb *= ipow(C[s], eb);
-        }
-        const double q = pf - pb;
-        // d q / d C_s for every participating species
+        const NuRow NF = load_nu(tb->nu_f[r]), NB = load_nu(tb->nu_b[r]);
         double dq[S];
-#pragma unroll
-        for (int t = 0; t < S; ++t) {
-          const int ft = tb->nu_f[r][t], bt = tb->nu_b[r][t];
-          double d = 0.0;
-          if (ft) {
-            double df = kf * ft * ipow(C[t], ft - 1);
-#pragma unroll
-            for (int s = 0; s < S; ++s) {
-              const int e = tb->nu_f[r][s];
-              if (s != t && e) df *= ipow(C[s], e);
-            }
-            d += df;
-          }
-          if (bt) {
-            double db = kb * bt * ipow(C[t], bt - 1);
-#pragma unroll
-            for (int s = 0; s < S; ++s) {
-              const int e = tb->nu_b[r][s];
-              if (s != t && e) db *= ipow(C[s], e);
-            }
-            d -= db;
-          }
-          dq[t] = d;
-        }
+        const double q = mass_action<S>(NF, NB, s_k[2 * r][lane], s_k[2 * r + 1][lane], C, dq);
         // chain rule to the unknowns: dC_a/dy_a = 1, dC_s/dtheta_s = gamma, dC_V/dtheta_s = -gamma
         double dqu[U];
 #pragma unroll
@@ -1159,16 +1191,16 @@ void k_chem(const ChemParams cp) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           const int s = (u < M) ? u : u + 1;
-          const int st = tb->nu_b[r][s] - tb->nu_f[r][s];
+          const int st = nu_of(NB, s) - nu_of(NF, s);
           if (st) {
-            const double coef = h * ((u < M) ? cp.a_s : 1.0) * st;
+            const double coef = ((u < M) ? hg : hs) * st;
             b[u] += coef * q;
 #pragma unroll
             for (int v = 0; v < U; ++v) J[u][v] -= coef * dqu[v];
           }
         }
       }
-      // LU with partial pivoting (first maximum on ties), then substitution
+      // LU with partial pivoting on the equilibrated rows (first maximum on ties)
 #pragma unroll
       for (int k = 0; k < U; ++k) {
         int piv = k;
@@ -1225,19 +1257,11 @@ void k_chem(const ChemParams cp) {
 #pragma unroll
     for (int s = 0; s < S; ++s) dn[s] = 0.0;
     for (int r = 0; r < cp.R; ++r) {
-      const double kf = tb->A_f[r] * exp(-tb->Ea_f[r] * inv_RT);
-      const double kb = tb->A_b[r] * exp(-tb->Ea_b[r] * inv_RT);
-      double pf = kf, pb = kb;
+      const NuRow NF = load_nu(tb->nu_f[r]), NB = load_nu(tb->nu_b[r]);
+      const double dxi = h * mass_action<S>(NF, NB, s_k[2 * r][lane], s_k[2 * r + 1][lane], C, nullptr);
 #pragma unroll
       for (int s = 0; s < S; ++s) {
-        const int ef = tb->nu_f[r][s], eb = tb->nu_b[r][s];
-        if (ef) pf *= ipow(C[s], ef);
-        if (eb) pb *= ipow(C[s], eb);
-      }
-      const double dxi = h * (pf - pb);
-#pragma unroll
-      for (int s = 0; s < S; ++s) {
-        const int st = tb->nu_b[r][s] - tb->nu_f[r][s];
+        const int st = nu_of(NB, s) - nu_of(NF, s);
         if (st) dn[s] += st * dxi;
       }
     }
@@ -1486,12 +1510,13 @@ hipError_t launch_chem(const ChemParams &cp, hipStream_t s) {
     return hipGetLastError();
   }
   const unsigned nb = (unsigned)((cp.N + 63) / 64);
+  const dim3 bs(64);
   if (cp.M == 2 && cp.K == 2)
-    hipLaunchKernelGGL((k_chem<2, 2>), dim3(nb), dim3(64), 0, s, cp);
+    hipLaunchKernelGGL((k_chem<2, 2>), dim3(nb), bs, 0, s, cp);
   else if (cp.M == 3 && cp.K == 4)
-    hipLaunchKernelGGL((k_chem<3, 4>), dim3(nb), dim3(64), 0, s, cp);
+    hipLaunchKernelGGL((k_chem<3, 4>), dim3(nb), bs, 0, s, cp);
   else if (cp.M == 5 && cp.K == 10)
-    hipLaunchKernelGGL((k_chem<5, 10>), dim3(nb), dim3(64), 0, s, cp);
+    hipLaunchKernelGGL((k_chem<5, 10>), dim3(nb), bs, 0, s, cp);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
