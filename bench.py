@@ -36,7 +36,6 @@ def kernel_bytes_per_node(w, kernel):
     E = 1 if w.energy_on else 0
     if kernel == "species":
         rd = (M + 1 + E) * Q + 3                      # species + momentum (+ energy) pops, phi, kfac, T
-        rd += (M + D) if chem else 0                  # previous-step source and node velocity
         wr = M * Q + D + 1 + (D if w.pore_radius and np.isfinite(w.pore_radius) else 0)
         wr += (M + D) if chem else 0                  # chemistry input densities, node velocity
         wr += (1 + M + D) if E else 0
@@ -46,7 +45,9 @@ def kernel_bytes_per_node(w, kernel):
         wr = (1 + E) * Q
         return 8 * (rd + wr)
     if kernel == "chem":
-        return 8 * (M + 2 + K + K + M + 1)
+        return 8 * (M + 2 + K + K + M + 1)          # rho_a, T, phi, theta in/out, source, sum
+    if kernel == "source":
+        return 8 * (2 * M * Q + M + D + 1)         # species pops read + written, record, T
     raise ValueError(kernel)
 
 
@@ -62,6 +63,8 @@ def make_workload(name):
     from workloads import synth
     if name == "c3":
         return synth.config3()
+    if name == "c3_nochem":
+        return synth.config3(with_mech=False)
     if name == "c2":
         return synth.config2(kn_index=3)
     if name == "c5":
@@ -140,10 +143,11 @@ def main():
 
     ms_step = wall * 1e3 / args.steps
     mlups = w.N * args.steps / wall / 1e6
-    kernels = {"species": tk["species_ms"], "chem": tk["chem_ms"], "mixture": tk["mixture_ms"]}
+    kernels = {"species": tk["species_ms"], "chem": tk["chem_ms"], "source": tk["source_ms"],
+               "mixture": tk["mixture_ms"]}
     per_kernel = {}
     for k, ms in kernels.items():
-        if ms <= 0 or (k == "chem" and w.mech is None and w.faradaic_rate is None):
+        if ms <= 0 or (k in ("chem", "source") and w.mech is None and w.faradaic_rate is None):
             continue
         b = kernel_bytes_per_node(w, k) * w.N
         per_kernel[k] = {"ms": ms, "GBps": b / (ms * 1e-3) / 1e9}

@@ -171,14 +171,15 @@ typedef struct {
 int lbm_get_diagnostics(lbm_ctx *ctx, lbm_diag *out);
 
 /* Kernel time of the last lbm_step call's launches, measured with HIP events
- * on the configured stream: total ms and the per-kernel averages (species,
- * chemistry, mixture) in ms per launch.  Enabled with lbm_set_timing(ctx, 1). */
+ * on the configured stream: total ms of the call and, over its last <= 64
+ * steps, the per-step averages of the species kernel, the chemistry kernel,
+ * the source kernel and the mixture kernel.  Enabled with lbm_set_timing(ctx, 1). */
 int lbm_set_timing(lbm_ctx *ctx, int32_t enable);
 int lbm_get_timing(lbm_ctx *ctx, double *total_ms, double *species_ms, double *chem_ms,
-                   double *mixture_ms);
+                   double *source_ms, double *mixture_ms);
 
-/* Snapshot of the complete state (populations, pending source, records,
- * coverages, step counter): call with buf == NULL to query *size. */
+/* Snapshot of the complete state (populations, node records, coverages, step
+ * counter): call with buf == NULL to query *size. */
 int lbm_save(lbm_ctx *ctx, void *buf, size_t *size);
 int lbm_load(lbm_ctx *ctx, const void *buf, size_t size);
 

@@ -41,9 +41,8 @@ struct lbm_ctx {
   double *X0 = nullptr, *Plat = nullptr;
   int8_t *colflag = nullptr;
   double *rA = nullptr, *rRT = nullptr, *rFk = nullptr, *rrho = nullptr, *rY = nullptr, *rqd = nullptr;
-  double *v[2] = {nullptr, nullptr};
+  double *rec[2] = {nullptr, nullptr};   // node records: velocity + species source
   double *T[2] = {nullptr, nullptr};
-  double *src[2] = {nullptr, nullptr};
   double *srcsum = nullptr;
   double *theta = nullptr;
   double *faradaic = nullptr;
@@ -53,7 +52,6 @@ struct lbm_ctx {
   // state
   int cur = 0;
   int first_step = 1;
-  int has_src = 0;
   long long steps_done = 0;
   int knudsen = 0;
   double pore_radius = 0.0;
@@ -63,7 +61,7 @@ struct lbm_ctx {
   int K = 0;
   // timing
   int timing = 0;
-  hipEvent_t ev[kTimingRing][4];
+  hipEvent_t ev[kTimingRing][5];
   int ev_count = 0;
   int ev_ready = 0;
   double t_total_ms = 0.0;
@@ -175,9 +173,7 @@ void fill_prev(const lbm_ctx *c, KParams &p) {
   const int q_last = (int)((c->steps_done + 1) & 1);   // parity of the last completed step
   p.pin = c->pop[c->cur];
   p.first_step = c->first_step;
-  p.has_src = c->has_src;
-  p.v_prev = c->v[q_last];
-  p.src_prev = c->src[q_last];
+  p.rec_prev = c->rec[q_last];
   p.T_prev = c->energy ? c->T[q_last] : c->Tfield;
 }
 
@@ -203,7 +199,6 @@ int rebuild_populations(lbm_ctx *c) {
   HIPCHK(c, launch_init(c->dim, ip, c->stream));
   c->cur = 0;
   c->first_step = 1;
-  c->has_src = 0;
   c->steps_done = 0;
   return LBM_OK;
 }
@@ -315,8 +310,7 @@ int common_init(const lbm_config *cfg, int N, const double *X0, const double *P0
   const int D = c->dim;
   if ((rc = dalloc(c, &c->rA, (size_t)D * N)) || (rc = dalloc(c, &c->rRT, N)) ||
       (rc = dalloc(c, &c->rFk, (size_t)D * N)) || (rc = dalloc(c, &c->rrho, (size_t)c->M * N)) ||
-      (rc = dalloc(c, &c->v[0], (size_t)D * N)) || (rc = dalloc(c, &c->v[1], (size_t)D * N)) ||
-      (rc = dalloc(c, &c->src[0], (size_t)c->M * N)) || (rc = dalloc(c, &c->src[1], (size_t)c->M * N)) ||
+      (rc = dalloc(c, &c->rec[0], (size_t)kRec * N)) || (rc = dalloc(c, &c->rec[1], (size_t)kRec * N)) ||
       (rc = dalloc(c, &c->srcsum, N)))
     return rc;
   if (c->energy) {
@@ -329,15 +323,15 @@ int common_init(const lbm_config *cfg, int N, const double *X0, const double *P0
   c->diag_blocks = (N + 255) / 256;
   if ((rc = dalloc(c, &c->partials, (size_t)c->diag_blocks * (c->L + D + 2)))) return rc;
   // upload fields
-  std::vector<double> Plat(N), ones(N, 1.0), zeros((size_t)D * N, 0.0);
+  std::vector<double> Plat(N), ones(N, 1.0), zeros((size_t)kRec * N, 0.0);
   for (int n = 0; n < N; ++n) Plat[n] = (P0 ? P0[n] : c->P_ref) / c->P_ref;
   HIPCHK(c, hipMemcpy(c->X0, X0, sizeof(double) * c->M * N, hipMemcpyHostToDevice));
   HIPCHK(c, hipMemcpy(c->Plat, Plat.data(), sizeof(double) * N, hipMemcpyHostToDevice));
   HIPCHK(c, hipMemcpy(c->Tfield, T0, sizeof(double) * N, hipMemcpyHostToDevice));
   HIPCHK(c, hipMemcpy(c->phi, ones.data(), sizeof(double) * N, hipMemcpyHostToDevice));
   HIPCHK(c, hipMemcpy(c->kfac, zeros.data(), sizeof(double) * N, hipMemcpyHostToDevice));
-  HIPCHK(c, hipMemcpy(c->v[0], zeros.data(), sizeof(double) * D * N, hipMemcpyHostToDevice));
-  HIPCHK(c, hipMemcpy(c->v[1], zeros.data(), sizeof(double) * D * N, hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(c->rec[0], zeros.data(), sizeof(double) * kRec * N, hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(c->rec[1], zeros.data(), sizeof(double) * kRec * N, hipMemcpyHostToDevice));
   if (c->energy) {
     HIPCHK(c, hipMemcpy(c->T[0], T0, sizeof(double) * N, hipMemcpyHostToDevice));
     HIPCHK(c, hipMemcpy(c->T[1], T0, sizeof(double) * N, hipMemcpyHostToDevice));
@@ -356,13 +350,11 @@ int enqueue_step(lbm_ctx *c, int record_slot) {
   p.pin = c->pop[c->cur];
   p.pout = c->pop[1 - c->cur];
   p.first_step = c->first_step;
-  p.has_src = c->has_src;
   const int chem = c->has_mech || c->has_faradaic;
   p.chem = chem;
   p.need_v = needs_v(c) ? 1 : 0;
-  p.v_prev = c->v[1 - q];
-  p.v_cur = c->v[q];
-  p.src_prev = c->src[1 - q];
+  p.rec_prev = c->rec[1 - q];
+  p.rec_cur = c->rec[q];
   p.T_prev = c->energy ? c->T[1 - q] : c->Tfield;
   p.T_cur = c->energy ? c->T[q] : nullptr;
   p.srcsum_cur = c->srcsum;
@@ -380,7 +372,7 @@ int enqueue_step(lbm_ctx *c, int record_slot) {
     cp.phi = c->phi;
     cp.faradaic = c->has_faradaic ? c->faradaic : nullptr;
     cp.theta = c->theta;
-    cp.src = c->src[q];
+    cp.rec = c->rec[q];
     cp.srcsum = c->srcsum;
     cp.dt = c->dt;
     cp.rho_unit = c->rho_unit;
@@ -389,11 +381,12 @@ int enqueue_step(lbm_ctx *c, int record_slot) {
     HIPCHK(c, launch_chem(cp, c->stream));
   }
   if (ev) HIPCHK(c, hipEventRecord(ev[2], c->stream));
-  HIPCHK(c, launch_mixture(c->dim, p, c->stream));
+  if (chem) HIPCHK(c, launch_source(c->dim, p, c->stream));
   if (ev) HIPCHK(c, hipEventRecord(ev[3], c->stream));
+  HIPCHK(c, launch_mixture(c->dim, p, c->stream));
+  if (ev) HIPCHK(c, hipEventRecord(ev[4], c->stream));
   c->cur = 1 - c->cur;
   c->first_step = 0;
-  c->has_src = chem;
   c->steps_done += 1;
   return LBM_OK;
 }
@@ -644,13 +637,6 @@ int lbm_get_diagnostics(lbm_ctx *c, lbm_diag *out) {
   HIPCHK(c, launch_diag(c->L, c->dim, c->M, c->N, c->pop[c->cur], c->partials, c->diag_blocks, c->stream));
   std::vector<double> h((size_t)c->diag_blocks * W);
   HIPCHK(c, hipMemcpyAsync(h.data(), c->partials, sizeof(double) * h.size(), hipMemcpyDeviceToHost, c->stream));
-  std::vector<double> srch;
-  if (c->has_src) {
-    const int q_last = (int)((c->steps_done + 1) & 1);
-    srch.resize((size_t)c->M * c->N);
-    HIPCHK(c, hipMemcpyAsync(srch.data(), c->src[q_last], sizeof(double) * srch.size(), hipMemcpyDeviceToHost,
-                             c->stream));
-  }
   HIPCHK(c, hipStreamSynchronize(c->stream));
   double mn = INFINITY, bad = 0.0;
   for (int b = 0; b < c->diag_blocks; ++b) {
@@ -662,9 +648,6 @@ int lbm_get_diagnostics(lbm_ctx *c, lbm_diag *out) {
     mn = fmin(mn, r[c->L + c->dim]);
     bad += r[c->L + c->dim + 1];
   }
-  if (c->has_src)
-    for (int a = 0; a < c->M && a < 8; ++a)
-      for (int n = 0; n < c->N; ++n) out->species_mass[a] += srch[(size_t)a * c->N + n];
   out->min_population = mn;
   out->n_nonfinite = (int64_t)bad;
   out->steps_done = c->steps_done;
@@ -676,14 +659,14 @@ int lbm_set_timing(lbm_ctx *c, int32_t enable) {
   if (!c) return LBM_EINVAL;
   if (enable && !c->timing) {
     for (int s = 0; s < kTimingRing; ++s)
-      for (int k = 0; k < 4; ++k) HIPCHK(c, hipEventCreate(&c->ev[s][k]));
+      for (int k = 0; k < 5; ++k) HIPCHK(c, hipEventCreate(&c->ev[s][k]));
     HIPCHK(c, hipEventCreate(&c->ev_all[0]));
     HIPCHK(c, hipEventCreate(&c->ev_all[1]));
     c->timing = 1;
   } else if (!enable && c->timing) {
     HIPCHK(c, hipStreamSynchronize(c->stream));
     for (int s = 0; s < kTimingRing; ++s)
-      for (int k = 0; k < 4; ++k) (void)hipEventDestroy(c->ev[s][k]);
+      for (int k = 0; k < 5; ++k) (void)hipEventDestroy(c->ev[s][k]);
     (void)hipEventDestroy(c->ev_all[0]);
     (void)hipEventDestroy(c->ev_all[1]);
     c->timing = 0;
@@ -692,26 +675,25 @@ int lbm_set_timing(lbm_ctx *c, int32_t enable) {
   return LBM_OK;
 }
 
-int lbm_get_timing(lbm_ctx *c, double *total_ms, double *species_ms, double *chem_ms, double *mixture_ms) {
+int lbm_get_timing(lbm_ctx *c, double *total_ms, double *species_ms, double *chem_ms, double *source_ms,
+                   double *mixture_ms) {
   if (!c) return LBM_EINVAL;
   if (!c->timing || !c->ev_ready || c->ev_count == 0) return fail(c, LBM_ESTATE, "no timed step recorded");
   HIPCHK(c, hipEventSynchronize(c->ev_all[1]));
   float t = 0.f;
   HIPCHK(c, hipEventElapsedTime(&t, c->ev_all[0], c->ev_all[1]));
-  double s1 = 0, s2 = 0, s3 = 0;
-  for (int s = 0; s < c->ev_count; ++s) {
-    float a = 0, b = 0, d = 0;
-    HIPCHK(c, hipEventElapsedTime(&a, c->ev[s][0], c->ev[s][1]));
-    HIPCHK(c, hipEventElapsedTime(&b, c->ev[s][1], c->ev[s][2]));
-    HIPCHK(c, hipEventElapsedTime(&d, c->ev[s][2], c->ev[s][3]));
-    s1 += a;
-    s2 += b;
-    s3 += d;
-  }
+  double acc[4] = {0, 0, 0, 0};
+  for (int s = 0; s < c->ev_count; ++s)
+    for (int k = 0; k < 4; ++k) {
+      float e = 0;
+      HIPCHK(c, hipEventElapsedTime(&e, c->ev[s][k], c->ev[s][k + 1]));
+      acc[k] += e;
+    }
   if (total_ms) *total_ms = t;
-  if (species_ms) *species_ms = s1 / c->ev_count;
-  if (chem_ms) *chem_ms = s2 / c->ev_count;
-  if (mixture_ms) *mixture_ms = s3 / c->ev_count;
+  if (species_ms) *species_ms = acc[0] / c->ev_count;
+  if (chem_ms) *chem_ms = acc[1] / c->ev_count;
+  if (source_ms) *source_ms = acc[2] / c->ev_count;
+  if (mixture_ms) *mixture_ms = acc[3] / c->ev_count;
   return LBM_OK;
 }
 
@@ -719,7 +701,7 @@ namespace {
 struct SnapHeader {
   uint64_t magic, N, L, Q, M, K, D;
   int64_t steps_done;
-  int32_t first_step, has_src, pad0, pad1;
+  int32_t first_step, pad0, pad1, pad2;
 };
 constexpr uint64_t kMagic = 0x314d424c5844ull;
 }  // namespace
@@ -728,7 +710,7 @@ int lbm_save(lbm_ctx *c, void *buf, size_t *size) {
   if (!c || !size) return LBM_EINVAL;
   const size_t N = c->N, D = c->dim, M = c->M;
   const size_t npop = (size_t)c->L * c->Q * N;
-  const size_t nrec = D * N + M * N + (c->energy ? N : 0) + (c->has_mech ? (size_t)c->K * N : 0);
+  const size_t nrec = (size_t)kRec * N + (c->energy ? N : 0) + (c->has_mech ? (size_t)c->K * N : 0);
   const size_t need = sizeof(SnapHeader) + sizeof(double) * (npop + nrec);
   if (!buf) {
     *size = need;
@@ -736,17 +718,15 @@ int lbm_save(lbm_ctx *c, void *buf, size_t *size) {
   }
   if (*size < need) return fail(c, LBM_EINVAL, "snapshot buffer too small (%zu < %zu)", *size, need);
   SnapHeader h = {kMagic, N, (uint64_t)c->L, (uint64_t)c->Q, M, (uint64_t)c->K, D, c->steps_done,
-                  c->first_step, c->has_src, 0, 0};
+                  c->first_step, 0, 0, 0};
   memcpy(buf, &h, sizeof(h));
   double *o = (double *)((char *)buf + sizeof(h));
   const int q_last = (int)((c->steps_done + 1) & 1);
   HIPCHK(c, hipStreamSynchronize(c->stream));
   HIPCHK(c, hipMemcpy(o, c->pop[c->cur], sizeof(double) * npop, hipMemcpyDeviceToHost));
   o += npop;
-  HIPCHK(c, hipMemcpy(o, c->v[q_last], sizeof(double) * D * N, hipMemcpyDeviceToHost));
-  o += D * N;
-  HIPCHK(c, hipMemcpy(o, c->src[q_last], sizeof(double) * M * N, hipMemcpyDeviceToHost));
-  o += M * N;
+  HIPCHK(c, hipMemcpy(o, c->rec[q_last], sizeof(double) * kRec * N, hipMemcpyDeviceToHost));
+  o += (size_t)kRec * N;
   if (c->energy) {
     HIPCHK(c, hipMemcpy(o, c->T[q_last], sizeof(double) * N, hipMemcpyDeviceToHost));
     o += N;
@@ -765,21 +745,18 @@ int lbm_load(lbm_ctx *c, const void *buf, size_t size) {
       h.D != D || h.K != (uint64_t)c->K)
     return fail(c, LBM_EINVAL, "snapshot does not match this context");
   const size_t npop = (size_t)c->L * c->Q * N;
-  const size_t nrec = D * N + M * N + (c->energy ? N : 0) + (c->has_mech ? (size_t)c->K * N : 0);
+  const size_t nrec = (size_t)kRec * N + (c->energy ? N : 0) + (c->has_mech ? (size_t)c->K * N : 0);
   if (size < sizeof(SnapHeader) + sizeof(double) * (npop + nrec)) return fail(c, LBM_EINVAL, "snapshot truncated");
   c->steps_done = h.steps_done;
   c->first_step = h.first_step;
-  c->has_src = h.has_src;
   c->cur = 0;
   const int q_last = (int)((c->steps_done + 1) & 1);
   const double *o = (const double *)((const char *)buf + sizeof(h));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   HIPCHK(c, hipMemcpy(c->pop[0], o, sizeof(double) * npop, hipMemcpyHostToDevice));
   o += npop;
-  HIPCHK(c, hipMemcpy(c->v[q_last], o, sizeof(double) * D * N, hipMemcpyHostToDevice));
-  o += D * N;
-  HIPCHK(c, hipMemcpy(c->src[q_last], o, sizeof(double) * M * N, hipMemcpyHostToDevice));
-  o += M * N;
+  HIPCHK(c, hipMemcpy(c->rec[q_last], o, sizeof(double) * kRec * N, hipMemcpyHostToDevice));
+  o += (size_t)kRec * N;
   if (c->energy) {
     HIPCHK(c, hipMemcpy(c->T[q_last], o, sizeof(double) * N, hipMemcpyHostToDevice));
     o += N;
@@ -796,8 +773,7 @@ void lbm_destroy(lbm_ctx *c) {
   else (void)hipDeviceSynchronize();
   if (c->timing) lbm_set_timing(c, 0);
   double *bufs[] = {c->pop[0], c->pop[1], c->phi, c->kfac, c->Tfield, c->X0, c->Plat, c->rA, c->rRT, c->rFk,
-                    c->rrho, c->rY, c->rqd, c->v[0], c->v[1], c->T[0], c->T[1], c->src[0], c->src[1],
-                    c->srcsum, c->theta, c->faradaic, c->macro, c->partials};
+                    c->rrho, c->rY, c->rqd, c->rec[0], c->rec[1], c->T[0], c->T[1], c->srcsum, c->theta, c->faradaic, c->macro, c->partials};
   for (double *b : bufs) dfree(b);
   dfree(c->colflag);
   dfree(c->chem_tab);

@@ -11,6 +11,9 @@
 
 enum { BC_PERIODIC = 0, BC_BOUNCEBACK = 1, BC_INLET = 2, BC_OUTFLOW = 3 };
 
+constexpr int kRec = 8;     // doubles per node record (velocity + species source)
+constexpr int kRecSrc = 3;  // offset of the species source in a record
+
 // Equilibrium state of a prescribed inlet mixture (lattice units).
 struct InletState {
   double rho_a[LBM_MMAX];   // species densities X_a P / (R_a T)
@@ -25,7 +28,6 @@ struct KParams {
   int N, nx, ny, nz;
   int M, energy, bc_lo, bc_hi;
   int first_step;           // populations are stored post-stream: identity pull
-  int has_src;              // species source of the previous step still to be streamed
   int knudsen;              // Knudsen relaxation on
   int chem;                 // a chemistry source is computed this step
   int need_v;               // node velocities are needed by the next step
@@ -51,11 +53,11 @@ struct KParams {
   double *rrho;             // [M][N] species densities (chemistry input)
   double *rY;               // [M][N] mass fractions (energy lattice)
   double *rqd;              // [D][N] sum_a H_a Y_a (u_a - u_bar) (energy lattice)
-  // ping-pong records between consecutive steps
-  const double *v_prev;     // [D][N] v = u/phi of the previous step
+  // ping-pong node records between consecutive steps, kRec doubles per node:
+  //   [0..2] v = u/phi, [3..7] species source rho_dot_a dt (lattice units)
+  const double *rec_prev;   // written by the previous step
+  double *rec_cur;          // written by this step
   const double *T_prev;     // [N] temperature of the previous step (energy) or Tfield
-  const double *src_prev;   // [M][N] species source of the previous step (rho_dot dt, lattice)
-  double *v_cur;
   double *T_cur;            // energy only
   const double *srcsum_cur; // [N] sum_a source of this step (mixture mass source)
 };
@@ -79,7 +81,7 @@ struct ChemParams {
   const double *phi;        // [N]
   const double *faradaic;   // [N] mol m^-3 s^-1 or NULL
   double *theta;            // [K][N] in place
-  double *src;              // [M][N]
+  double *rec;              // node records of this step: source written at kRecSrc + a
   double *srcsum;           // [N]
 };
 
@@ -104,6 +106,7 @@ struct MomParams {
 hipError_t launch_init(int dim, const InitParams &ip, hipStream_t s);
 hipError_t launch_species(int dim, const KParams &p, hipStream_t s);
 hipError_t launch_mixture(int dim, const KParams &p, hipStream_t s);
+hipError_t launch_source(int dim, const KParams &p, hipStream_t s);
 hipError_t launch_chem(const ChemParams &cp, hipStream_t s);
 hipError_t launch_moments(int dim, const KParams &p, double *out, hipStream_t s);
 hipError_t launch_diag(int L, int D, int Mmom, int N, const double *pop, double *partials, int nblocks,

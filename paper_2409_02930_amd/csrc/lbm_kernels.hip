@@ -1,17 +1,18 @@
 // HIP kernels of the mean-field reactive porous-media lattice Boltzmann step (gfx950).
 //
-// One time step is three launches:
+// One time step is three to four launches:
 //   k_species  : pull-stream of every lattice, moments, composition, relaxation
 //                rates, the M x M species-momentum solve, the species collision
 //                (Section 2.3, eq finalNumericalEquationsReactive) and the small
-//                per-node records the next two kernels need;
+//                per-node records the next kernels need;
 //   k_chem     : the local surface-chemistry update (Section 4.2), only when a
 //                mechanism or a Faradaic source is installed;
+//   k_source   : adds that step's reaction populations to the post-collision
+//                species populations (eq fsourceHetero), only with chemistry;
 //   k_mixture  : momentum (eqs f_source, feqmix, Pex) and energy (eqs g_source,
 //                geq_i, gstar) collisions, which need gradients of node records.
-// The species source rho_dot_a dt of step t is added while the next step pulls
-// the species populations (same streaming path, same value), which keeps the
-// chemistry out of the bandwidth-bound species kernel.
+// Keeping the chemistry and its source out of k_species keeps that kernel a
+// pure bandwidth kernel.
 //
 // Populations are FP64 SoA [lattice][direction][node], one thread per node,
 // node index x-fastest so every direction is a coalesced (shifted) stream.
@@ -114,13 +115,6 @@ __device__ __forceinline__ bool get_node(const KParams &p, Node &nd) {
   return true;
 }
 
-struct Src {
-  int kind;   // 0: read stored population, 1: inlet at x-low, 2: inlet at x-high
-  int node;
-  int dir;
-};
-
-
 // Inlet state of side kind-1 without indexing the argument block per lane.
 struct InletSel {
   double rho, RT, U, rho_a, RaT;
@@ -143,46 +137,130 @@ __device__ __forceinline__ InletSel inlet_sel(const KParams &p, int kind, int la
   return r;
 }
 
-// Where the post-stream population of direction i at node nd comes from.
+// Source geometry of the pull at one node, computed once and shared by every
+// lattice: the wrapped source coordinate along x for c_x = -1, 0, +1, the
+// wrapped y-z row offset for every (c_y, c_z), and whether the node sits on a
+// non-periodic x end.  Packed columns use x = n and a zero row offset; the
+// first step (populations stored post-stream) uses zero shifts everywhere.
 template <int D>
-__device__ __forceinline__ Src pull_src(const KParams &p, const Node &nd, int i) {
-  Src s;
-  s.kind = 0;
-  s.dir = i;
-  if (p.first_step) {
-    s.node = nd.n;
-    return s;
+struct PullGeo {
+  int xs[3];        // source x for c_x = -1, 0, +1 (index c_x + 1)
+  int yz[3][3];     // nx * (y_src + ny * z_src) for (c_y + 1, c_z + 1)
+  int xself;        // x of the node itself (outflow copy source)
+  bool lo_wall, hi_wall;
+};
+
+template <int D>
+__device__ __forceinline__ PullGeo<D> pull_geo(const KParams &p, const Node &nd) {
+  PullGeo<D> g;
+  const bool first = p.first_step != 0;
+  g.lo_wall = !first && (nd.flag & 1) && p.bc_lo != BC_PERIODIC;
+  g.hi_wall = !first && (nd.flag & 2) && p.bc_hi != BC_PERIODIC;
+  const bool col = p.colflag != nullptr;
+  const int x = col ? nd.n : nd.x;
+  g.xself = x;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const int c = first ? 0 : k - 1;
+    int xs = x - c;
+    if (!col) { xs += (xs < 0) ? p.nx : 0; xs -= (xs >= p.nx) ? p.nx : 0; }
+    g.xs[k] = xs;
   }
+  int ys[3], zs[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const int c = first ? 0 : k - 1;
+    ys[k] = nd.y;
+    zs[k] = nd.z;
+    if (D > 1) { ys[k] -= c; ys[k] += (ys[k] < 0) ? p.ny : 0; ys[k] -= (ys[k] >= p.ny) ? p.ny : 0; }
+    if (D > 2) { zs[k] -= c; zs[k] += (zs[k] < 0) ? p.nz : 0; zs[k] -= (zs[k] >= p.nz) ? p.nz : 0; }
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) g.yz[a][b] = col ? 0 : p.nx * (ys[a] + p.ny * zs[b]);
+  return g;
+}
+
+// Stored population that streams into direction i: returns the source node and
+// sets the source direction.  Always an in-range address and free of branches:
+// periodic wrap, bounce-back (own node, opposite direction) and outflow (copy
+// of the same x, i.e. the zero-gradient extrapolation along x) are selects.
+// Inlet directions read the node's own slot here and are replaced by the inlet
+// equilibrium afterwards (inlet_kind).
+template <int D>
+__device__ __forceinline__ int pull_addr(const KParams &p, const Node &nd, const PullGeo<D> &g, int i,
+                                         int &dir) {
   const int cx = cdir(i, 0);
   const int cy = D > 1 ? cdir(i, 1) : 0;
   const int cz = D > 2 ? cdir(i, 2) : 0;
-  const bool lo_miss = (cx == 1) && (nd.flag & 1) && p.bc_lo != BC_PERIODIC;
-  const bool hi_miss = (cx == -1) && (nd.flag & 2) && p.bc_hi != BC_PERIODIC;
-  int ys = nd.y, zs = nd.z;
-  if (D > 1) { ys -= cy; ys += (ys < 0) ? p.ny : 0; ys -= (ys >= p.ny) ? p.ny : 0; }
-  if (D > 2) { zs -= cz; zs += (zs < 0) ? p.nz : 0; zs -= (zs >= p.nz) ? p.nz : 0; }
-  if (lo_miss || hi_miss) {
-    const int kind = lo_miss ? p.bc_lo : p.bc_hi;
-    if (kind == BC_BOUNCEBACK) {
-      s.node = nd.n;
-      s.dir = LQ<D>::Q - 1 - i;
-    } else if (kind == BC_OUTFLOW) {
-      s.node = p.colflag ? nd.n : nd.x + p.nx * (ys + p.ny * zs);
-    } else {
-      s.kind = lo_miss ? 1 : 2;
-      s.node = nd.n;
+  const bool miss = (cx == 1 && g.lo_wall) || (cx == -1 && g.hi_wall);
+  const int kind = cx == 1 ? p.bc_lo : p.bc_hi;
+  const int row = g.yz[cy + 1][cz + 1];
+  dir = (miss && kind == BC_BOUNCEBACK) ? LQ<D>::Q - 1 - i : i;
+  const int x = (miss && kind == BC_OUTFLOW) ? g.xself : g.xs[cx + 1];
+  return (miss && kind != BC_OUTFLOW) ? nd.n : x + row;
+}
+
+// 1 or 2 when direction i of nd enters through the inlet at x-low or x-high.
+template <int D>
+__device__ __forceinline__ int inlet_kind(const KParams &p, const Node &nd, int i) {
+  if (p.first_step) return 0;
+  const int cx = cdir(i, 0);
+  if (cx == 1 && (nd.flag & 1) && p.bc_lo == BC_INLET) return 1;
+  if (cx == -1 && (nd.flag & 2) && p.bc_hi == BC_INLET) return 2;
+  return 0;
+}
+
+// True when some direction of nd enters through an inlet.
+__device__ __forceinline__ bool is_inlet_node(const KParams &p, const Node &nd) {
+  return !p.first_step &&
+         (((nd.flag & 1) && p.bc_lo == BC_INLET) || ((nd.flag & 2) && p.bc_hi == BC_INLET));
+}
+
+// Equilibrium population of lattice `lat` entering direction i through the
+// inlet of side kind (eq 27eq for species, eq feqmix for the momentum lattice,
+// eq geq_i for the energy lattice) at the node velocity vb.
+template <int D, int M>
+__device__ __forceinline__ double inlet_population(const KParams &p, int kind, int lat, int i,
+                                                   double phi, const double *vb) {
+  const InletSel in = inlet_sel(p, kind, lat);
+  double P[D];
+  if (lat < M) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) P[d] = vb[d] * vb[d] + in.RaT;
+    return phi * in.rho_a * psi_dir<D>(i, vb, P);
+  }
+  if (lat == M) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) P[d] = in.RT + vb[d] * vb[d];
+    return phi * in.rho * psi_dir<D>(i, vb, P);
+  }
+  return geq_dir<D>(i, phi * in.rho, in.U, in.RT, vb);
+}
+
+// Post-stream populations of lattice `lat` at node nd (pull scheme).  All Q
+// loads are issued unconditionally; the inlet fix-up runs on inlet nodes only.
+template <int D, int M>
+__device__ __forceinline__ void pull_lattice(const KParams &p, const Node &nd, const PullGeo<D> &g,
+                                             int lat, double phi, const double *vb, bool inlet_node,
+                                             double *f) {
+  constexpr int Q = LQ<D>::Q;
+  const int N = p.N;
+  const double *base = p.pin + (size_t)lat * Q * N;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    int dir;
+    const int src = pull_addr<D>(p, nd, g, i, dir);
+    f[i] = base[(size_t)dir * N + src];
+  }
+  if (inlet_node) {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const int kind = inlet_kind<D>(p, nd, i);
+      if (kind) f[i] = inlet_population<D, M>(p, kind, lat, i, phi, vb);
     }
-    return s;
   }
-  if (p.colflag) {
-    s.node = nd.n - cx;
-  } else {
-    int xs = nd.x - cx;
-    xs += (xs < 0) ? p.nx : 0;
-    xs -= (xs >= p.nx) ? p.nx : 0;
-    s.node = xs + p.nx * (ys + p.ny * zs);
-  }
-  return s;
 }
 
 // Node at x + c for the gradient stencil: periodic wrap, mirror ghost (the node
@@ -227,31 +305,24 @@ __device__ __forceinline__ void species_front(const KParams &p, const Node &nd, 
   const int n = nd.n;
   // velocity of this node at the previous step (inlet equilibria)
   double vb[D];
-  const bool inlet_node = !p.first_step &&
-      (((nd.flag & 1) && p.bc_lo == BC_INLET) || ((nd.flag & 2) && p.bc_hi == BC_INLET));
+  const bool inlet_node = is_inlet_node(p, nd);
 #pragma unroll
-  for (int d = 0; d < D; ++d) vb[d] = inlet_node ? p.v_prev[(size_t)d * N + n] : 0.0;
+  for (int d = 0; d < D; ++d) vb[d] = inlet_node ? p.rec_prev[(size_t)n * kRec + d] : 0.0;
+  const PullGeo<D> geo = pull_geo<D>(p, nd);
 
   // ---- momentum lattice: sum f = phi rho (eq fdensity), sum f c = rho u
   double sf = 0.0, jf[D];
 #pragma unroll
   for (int d = 0; d < D; ++d) jf[d] = 0.0;
+  {
+    double fm[Q];
+    pull_lattice<D, M>(p, nd, geo, M, phi, vb, inlet_node, fm);
 #pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    const Src s = pull_src<D>(p, nd, i);
-    double val;
-    if (s.kind == 0) {
-      val = p.pin[(size_t)(M * Q + s.dir) * N + s.node];
-    } else {
-      const InletSel in = inlet_sel(p, s.kind, -1);
-      double P[D];
+    for (int i = 0; i < Q; ++i) {
+      sf += fm[i];
 #pragma unroll
-      for (int d = 0; d < D; ++d) P[d] = in.RT + vb[d] * vb[d];
-      val = phi * in.rho * psi_dir<D>(i, vb, P);
+      for (int d = 0; d < D; ++d) jf[d] += cdir(i, d) * fm[i];
     }
-    sf += val;
-#pragma unroll
-    for (int d = 0; d < D; ++d) jf[d] += cdir(i, d) * val;
   }
   S.rho = sf / phi;
 #pragma unroll
@@ -262,56 +333,16 @@ __device__ __forceinline__ void species_front(const KParams &p, const Node &nd, 
   // ---- energy lattice zeroth moment (eq g0momTotalEnergy)
   S.sumg = 0.0;
   if (ENERGY) {
+    double g[Q];
+    pull_lattice<D, M>(p, nd, geo, M + 1, phi, vb, inlet_node, g);
     double sg = 0.0;
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      const Src s = pull_src<D>(p, nd, i);
-      double val;
-      if (s.kind == 0) {
-        val = p.pin[(size_t)((M + 1) * Q + s.dir) * N + s.node];
-      } else {
-        const InletSel in = inlet_sel(p, s.kind, -1);
-        val = geq_dir<D>(i, phi * in.rho, in.U, in.RT, vb);
-      }
-      sg += val;
-    }
+    for (int i = 0; i < Q; ++i) sg += g[i];
     S.sumg = sg;
   }
-  // ---- species lattices (+ the source of the previous step, streamed along)
+  // ---- species lattices
 #pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    const Src s = pull_src<D>(p, nd, i);
-    if (s.kind == 0) {
-      double vs[D], Ts = 0.0;
-      if (p.has_src) {
-#pragma unroll
-        for (int d = 0; d < D; ++d) vs[d] = p.v_prev[(size_t)d * N + s.node];
-        Ts = p.T_prev[s.node];
-      }
-#pragma unroll
-      for (int a = 0; a < M; ++a) {
-        double val = p.pin[(size_t)(a * Q + s.dir) * N + s.node];
-        if (p.has_src) {
-          const double sa = p.src_prev[(size_t)a * N + s.node];
-          const double RaTs = p.theta_ref * p.mmin_over_m[a] * (Ts * p.inv_T_ref);
-          double P[D];
-#pragma unroll
-          for (int d = 0; d < D; ++d) P[d] = vs[d] * vs[d] + RaTs;
-          val += sa * psi_dir<D>(s.dir, vs, P);     // eq fsourceHetero
-        }
-        S.f[a][i] = val;
-      }
-    } else {
-#pragma unroll
-      for (int a = 0; a < M; ++a) {
-        const InletSel in = inlet_sel(p, s.kind, a);
-        double P[D];
-#pragma unroll
-        for (int d = 0; d < D; ++d) P[d] = vb[d] * vb[d] + in.RaT;
-        S.f[a][i] = phi * in.rho_a * psi_dir<D>(i, vb, P);
-      }
-    }
-  }
+  for (int a = 0; a < M; ++a) pull_lattice<D, M>(p, nd, geo, a, phi, vb, inlet_node, S.f[a]);
   // ---- species moments (eqs density1, momentum1)
 #pragma unroll
   for (int a = 0; a < M; ++a) {
@@ -461,53 +492,6 @@ struct SpeciesShared {
   double itk[M][64];          // 1 / tau^k_a
 };
 
-// Pull lattice `lat` at one node (phase 1 of k_species).
-template <int D, int M>
-__device__ __forceinline__ void pull_lattice(const KParams &p, const Node &nd, int lat, double phi,
-                                             const double *vb, double *f) {
-  constexpr int Q = LQ<D>::Q;
-  const int N = p.N;
-  const bool is_species = lat < M;
-  double mm_lat = 0.0;                 // m_min / m_lat, selected without indexing the argument block
-#pragma unroll
-  for (int a = 0; a < M; ++a)
-    if (a == lat) mm_lat = p.mmin_over_m[a];
-#pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    const Src s = pull_src<D>(p, nd, i);
-    double val;
-    if (s.kind == 0) {
-      val = p.pin[(size_t)(lat * Q + s.dir) * N + s.node];
-      if (is_species && p.has_src) {
-        const double sa = p.src_prev[(size_t)lat * N + s.node];
-        double vs[D];
-#pragma unroll
-        for (int d = 0; d < D; ++d) vs[d] = p.v_prev[(size_t)d * N + s.node];
-        const double RaTs = p.theta_ref * mm_lat * (p.T_prev[s.node] * p.inv_T_ref);
-        double P[D];
-#pragma unroll
-        for (int d = 0; d < D; ++d) P[d] = vs[d] * vs[d] + RaTs;
-        val += sa * psi_dir<D>(s.dir, vs, P);     // eq fsourceHetero, streamed with its population
-      }
-    } else {
-      const InletSel in = inlet_sel(p, s.kind, lat);
-      double P[D];
-      if (is_species) {
-#pragma unroll
-        for (int d = 0; d < D; ++d) P[d] = vb[d] * vb[d] + in.RaT;
-        val = phi * in.rho_a * psi_dir<D>(i, vb, P);
-      } else if (lat == M) {
-#pragma unroll
-        for (int d = 0; d < D; ++d) P[d] = in.RT + vb[d] * vb[d];
-        val = phi * in.rho * psi_dir<D>(i, vb, P);
-      } else {
-        val = geq_dir<D>(i, phi * in.rho, in.U, in.RT, vb);
-      }
-    }
-    f[i] = val;
-  }
-}
-
 template <int D, int M, bool ENERGY>
 __global__ __launch_bounds__(64 * (M + 1 + (ENERGY ? 1 : 0))) void k_species(const KParams p) {
   constexpr int Q = LQ<D>::Q;
@@ -530,6 +514,8 @@ __global__ __launch_bounds__(64 * (M + 1 + (ENERGY ? 1 : 0))) void k_species(con
   double vb[D];
 #pragma unroll
   for (int d = 0; d < D; ++d) vb[d] = 0.0;
+  bool inlet_node = false;
+  PullGeo<D> geo = {};
   if (valid) {
     if (p.colflag) {
       nd.flag = p.colflag[n];
@@ -541,11 +527,11 @@ __global__ __launch_bounds__(64 * (M + 1 + (ENERGY ? 1 : 0))) void k_species(con
       nd.flag = (nd.x == 0 ? 1 : 0) | (nd.x == p.nx - 1 ? 2 : 0);
     }
     phi = p.phi[n];
-    const bool inlet_node = !p.first_step &&
-        (((nd.flag & 1) && p.bc_lo == BC_INLET) || ((nd.flag & 2) && p.bc_hi == BC_INLET));
+    inlet_node = is_inlet_node(p, nd);
+    geo = pull_geo<D>(p, nd);
     if (inlet_node) {
 #pragma unroll
-      for (int d = 0; d < D; ++d) vb[d] = p.v_prev[(size_t)d * N + n];
+      for (int d = 0; d < D; ++d) vb[d] = p.rec_prev[(size_t)n * kRec + d];
     }
   }
 
@@ -554,7 +540,7 @@ __global__ __launch_bounds__(64 * (M + 1 + (ENERGY ? 1 : 0))) void k_species(con
     const int a = w;
     double f[Q];
     if (valid) {
-      pull_lattice<D, M>(p, nd, a, phi, vb, f);
+      pull_lattice<D, M>(p, nd, geo, a, phi, vb, inlet_node, f);
       double s0 = 0.0, s1[D];
 #pragma unroll
       for (int d = 0; d < D; ++d) s1[d] = 0.0;
@@ -634,7 +620,7 @@ __global__ __launch_bounds__(64 * (M + 1 + (ENERGY ? 1 : 0))) void k_species(con
     // ================= momentum wave: moments, then the per-node solve =================
     if (valid) {
       double f[Q];
-      pull_lattice<D, M>(p, nd, M, phi, vb, f);
+      pull_lattice<D, M>(p, nd, geo, M, phi, vb, inlet_node, f);
       double s0 = 0.0, s1[D];
 #pragma unroll
       for (int d = 0; d < D; ++d) s1[d] = 0.0;
@@ -760,7 +746,7 @@ __global__ __launch_bounds__(64 * (M + 1 + (ENERGY ? 1 : 0))) void k_species(con
         for (int c = 0; c < M; ++c) fk -= x[c][d] * itk[c];              // eq netKnudsenForce
         p.rA[(size_t)d * N + n] = rho * u[d] * (1.0 - 3.0 * RT) - rho * u[d] * u[d] * u[d] / (phi * phi);
         if (p.knudsen) p.rFk[(size_t)d * N + n] = fk;
-        if (p.need_v) p.v_cur[(size_t)d * N + n] = v[d];
+        if (p.need_v) p.rec_cur[(size_t)n * kRec + d] = v[d];
       }
       p.rRT[n] = RT;
       if (p.chem) {
@@ -788,11 +774,11 @@ __global__ __launch_bounds__(64 * (M + 1 + (ENERGY ? 1 : 0))) void k_species(con
       }
     }
     __syncthreads();
-  } else {
+  } else if constexpr (ENERGY) {
     // ================= energy wave: zeroth moment of g =================
     if (valid) {
       double f[Q];
-      pull_lattice<D, M>(p, nd, M + 1, phi, vb, f);
+      pull_lattice<D, M>(p, nd, geo, M + 1, phi, vb, inlet_node, f);
       double s0 = 0.0;
 #pragma unroll
       for (int i = 0; i < Q; ++i) s0 += f[i];
@@ -800,6 +786,46 @@ __global__ __launch_bounds__(64 * (M + 1 + (ENERGY ? 1 : 0))) void k_species(con
     }
     __syncthreads();
     __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// k_source: adds the reaction population of this step to the post-collision
+// species populations at their own node (eq fsourceHetero):
+//   f'_ai += rho_dot_a dt prod_d Psi_{c_id}(v_d, v_d^2 + R_a T).
+// The populations then stream with their source, as the paper writes it.
+// ---------------------------------------------------------------------------
+template <int D, int M>
+__global__ __launch_bounds__(256) void k_source(const KParams p) {
+  constexpr int Q = LQ<D>::Q;
+  Node nd;
+  if (!get_node(p, nd)) return;
+  const int N = p.N;
+  const int n = nd.n;
+  double v[D];
+#pragma unroll
+  for (int d = 0; d < D; ++d) v[d] = p.rec_cur[(size_t)n * kRec + d];
+  const double Tn = p.energy ? p.T_cur[n] : p.Tfield[n];
+#pragma unroll
+  for (int a = 0; a < M; ++a) {
+    const double sa = p.rec_cur[(size_t)n * kRec + kRecSrc + a];
+    const double RaT = p.theta_ref * p.mmin_over_m[a] * (Tn * p.inv_T_ref);
+    double t[D][3];
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      const double P = v[d] * v[d] + RaT;
+      t[d][0] = 0.5 * (-v[d] + P);
+      t[d][1] = 1.0 - P;
+      t[d][2] = 0.5 * (v[d] + P);
+    }
+    double *f = p.pout + (size_t)(a * Q) * N + n;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      double psi = t[0][i % 3];
+      if (D > 1) psi *= t[1][(i / 3) % 3];
+      if (D > 2) psi *= t[2][i / 9];
+      f[(size_t)i * N] += sa * psi;
+    }
   }
 }
 
@@ -815,32 +841,21 @@ __global__ __launch_bounds__(256) void k_mixture(const KParams p) {
   const int n = nd.n;
   const double phi = p.phi[n];
   double vb[D];
-  const bool inlet_node = !p.first_step &&
-      (((nd.flag & 1) && p.bc_lo == BC_INLET) || ((nd.flag & 2) && p.bc_hi == BC_INLET));
+  const bool inlet_node = is_inlet_node(p, nd);
 #pragma unroll
-  for (int d = 0; d < D; ++d) vb[d] = inlet_node ? p.v_prev[(size_t)d * N + n] : 0.0;
+  for (int d = 0; d < D; ++d) vb[d] = inlet_node ? p.rec_prev[(size_t)n * kRec + d] : 0.0;
+  const PullGeo<D> geo = pull_geo<D>(p, nd);
 
   double f[Q];
+  pull_lattice<D, M>(p, nd, geo, M, phi, vb, inlet_node, f);
   double sf = 0.0, jf[D];
 #pragma unroll
   for (int d = 0; d < D; ++d) jf[d] = 0.0;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    const Src s = pull_src<D>(p, nd, i);
-    double val;
-    if (s.kind == 0) {
-      val = p.pin[(size_t)(M * Q + s.dir) * N + s.node];
-    } else {
-      const InletSel in = inlet_sel(p, s.kind, -1);
-      double P[D];
+    sf += f[i];
 #pragma unroll
-      for (int d = 0; d < D; ++d) P[d] = in.RT + vb[d] * vb[d];
-      val = phi * in.rho * psi_dir<D>(i, vb, P);
-    }
-    f[i] = val;
-    sf += val;
-#pragma unroll
-    for (int d = 0; d < D; ++d) jf[d] += cdir(i, d) * val;
+    for (int d = 0; d < D; ++d) jf[d] += cdir(i, d) * f[i];
   }
   const double rho = sf / phi;
   double u[D], v[D];
@@ -932,19 +947,11 @@ __global__ __launch_bounds__(256) void k_mixture(const KParams p) {
     double g[Q], q[D];
 #pragma unroll
     for (int d = 0; d < D; ++d) q[d] = 0.0;
+    pull_lattice<D, M>(p, nd, geo, M + 1, phi, vb, inlet_node, g);
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-      const Src s = pull_src<D>(p, nd, i);
-      double val;
-      if (s.kind == 0) {
-        val = p.pin[(size_t)((M + 1) * Q + s.dir) * N + s.node];
-      } else {
-        const InletSel in = inlet_sel(p, s.kind, -1);
-        val = geq_dir<D>(i, phi * in.rho, in.U, in.RT, vb);
-      }
-      g[i] = val;
 #pragma unroll
-      for (int d = 0; d < D; ++d) q[d] += cdir(i, d) * val;
+      for (int d = 0; d < D; ++d) q[d] += cdir(i, d) * g[i];
     }
     // Q_a = (omega - omega1) (q* - q^eq), expanded (eqs gstareq1mom, interdiffusion,
     //       corrFourier, qex; natural bulk viscosity)
@@ -1285,7 +1292,7 @@ void k_chem(const ChemParams cp) {
   double ssum = 0.0;
 #pragma unroll
   for (int a = 0; a < M; ++a) {
-    cp.src[(size_t)a * N + n] = src[a];
+    cp.rec[(size_t)n * kRec + kRecSrc + a] = src[a];
     ssum += src[a];
   }
   cp.srcsum[n] = ssum;
@@ -1306,7 +1313,7 @@ __global__ __launch_bounds__(256) void k_faradaic(const ChemParams cp) {
     double s = 0.0;
     if (a == cp.fuel) s -= r * cp.m[a] / cp.rho_unit;
     if (a == cp.product) s += r * cp.m[a] / cp.rho_unit;
-    cp.src[(size_t)a * N + n] = s;
+    cp.rec[(size_t)n * kRec + kRecSrc + a] = s;
     ssum += s;
   }
   cp.srcsum[n] = ssum;
@@ -1443,6 +1450,19 @@ hipError_t moments_dispatch(const KParams &p, double *out, hipStream_t s) {
 }
 
 template <int D>
+hipError_t source_dispatch(const KParams &p, hipStream_t s) {
+  const unsigned nb = padded_blocks(p.N, 256);
+  switch (p.M) {
+    case 2: hipLaunchKernelGGL((k_source<D, 2>), dim3(nb), dim3(256), 0, s, p); break;
+    case 3: hipLaunchKernelGGL((k_source<D, 3>), dim3(nb), dim3(256), 0, s, p); break;
+    case 4: hipLaunchKernelGGL((k_source<D, 4>), dim3(nb), dim3(256), 0, s, p); break;
+    case 5: hipLaunchKernelGGL((k_source<D, 5>), dim3(nb), dim3(256), 0, s, p); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <int D>
 hipError_t init_dispatch(const InitParams &ip, hipStream_t s) {
   const unsigned nb = (unsigned)((ip.N + 255) / 256);
   switch (ip.M) {
@@ -1471,6 +1491,15 @@ hipError_t launch_species(int dim, const KParams &p, hipStream_t s) {
     case 1: return species_dispatch<1>(p, s);
     case 2: return species_dispatch<2>(p, s);
     case 3: return species_dispatch<3>(p, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_source(int dim, const KParams &p, hipStream_t s) {
+  switch (dim) {
+    case 1: return source_dispatch<1>(p, s);
+    case 2: return source_dispatch<2>(p, s);
+    case 3: return source_dispatch<3>(p, s);
   }
   return hipErrorInvalidValue;
 }
