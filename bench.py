@@ -113,6 +113,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--chem-kernel", choices=["specialized", "generic"], default="specialized",
+                    help="mechanism-specialised (default) or generic chemistry kernel")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run a plain 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -123,10 +127,20 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     from paper_2409_02930_amd import lbm
 
+    if args.copy_calibration:
+        nbytes = 1 << 30
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: 3 copies of {nbytes} bytes")
+        del src, dst
     log(f"building workload {args.workload}")
     w = make_workload(args.workload)
     stream = torch.cuda.current_stream()
     lat = lbm.lattice_from_workload(w, stream=stream.cuda_stream)
+    lat.set_chem_kernel(lbm.CHEM_SPECIALIZED if args.chem_kernel == "specialized" else lbm.CHEM_GENERIC)
     log(f"lattice ready N={w.N}; warmup {args.warmup}")
     lat.step(args.warmup)
     torch.cuda.synchronize()
@@ -170,6 +184,7 @@ def main():
         "config": {"workload": f"{w.name} {w.nx}x{w.ny}x{w.nz} D{w.lattice}Q{3 ** w.lattice} M={w.M}"
                                + (f" K={w.mech.K} R={w.mech.R} n_sub={w.mech.n_sub} n_newton={w.mech.n_newton}"
                                   if w.mech is not None else "")
+                               + (f" chem={args.chem_kernel}" if w.mech is not None else "")
                                + (" energy" if w.energy_on else ""),
                    "nodes": w.N, "parallelism": "single GPU"},
         "kernels_ms": per_kernel,

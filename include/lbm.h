@@ -140,6 +140,21 @@ int lbm_set_porous_field(lbm_ctx *ctx, const double *phi, const double *tort, do
  * theta0.  Only valid before the first lbm_step. */
 int lbm_set_mechanism(lbm_ctx *ctx, const lbm_mechanism *mech);
 
+/* Chemistry kernel used for an installed mechanism.  LBM_CHEM_SPECIALIZED
+ * (default): the first step runs the generic kernel; before the second step
+ * the library generates a kernel with the mechanism's stoichiometry and
+ * Arrhenius constants written in and compiles it for gfx950 with hiprtc (once
+ * per mechanism and process; a failed compilation makes that lbm_step return
+ * LBM_EHIP).  It solves each Newton system with a sparse LU in an elimination
+ * order chosen on Newton matrices sampled from the state after the first step,
+ * and falls back, per node, to a dense LU with partial pivoting wherever
+ * partial pivoting would exchange rows.  LBM_CHEM_GENERIC runs the precompiled
+ * kernel that reads the mechanism from device tables (dense LU with partial
+ * pivoting) on every step.  Both compute the backward-Euler update of
+ * Section 4; they agree to rounding. */
+enum { LBM_CHEM_SPECIALIZED = 0, LBM_CHEM_GENERIC = 1 };
+int lbm_set_chem_kernel(lbm_ctx *ctx, int32_t kind);
+
 /* Prescribed volumetric Faradaic source rate [N] (mol m^-3 s^-1) that consumes
  * species `fuel` and produces species `product` (explicit, added to the
  * chemistry source; NULL removes it).  Only valid before the first lbm_step. */

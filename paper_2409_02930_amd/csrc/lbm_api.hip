@@ -11,6 +11,8 @@
 #include "lbm.h"
 #include "lbm_internal.h"
 
+#include <cmath>
+
 namespace {
 
 constexpr double kRU = 8.314462618;      // J/(mol K)
@@ -58,6 +60,11 @@ struct lbm_ctx {
   int has_mech = 0, has_faradaic = 0;
   ChemParams chem;
   ChemTables *chem_tab = nullptr;
+  ChemTables chem_host;                 // host copy of the installed mechanism
+  int chem_kernel = LBM_CHEM_SPECIALIZED;
+  hipFunction_t chem_fn = nullptr;      // specialised kernel of the installed mechanism
+  int chem_perm[16] = {};               // its elimination order (kept in snapshots)
+  int have_perm = 0;
   int K = 0;
   // timing
   int timing = 0;
@@ -344,6 +351,78 @@ int common_init(const lbm_config *cfg, int N, const double *X0, const double *P0
   return LBM_OK;
 }
 
+int sample_order(lbm_ctx *c, ChemSpec &sp);
+
+// Builds the mechanism-specialised chemistry kernel.  The elimination order is
+// chosen on Newton matrices sampled (up to 64 nodes spread over the grid) from
+// the chemistry input and coverages of the last step, so it is called after a
+// first step has run with the generic kernel; compilation happens once per
+// mechanism and process.
+int specialize_chemistry(lbm_ctx *c) {
+  const int M = c->M, K = c->K, S = M + K;
+  const ChemParams &cp = c->chem;
+  ChemSpec sp;
+  memset(&sp, 0, sizeof(sp));
+  sp.M = M;
+  sp.K = K;
+  sp.R = cp.R;
+  sp.n_sub = cp.n_sub;
+  sp.n_newton = cp.n_newton;
+  for (int r = 0; r < cp.R; ++r) {
+    for (int t = 0; t < S; ++t) {
+      sp.nu_f[r][t] = c->chem_host.nu_f[r][t];
+      sp.nu_b[r][t] = c->chem_host.nu_b[r][t];
+    }
+    sp.A_f[r] = c->chem_host.A_f[r];
+    sp.Ea_f[r] = c->chem_host.Ea_f[r];
+    sp.A_b[r] = c->chem_host.A_b[r];
+    sp.Ea_b[r] = c->chem_host.Ea_b[r];
+  }
+  for (int a = 0; a < M; ++a) sp.m[a] = c->m[a];
+  sp.R_U = kRU;
+  if (c->have_perm) {
+    memcpy(sp.perm, c->chem_perm, sizeof(sp.perm));
+  } else {
+    const int rc = sample_order(c, sp);
+    if (rc) return rc;
+  }
+  std::string log;
+  const hipError_t e = chem_specialize(sp, &c->chem_fn, &log);
+  if (e != hipSuccess) {
+    c->chem_fn = nullptr;
+    return fail(c, LBM_EHIP, "specialised chemistry kernel: %s (%s)", hipGetErrorString(e), log.c_str());
+  }
+  memcpy(c->chem_perm, sp.perm, sizeof(sp.perm));
+  c->have_perm = 1;
+  return LBM_OK;
+}
+
+// Elimination order from Newton matrices at up to 64 sampled nodes.
+int sample_order(lbm_ctx *c, ChemSpec &sp) {
+  const int M = c->M, K = c->K, S = M + K, N = c->N;
+  const ChemParams &cp = c->chem;
+  const int ns = N < 64 ? N : 64;
+  std::vector<double> T(ns), phi(ns), C((size_t)ns * S);
+  const double *Tsrc = c->energy ? c->T[(c->steps_done + 1) & 1] : c->Tfield;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (int j = 0; j < ns; ++j) {
+    const size_t n = (size_t)j * N / ns;
+    double x;
+    HIPCHK(c, hipMemcpy(&T[j], Tsrc + n, sizeof(double), hipMemcpyDeviceToHost));
+    HIPCHK(c, hipMemcpy(&phi[j], c->phi + n, sizeof(double), hipMemcpyDeviceToHost));
+    for (int a = 0; a < M; ++a) {
+      HIPCHK(c, hipMemcpy(&x, c->rrho + (size_t)a * N + n, sizeof(double), hipMemcpyDeviceToHost));
+      C[(size_t)j * S + a] = x * c->rho_unit / c->m[a];
+    }
+    for (int k = 0; k < K; ++k) {
+      HIPCHK(c, hipMemcpy(&x, c->theta + (size_t)k * N + n, sizeof(double), hipMemcpyDeviceToHost));
+      C[(size_t)j * S + M + k] = cp.gamma * x;
+    }
+  }
+  chem_choose_order(sp, ns, T.data(), phi.data(), C.data(), c->dt / cp.n_sub, cp.a_s, cp.gamma);
+  return LBM_OK;
+}
+
 int enqueue_step(lbm_ctx *c, int record_slot) {
   const int q = (int)(c->steps_done & 1);
   KParams p = base_params(c);
@@ -378,7 +457,10 @@ int enqueue_step(lbm_ctx *c, int record_slot) {
     cp.rho_unit = c->rho_unit;
     cp.R_U = kRU;
     for (int a = 0; a < c->M; ++a) cp.m[a] = c->m[a];
-    HIPCHK(c, launch_chem(cp, c->stream));
+    if (c->chem_fn)
+      HIPCHK(c, launch_chem_specialized(c->chem_fn, cp, c->stream));
+    else
+      HIPCHK(c, launch_chem(cp, c->stream));
   }
   if (ev) HIPCHK(c, hipEventRecord(ev[2], c->stream));
   if (chem) HIPCHK(c, launch_source(c->dim, p, c->stream));
@@ -507,6 +589,9 @@ int lbm_set_mechanism(lbm_ctx *c, const lbm_mechanism *mech) {
       }
     }
     if (site_f != site_b) return fail(c, LBM_EINVAL, "reaction %d is not site-balanced", r);
+    if (!std::isfinite(mech->A_f[r]) || !std::isfinite(mech->A_b[r]) || !std::isfinite(mech->Ea_f[r]) ||
+        !std::isfinite(mech->Ea_b[r]) || mech->A_f[r] < 0 || mech->A_b[r] < 0)
+      return fail(c, LBM_EINVAL, "reaction %d: pre-factors must be finite and >= 0, energies finite", r);
     tab.A_f[r] = mech->A_f[r];
     tab.Ea_f[r] = mech->Ea_f[r];
     tab.A_b[r] = mech->A_b[r];
@@ -517,6 +602,9 @@ int lbm_set_mechanism(lbm_ctx *c, const lbm_mechanism *mech) {
     if (e != hipSuccess) return fail(c, LBM_ENOMEM, "hipMalloc chemistry tables");
   }
   HIPCHK(c, hipMemcpy(c->chem_tab, &tab, sizeof(tab), hipMemcpyHostToDevice));
+  c->chem_host = tab;
+  c->chem_fn = nullptr;
+  c->have_perm = 0;
   ChemParams &cp = c->chem;
   memset(&cp, 0, sizeof(cp));
   cp.tab = c->chem_tab;
@@ -543,6 +631,15 @@ int lbm_set_mechanism(lbm_ctx *c, const lbm_mechanism *mech) {
   return LBM_OK;
 }
 
+int lbm_set_chem_kernel(lbm_ctx *c, int32_t kind) {
+  if (!c) return LBM_EINVAL;
+  if (kind != LBM_CHEM_SPECIALIZED && kind != LBM_CHEM_GENERIC) return fail(c, LBM_EINVAL, "unknown chemistry kernel %d", kind);
+  c->chem_kernel = kind;
+  c->chem_fn = nullptr;
+  c->have_perm = 0;
+  return LBM_OK;
+}
+
 int lbm_set_faradaic_source(lbm_ctx *c, const double *rate, int32_t fuel, int32_t product) {
   if (!c) return LBM_EINVAL;
   if (c->steps_done) return fail(c, LBM_ESTATE, "lbm_set_faradaic_source after the first step");
@@ -566,12 +663,17 @@ int lbm_set_faradaic_source(lbm_ctx *c, const double *rate, int32_t fuel, int32_
 int lbm_step(lbm_ctx *c, int64_t n_steps) {
   if (!c) return LBM_EINVAL;
   if (n_steps < 0) return fail(c, LBM_EINVAL, "negative step count");
+
   if (c->timing) {
     HIPCHK(c, hipEventRecord(c->ev_all[0], c->stream));
   }
   const int64_t first_timed = n_steps > kTimingRing ? n_steps - kTimingRing : 0;
   int slot = 0;
   for (int64_t s = 0; s < n_steps; ++s) {
+    if (c->has_mech && c->chem_kernel == LBM_CHEM_SPECIALIZED && !c->chem_fn && c->steps_done >= 1) {
+      const int rc = specialize_chemistry(c);   // after the first step (generic kernel)
+      if (rc) return rc;
+    }
     const int rec = (c->timing && s >= first_timed) ? slot++ : -1;
     int rc = enqueue_step(c, rec);
     if (rc) return rc;
@@ -701,9 +803,10 @@ namespace {
 struct SnapHeader {
   uint64_t magic, N, L, Q, M, K, D;
   int64_t steps_done;
-  int32_t first_step, pad0, pad1, pad2;
+  int32_t first_step, have_perm, pad0, pad1;
+  int32_t perm[16];          // elimination order of the specialised chemistry kernel
 };
-constexpr uint64_t kMagic = 0x314d424c5844ull;
+constexpr uint64_t kMagic = 0x324d424c5844ull;
 }  // namespace
 
 int lbm_save(lbm_ctx *c, void *buf, size_t *size) {
@@ -717,8 +820,19 @@ int lbm_save(lbm_ctx *c, void *buf, size_t *size) {
     return LBM_OK;
   }
   if (*size < need) return fail(c, LBM_EINVAL, "snapshot buffer too small (%zu < %zu)", *size, need);
-  SnapHeader h = {kMagic, N, (uint64_t)c->L, (uint64_t)c->Q, M, (uint64_t)c->K, D, c->steps_done,
-                  c->first_step, 0, 0, 0};
+  SnapHeader h;
+  memset(&h, 0, sizeof(h));
+  h.magic = kMagic;
+  h.N = N;
+  h.L = (uint64_t)c->L;
+  h.Q = (uint64_t)c->Q;
+  h.M = M;
+  h.K = (uint64_t)c->K;
+  h.D = D;
+  h.steps_done = c->steps_done;
+  h.first_step = c->first_step;
+  h.have_perm = c->have_perm;
+  memcpy(h.perm, c->chem_perm, sizeof(h.perm));
   memcpy(buf, &h, sizeof(h));
   double *o = (double *)((char *)buf + sizeof(h));
   const int q_last = (int)((c->steps_done + 1) & 1);
@@ -749,6 +863,10 @@ int lbm_load(lbm_ctx *c, const void *buf, size_t size) {
   if (size < sizeof(SnapHeader) + sizeof(double) * (npop + nrec)) return fail(c, LBM_EINVAL, "snapshot truncated");
   c->steps_done = h.steps_done;
   c->first_step = h.first_step;
+  if (h.have_perm && c->have_perm && memcmp(h.perm, c->chem_perm, sizeof(h.perm)) != 0) c->chem_fn = nullptr;
+  c->have_perm = h.have_perm;
+  memcpy(c->chem_perm, h.perm, sizeof(h.perm));
+  if (!h.have_perm) c->chem_fn = nullptr;
   c->cur = 0;
   const int q_last = (int)((c->steps_done + 1) & 1);
   const double *o = (const double *)((const char *)buf + sizeof(h));

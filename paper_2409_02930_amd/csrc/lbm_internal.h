@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <string>
+
 #define LBM_MMAX 5          // gas species
 #define LBM_KMAX 10         // surface species (vacancy included)
 #define LBM_RMAX 24         // surface reactions
@@ -102,6 +104,17 @@ struct MomParams {
   double *out;
 };
 
+// Mechanism of the specialised chemistry kernel (chem_jit.hip): everything that
+// is written into the generated source as a literal.
+struct ChemSpec {
+  int M, K, R, n_sub, n_newton;
+  int nu_f[LBM_RMAX][16], nu_b[LBM_RMAX][16];   // [reaction][species], species = gas, vacancy, adsorbates
+  double A_f[LBM_RMAX], Ea_f[LBM_RMAX], A_b[LBM_RMAX], Ea_b[LBM_RMAX];
+  double m[LBM_MMAX];                            // gas molar masses, kg/mol
+  double R_U;
+  int perm[16];                                  // elimination order of the S = M + K unknowns
+};
+
 // launchers (lbm_kernels.hip)
 hipError_t launch_init(int dim, const InitParams &ip, hipStream_t s);
 hipError_t launch_species(int dim, const KParams &p, hipStream_t s);
@@ -112,3 +125,10 @@ hipError_t launch_moments(int dim, const KParams &p, double *out, hipStream_t s)
 hipError_t launch_diag(int L, int D, int Mmom, int N, const double *pop, double *partials, int nblocks,
                        hipStream_t s);
 int chem_supported(int M, int K);
+
+// specialised chemistry (chem_jit.hip)
+std::string chem_specialized_source(const ChemSpec &spec);
+void chem_choose_order(ChemSpec &spec, int ns, const double *T, const double *phi, const double *C, double h,
+                       double a_s, double gam);
+hipError_t chem_specialize(const ChemSpec &spec, hipFunction_t *fn, std::string *log);
+hipError_t launch_chem_specialized(hipFunction_t fn, const ChemParams &cp, hipStream_t s);

@@ -301,7 +301,6 @@ template <int D, int M, bool ENERGY>
 __device__ __forceinline__ void species_front(const KParams &p, const Node &nd, double phi,
                                               SpeciesState<D, M> &S) {
   constexpr int Q = LQ<D>::Q;
-  const int N = p.N;
   const int n = nd.n;
   // velocity of this node at the previous step (inlet equilibria)
   double vb[D];
@@ -1305,7 +1304,6 @@ template <int M>
 __global__ __launch_bounds__(256) void k_faradaic(const ChemParams cp) {
   const int n = blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= cp.N) return;
-  const int N = cp.N;
   const double r = cp.faradaic[n] * cp.dt;
   double ssum = 0.0;
 #pragma unroll

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "_lib", "liblbm.so")
 
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EHIP, LBM_ESTATE, LBM_EUNSTABLE = 0, -1, -2, -3, -4, -5
 BC_PERIODIC, BC_BOUNCEBACK, BC_INLET, BC_OUTFLOW = 0, 1, 2, 3
+CHEM_SPECIALIZED, CHEM_GENERIC = 0, 1
 
 MOM_RHO_SPECIES = 1 << 0
 MOM_VELOCITY = 1 << 1
@@ -80,6 +81,7 @@ def _load():
         "lbm_set_porous_field": ([vp, _dp, _dp, C.c_double], C.c_int),
         "lbm_set_mechanism": ([vp, C.POINTER(lbm_mechanism)], C.c_int),
         "lbm_set_faradaic_source": ([vp, _dp, C.c_int32, C.c_int32], C.c_int),
+        "lbm_set_chem_kernel": ([vp, C.c_int32], C.c_int),
         "lbm_step": ([vp, C.c_int64], C.c_int),
         "lbm_moments": ([vp, C.c_uint32, vp, C.c_int32], C.c_int),
         "lbm_moment_rows": ([vp, C.c_uint32, _ip], C.c_int),
@@ -101,7 +103,7 @@ def _load():
 _lib = _load()
 
 EXPORTED = ["lbm_init", "lbm_init_columns", "lbm_set_porous_field", "lbm_set_mechanism",
-            "lbm_set_faradaic_source", "lbm_step", "lbm_moments", "lbm_moment_rows",
+            "lbm_set_chem_kernel", "lbm_set_faradaic_source", "lbm_step", "lbm_moments", "lbm_moment_rows",
             "lbm_get_diagnostics", "lbm_set_timing", "lbm_get_timing", "lbm_save", "lbm_load",
             "lbm_last_error", "lbm_destroy"]
 
@@ -206,6 +208,10 @@ class Lattice:
         st.gamma, st.a_s = float(mech.gamma), float(mech.a_s)
         self._check(_lib.lbm_set_mechanism(self.ctx, C.byref(st)))
         self.K = int(mech.K)
+
+    def set_chem_kernel(self, kind):
+        """CHEM_SPECIALIZED (default) or CHEM_GENERIC."""
+        self._check(_lib.lbm_set_chem_kernel(self.ctx, int(kind)))
 
     def set_faradaic_source(self, rate, fuel=0, product=1):
         rate = _arr(rate)

@@ -51,9 +51,11 @@ def _compare(got, ref, keys, tol=TOL):
     return errs
 
 
-def _run(lbm, w, steps, keys=("rho_a", "u", "T", "P", "j_a", "X", "rho")):
-    _log(f"case {w.name} N={w.N} steps={steps}")
+def _run(lbm, w, steps, keys=("rho_a", "u", "T", "P", "j_a", "X", "rho"), chem_kernel=None):
+    _log(f"case {w.name} N={w.N} steps={steps} chem_kernel={chem_kernel}")
     lat = lbm.lattice_from_workload(w)
+    if chem_kernel is not None:
+        lat.set_chem_kernel(chem_kernel)
     lat.step(steps)
     got = lat.fields()
     lat.close()
@@ -93,9 +95,27 @@ def test_d3q27_porous_no_chemistry(lbm):
     _run(lbm, w, 40)
 
 
-def test_d3q27_porous_with_chemistry(lbm):
+@pytest.mark.parametrize("kernel", ["specialized", "generic"])
+def test_d3q27_porous_with_chemistry(lbm, kernel):
     w = synth.config3(nx=10, ny=6, nz=4)
-    _run(lbm, w, 12)
+    kind = lbm.CHEM_SPECIALIZED if kernel == "specialized" else lbm.CHEM_GENERIC
+    _run(lbm, w, 12, chem_kernel=kind)
+
+
+def test_specialized_chemistry_matches_generic_full_newton(lbm):
+    """Specialised vs generic kernel on a stiffer mechanism setting (more
+    sub-steps and Newton iterations), both through lbm_step: every field
+    agrees to rounding."""
+    w = synth.config3(nx=12, ny=8, nz=6)
+    w = replace(w, mech=replace(w.mech, n_sub=3, n_newton=4))
+    out = {}
+    for kind in (lbm.CHEM_GENERIC, lbm.CHEM_SPECIALIZED):
+        lat = lbm.lattice_from_workload(w)
+        lat.set_chem_kernel(kind)
+        lat.step(8)
+        out[kind] = lat.fields()
+        lat.close()
+    _compare(out[lbm.CHEM_SPECIALIZED], out[lbm.CHEM_GENERIC], ("rho_a", "u", "P", "j_a", "theta"), tol=1e-12)
 
 
 def test_c2_energy_inlets_short(lbm):
@@ -123,6 +143,7 @@ def test_c4_columns_match_oracle_and_plain(lbm):
     lat.set_porous_field(cat("phi"), cat("tort"), w0.pore_radius)
     lat.set_faradaic_source(cat("faradaic_rate"), 0, 1)
     lat.set_mechanism(w0.mech)
+    lat.set_chem_kernel(lbm.CHEM_GENERIC)     # node-local and order-independent: batched == plain bitwise
     lat.step(steps)
     got = lat.fields()
     lat.close()
@@ -130,6 +151,7 @@ def test_c4_columns_match_oracle_and_plain(lbm):
     for c in cols:
         _log(f"column L={c.nx}")
         plain = lbm.lattice_from_workload(c)
+        plain.set_chem_kernel(lbm.CHEM_GENERIC)
         plain.step(steps)
         gp = plain.fields()
         plain.close()
@@ -140,7 +162,12 @@ def test_c4_columns_match_oracle_and_plain(lbm):
             assert np.array_equal(a, b), k          # batched == plain, bitwise
         o = Oracle(c)
         o.step(steps)
-        _compare(gp, o.moments(), ("rho_a", "u", "P", "X", "j_a", "theta"))
+        ref = o.moments()
+        _compare(gp, ref, ("rho_a", "u", "P", "X", "j_a", "theta"))
+        spec = lbm.lattice_from_workload(c)       # default: specialised chemistry
+        spec.step(steps)
+        _compare(spec.fields(), ref, ("rho_a", "u", "P", "X", "j_a", "theta"))
+        spec.close()
         off += c.nx
 
 
