@@ -473,29 +473,127 @@ __device__ __forceinline__ void species_front(const KParams &p, const Node &nd, 
 // k_species: one block = 64 nodes x (M species + momentum [+ energy]) waves.
 // Wave w pulls lattice w for its 64 nodes (one coalesced stream per direction)
 // and keeps only those Q populations in registers.  Lattice moments meet in
-// LDS; the momentum wave evaluates composition, temperature, relaxation rates,
-// the M x M species-momentum solve and the Knudsen force once per node and
-// publishes them; every species wave then collides its own lattice.
+// LDS.  Then every wave evaluates the cheap per-node state (composition,
+// temperature, R_a T) itself, and species wave a its own row of relaxation
+// rates (1/tau_ab, beta_a, 1/tau^k_a) and of the M x M species-momentum
+// system, published in LDS.  After the second barrier every wave that needs
+// the second-order species momenta solves that small system itself, so no
+// wave waits on a serial per-node phase; the species waves collide their own
+// lattice and the momentum wave writes the node records.
 // ---------------------------------------------------------------------------
 template <int D, int M, bool ENERGY>
 struct SpeciesShared {
   static constexpr int L = M + 1 + (ENERGY ? 1 : 0);
-  double m0[L][64];           // zeroth moments: phi rho_a, phi rho, phi rho E
-  double m1[M + 1][D][64];    // first moments of species and momentum lattices
-  double v[D][64];            // u / phi
-  double xi[M][D][64];        // j_a / (phi rho_a)
-  double RaT[M][64];
-  double Y[M][64];
-  double itab[M][M][64];      // 1 / tau_ab
-  double beta[M][64];
-  double itk[M][64];          // 1 / tau^k_a
+  static constexpr int Q = LQ<D>::Q;
+  double m0[L][64];             // zeroth moments: phi rho_a, phi rho, phi rho E
+  double x[M][D][64];           // second-order species momenta, from the momentum wave
+  union {
+    struct {
+      double m1[M + 1][D][64];  // first moments of species and momentum lattices
+      double A[M][M][64];       // species-momentum system, row a from species wave a
+      double itk[M][64];        // 1 / tau^k_a
+    } s;
+    double dlt[M][Q][64];       // phi rho_c (Psi_i(v) - Psi_i(xi_c)), after the solves
+  } u;
 };
+
+// Per-node state every wave derives from the lattice moments in LDS.
+template <int D, int M>
+struct NodeState {
+  double rho_a[M], Y[M], RaT[M];
+  double rho, u[D], v[D], im, T, RT, Ps, dfac;
+};
+
+template <int D, int M, bool ENERGY>
+__device__ __forceinline__ void node_state(const KParams &p, const SpeciesShared<D, M, ENERGY> &sh, int lane,
+                                           double phi, double Tfield, NodeState<D, M> &s) {
+  s.rho = sh.m0[M][lane] / phi;
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    s.u[d] = sh.u.s.m1[M][d][lane] / s.rho;
+    s.v[d] = s.u[d] / phi;
+  }
+  double rs = 0.0;
+#pragma unroll
+  for (int a = 0; a < M; ++a) {
+    s.rho_a[a] = sh.m0[a][lane] / phi;
+    rs += s.rho_a[a];
+  }
+  s.im = 0.0;
+#pragma unroll
+  for (int a = 0; a < M; ++a) {
+    s.Y[a] = s.rho_a[a] / rs;
+    s.im += s.Y[a] * p.inv_m[a];
+  }
+  if constexpr (ENERGY) {
+    const double E = sh.m0[M + 1][lane] / (phi * s.rho);
+    double v2 = 0.0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) v2 += s.v[d] * s.v[d];
+    double cvm = 0.0, u0m = 0.0;
+#pragma unroll
+    for (int a = 0; a < M; ++a) {
+      cvm += s.Y[a] * p.cv[a];
+      u0m += s.Y[a] * p.uf[a];
+    }
+    s.T = (E - 0.5 * v2 - u0m) / cvm;                 // eq temperature
+  } else {
+    s.T = Tfield;
+  }
+  s.RT = 0.0;
+  s.Ps = 0.0;
+#pragma unroll
+  for (int a = 0; a < M; ++a) {
+    s.RaT[a] = p.theta_ref * p.mmin_over_m[a] * (s.T * p.inv_T_ref);
+    s.RT += s.Y[a] * s.RaT[a];
+    s.Ps += s.rho_a[a] * s.RaT[a];
+  }
+  const double Tr = s.T * p.inv_T_ref;
+  s.dfac = Tr * sqrt(Tr) / s.Ps;                      // D_ab(T, P) = D_ab^ref (T/T_ref)^1.5 / P
+}
+
+// Second-order species momenta (eq transform1 with the Knudsen terms): solves
+// A x = j from the rows in LDS (Gaussian elimination, M x M, D right sides).
+template <int D, int M, bool ENERGY>
+__device__ __forceinline__ void species_momenta(const SpeciesShared<D, M, ENERGY> &sh, int lane,
+                                                double (&x)[M][D]) {
+  double A[M][M];
+#pragma unroll
+  for (int a = 0; a < M; ++a) {
+#pragma unroll
+    for (int c = 0; c < M; ++c) A[a][c] = sh.u.s.A[a][c][lane];
+#pragma unroll
+    for (int d = 0; d < D; ++d) x[a][d] = sh.u.s.m1[a][d][lane];
+  }
+#pragma unroll
+  for (int k = 0; k < M; ++k) {
+    const double inv = 1.0 / A[k][k];
+#pragma unroll
+    for (int r = k + 1; r < M; ++r) {
+      const double l = A[r][k] * inv;
+#pragma unroll
+      for (int c = k + 1; c < M; ++c) A[r][c] -= l * A[k][c];
+#pragma unroll
+      for (int d = 0; d < D; ++d) x[r][d] -= l * x[k][d];
+    }
+  }
+#pragma unroll
+  for (int k = M - 1; k >= 0; --k) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      double sacc = x[k][d];
+#pragma unroll
+      for (int c = k + 1; c < M; ++c) sacc -= A[k][c] * x[c][d];
+      x[k][d] = sacc / A[k][k];
+    }
+  }
+}
 
 template <int D, int M, bool ENERGY>
 __global__ __launch_bounds__(64 * (M + 1 + (ENERGY ? 1 : 0))) void k_species(const KParams p) {
   constexpr int Q = LQ<D>::Q;
   __shared__ SpeciesShared<D, M, ENERGY> sh;
-  const int w = threadIdx.x >> 6;                 // wave-uniform role
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform role (scalar)
   const int lane = threadIdx.x & 63;
   const unsigned nb = gridDim.x;
   const unsigned per = nb >> 3;
@@ -509,7 +607,7 @@ __global__ __launch_bounds__(64 * (M + 1 + (ENERGY ? 1 : 0))) void k_species(con
   nd.n = n;
   nd.x = nd.y = nd.z = 0;
   nd.flag = 0;
-  double phi = 1.0;
+  double phi = 1.0, Tfield = 0.0;
   double vb[D];
 #pragma unroll
   for (int d = 0; d < D; ++d) vb[d] = 0.0;
@@ -526,6 +624,7 @@ __global__ __launch_bounds__(64 * (M + 1 + (ENERGY ? 1 : 0))) void k_species(con
       nd.flag = (nd.x == 0 ? 1 : 0) | (nd.x == p.nx - 1 ? 2 : 0);
     }
     phi = p.phi[n];
+    if (!ENERGY) Tfield = p.Tfield[n];
     inlet_node = is_inlet_node(p, nd);
     geo = pull_geo<D>(p, nd);
     if (inlet_node) {
@@ -534,256 +633,159 @@ __global__ __launch_bounds__(64 * (M + 1 + (ENERGY ? 1 : 0))) void k_species(con
     }
   }
 
-  if (w < M) {
-    // ================= species wave: pull, moments, [wait], collide =================
-    const int a = w;
-    double f[Q];
-    if (valid) {
-      pull_lattice<D, M>(p, nd, geo, a, phi, vb, inlet_node, f);
-      double s0 = 0.0, s1[D];
+  // ---- phase 1: pull this wave's lattice, moments to LDS
+  double f[Q];
+  if (valid) {
+    const int lat = w;                       // species a, momentum M, energy M + 1
+    pull_lattice<D, M>(p, nd, geo, lat, phi, vb, inlet_node, f);
+    double s0 = 0.0, s1[D];
 #pragma unroll
-      for (int d = 0; d < D; ++d) s1[d] = 0.0;
+    for (int d = 0; d < D; ++d) s1[d] = 0.0;
 #pragma unroll
-      for (int i = 0; i < Q; ++i) {
-        s0 += f[i];
+    for (int i = 0; i < Q; ++i) {
+      s0 += f[i];
 #pragma unroll
-        for (int d = 0; d < D; ++d) s1[d] += cdir(i, d) * f[i];
-      }
-      sh.m0[a][lane] = s0;
-#pragma unroll
-      for (int d = 0; d < D; ++d) sh.m1[a][d][lane] = s1[d];
+      for (int d = 0; d < D; ++d) s1[d] += cdir(i, d) * f[i];
     }
-    __syncthreads();
-    __syncthreads();
-    if (valid) {
-      // eqs 27eq, 27qeq, fKnudsen, fStar, finalNumericalEquationsReactive.
-      // Cross term sum_{b != a} (1/tau_ab)(f^eq_b - f*_b), accumulated species by
-      // species from per-direction Psi factors.
-      double v[D];
+    sh.m0[lat][lane] = s0;
+    if (lat <= M) {
 #pragma unroll
-      for (int d = 0; d < D; ++d) v[d] = sh.v[d][lane];
-      double F[Q];
+      for (int d = 0; d < D; ++d) sh.u.s.m1[lat][d][lane] = s1[d];
+    }
+  }
+  __syncthreads();
+
+  // ---- phase 2: node state; species wave a publishes its rates and its row
+  NodeState<D, M> s;
+  double iab[M], beta = 0.0, itk_a = 0.0, RaTa = 0.0, Ya = 0.0;
+  if (valid && w <= M) {
+    node_state<D, M, ENERGY>(p, sh, lane, phi, Tfield, s);
+    if (w < M) {
+      const int a = w;
+      double Dr[M];
 #pragma unroll
-      for (int i = 0; i < Q; ++i) F[i] = 0.0;
+      for (int c = 0; c < M; ++c) {              // select without indexing by the run-time a
+        if (c == a) { RaTa = s.RaT[c]; Ya = s.Y[c]; }
+      }
+#pragma unroll
+      for (int c = 0; c < M; ++c) Dr[c] = p.Dref[a * LBM_MMAX + c];
+      double it = 0.0;
 #pragma unroll
       for (int c = 0; c < M; ++c) {
-        if (c == a) continue;                      // wave-uniform
-        const double coef = sh.itab[a][c][lane] * sh.m0[c][lane];   // (1/tau_ac) phi rho_c
-        const double RaTc = sh.RaT[c][lane];
-        double te[D][3], ts[D][3];
-#pragma unroll
-        for (int d = 0; d < D; ++d) {
-          const double xs = sh.xi[c][d][lane];
-          const double Pe = v[d] * v[d] + RaTc, Ps = xs * xs + RaTc;
-          te[d][0] = 0.5 * (-v[d] + Pe); te[d][1] = 1.0 - Pe; te[d][2] = 0.5 * (v[d] + Pe);
-          ts[d][0] = 0.5 * (-xs + Ps);   ts[d][1] = 1.0 - Ps; ts[d][2] = 0.5 * (xs + Ps);
-        }
-#pragma unroll
-        for (int i = 0; i < Q; ++i) {
-          double pe = te[0][i % 3], ps = ts[0][i % 3];
-          if (D > 1) { pe *= te[1][(i / 3) % 3]; ps *= ts[1][(i / 3) % 3]; }
-          if (D > 2) { pe *= te[2][i / 9]; ps *= ts[2][i / 9]; }
-          F[i] += coef * (pe - ps);
+        iab[c] = 0.0;
+        if (c != a) {
+          iab[c] = RaTa / (Dr[c] * s.dfac * (s.im / p.inv_m[c]));   // 1/tau_ab (eq tauab)
+          it += s.Y[c] * iab[c];
         }
       }
-      const double Ya = sh.Y[a][lane];
-      const double beta = sh.beta[a][lane];
-      const double itk = sh.itk[a][lane];
-      const double RaTa = sh.RaT[a][lane];
-      const double pra = sh.m0[a][lane];
-      const bool pos = pra > 0.0;
-      double te[D][3], ts[D][3], tk[D][3];
+      beta = it / (2.0 + it);                   // eq betaa
+      itk_a = p.knudsen ? RaTa / (p.kfac[n] * sqrt(RaTa)) : 0.0;   // eq tauak
+#pragma unroll
+      for (int c = 0; c < M; ++c)
+        sh.u.s.A[a][c][lane] = (c == a) ? 1.0 + 0.5 * it + 0.5 * itk_a : -0.5 * Ya * iab[c];
+      sh.u.s.itk[a][lane] = itk_a;
+    }
+  }
+  __syncthreads();
+
+  if (w < M) {
+    // ---- species wave a: waits for the second-order momenta of the momentum
+    //      wave, publishes Delta_a,i = phi rho_a (Psi_i(v, R_a T) - Psi_i(xi_a, R_a T)),
+    //      then collides (eqs 27eq, 27qeq, fKnudsen, fStar,
+    //      finalNumericalEquationsReactive) with the cross term
+    //      sum_{c != a} (1/tau_ac) Delta_c,i read back from LDS.
+    const int a = w;
+    __syncthreads();                              // x is in LDS; m1, A, itk are free
+    double te[D][3], ts[D][3], tk[D][3];
+    const double pra = sh.m0[a][lane];            // phi rho_a
+    const bool pos = pra > 0.0;
+    if (valid) {
 #pragma unroll
       for (int d = 0; d < D; ++d) {
-        const double xs = sh.xi[a][d][lane];
-        const double Pe = v[d] * v[d] + RaTa, Ps = xs * xs + RaTa;
-        te[d][0] = 0.5 * (-v[d] + Pe); te[d][1] = 1.0 - Pe; te[d][2] = 0.5 * (v[d] + Pe);
-        ts[d][0] = 0.5 * (-xs + Ps);   ts[d][1] = 1.0 - Ps; ts[d][2] = 0.5 * (xs + Ps);
-        tk[d][0] = 0.5 * RaTa;         tk[d][1] = 1.0 - RaTa; tk[d][2] = 0.5 * RaTa;
+        const double xs = pos ? sh.x[a][d][lane] / pra : 0.0;   // j_a / (phi rho_a)
+        const double Pe = s.v[d] * s.v[d] + RaTa, Ps = xs * xs + RaTa;
+        te[d][0] = 0.5 * (-s.v[d] + Pe); te[d][1] = 1.0 - Pe; te[d][2] = 0.5 * (s.v[d] + Pe);
+        ts[d][0] = 0.5 * (-xs + Ps);     ts[d][1] = 1.0 - Ps; ts[d][2] = 0.5 * (xs + Ps);
+        tk[d][0] = 0.5 * RaTa;           tk[d][1] = 1.0 - RaTa; tk[d][2] = 0.5 * RaTa;
       }
-      double* out = p.pout + (size_t)(a * Q) * N + n;
 #pragma unroll
       for (int i = 0; i < Q; ++i) {
+        double pe = te[0][i % 3], ps = ts[0][i % 3];
+        if (D > 1) { pe *= te[1][(i / 3) % 3]; ps *= ts[1][(i / 3) % 3]; }
+        if (D > 2) { pe *= te[2][i / 9]; ps *= ts[2][i / 9]; }
+        sh.u.dlt[a][i][lane] = pra * (pe - ps);
+      }
+    }
+    __syncthreads();
+    if (valid) {
+      double *out = p.pout + (size_t)(a * Q) * N + n;
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        double F = 0.0;                            // iab[a] == 0: the own term drops out
+#pragma unroll
+        for (int c = 0; c < M; ++c) F += iab[c] * sh.u.dlt[c][i][lane];
         double pe = te[0][i % 3], ps = ts[0][i % 3], pk = tk[0][i % 3];
         if (D > 1) { pe *= te[1][(i / 3) % 3]; ps *= ts[1][(i / 3) % 3]; pk *= tk[1][(i / 3) % 3]; }
         if (D > 2) { pe *= te[2][i / 9]; ps *= ts[2][i / 9]; pk *= tk[2][i / 9]; }
         const double feq = pra * pe;
         const double fst = pos ? pra * ps : 0.0;
         const double fk = pra * pk;
-        const double Fi = Ya * F[i] + itk * (fst - fk);
+        const double Fi = Ya * F + itk_a * (fst - fk);
         const double f0 = f[i];
         out[(size_t)i * N] = f0 + 2.0 * beta * (feq - f0) + (beta - 1.0) * Fi;
       }
     }
   } else if (w == M) {
-    // ================= momentum wave: moments, then the per-node solve =================
+    // ---- momentum wave: node records for the chemistry and mixture kernels and
+    //      for the next step
     if (valid) {
-      double f[Q];
-      pull_lattice<D, M>(p, nd, geo, M, phi, vb, inlet_node, f);
-      double s0 = 0.0, s1[D];
+      double x[M][D], itk[M];
+      species_momenta<D, M, ENERGY>(sh, lane, x);
 #pragma unroll
-      for (int d = 0; d < D; ++d) s1[d] = 0.0;
+      for (int c = 0; c < M; ++c) {
+        itk[c] = sh.u.s.itk[c][lane];
 #pragma unroll
-      for (int i = 0; i < Q; ++i) {
-        s0 += f[i];
-#pragma unroll
-        for (int d = 0; d < D; ++d) s1[d] += cdir(i, d) * f[i];
+        for (int d = 0; d < D; ++d) sh.x[c][d][lane] = x[c][d];
       }
-      sh.m0[M][lane] = s0;
-#pragma unroll
-      for (int d = 0; d < D; ++d) sh.m1[M][d][lane] = s1[d];
-    }
-    __syncthreads();
-    if (valid) {
-      double rho_a[M], Y[M], RaT[M];
-      const double rho = sh.m0[M][lane] / phi;
-      double u[D], v[D];
-#pragma unroll
-      for (int d = 0; d < D; ++d) {
-        u[d] = sh.m1[M][d][lane] / rho;
-        v[d] = u[d] / phi;
-        sh.v[d][lane] = v[d];
-      }
-      double rs = 0.0;
-#pragma unroll
-      for (int a = 0; a < M; ++a) {
-        rho_a[a] = sh.m0[a][lane] / phi;
-        rs += rho_a[a];
-      }
-      double im = 0.0;
-#pragma unroll
-      for (int a = 0; a < M; ++a) {
-        Y[a] = rho_a[a] / rs;
-        im += Y[a] * p.inv_m[a];
-        sh.Y[a][lane] = Y[a];
-      }
-      double T;
-      if (ENERGY) {
-        const double E = sh.m0[M + 1][lane] / (phi * rho);
-        double v2 = 0.0;
-#pragma unroll
-        for (int d = 0; d < D; ++d) v2 += v[d] * v[d];
-        double cvm = 0.0, u0m = 0.0;
-#pragma unroll
-        for (int a = 0; a < M; ++a) {
-          cvm += Y[a] * p.cv[a];
-          u0m += Y[a] * p.uf[a];
-        }
-        T = (E - 0.5 * v2 - u0m) / cvm;                 // eq temperature
-      } else {
-        T = p.Tfield[n];
-      }
-      double RT = 0.0, Ps = 0.0;
-#pragma unroll
-      for (int a = 0; a < M; ++a) {
-        RaT[a] = p.theta_ref * p.mmin_over_m[a] * (T * p.inv_T_ref);
-        RT += Y[a] * RaT[a];
-        Ps += rho_a[a] * RaT[a];
-        sh.RaT[a][lane] = RaT[a];
-      }
-      const double Tr = T * p.inv_T_ref;
-      const double dfac = Tr * sqrt(Tr) / Ps;         // D_ab(T, P) = D_ab^ref (T/T_ref)^1.5 / P
-      double A[M][M], itk[M];
-#pragma unroll
-      for (int a = 0; a < M; ++a) {
-        double it = 0.0;
-#pragma unroll
-        for (int c = 0; c < M; ++c) {
-          double iab = 0.0;
-          if (c != a) {
-            iab = RaT[a] / (p.Dref[a * LBM_MMAX + c] * dfac * (im / p.inv_m[c]));   // 1/tau_ab (eq tauab)
-            it += Y[c] * iab;
-          }
-          sh.itab[a][c][lane] = iab;
-          A[a][c] = -0.5 * Y[a] * iab;
-        }
-        sh.beta[a][lane] = it / (2.0 + it);             // eq betaa
-        itk[a] = p.knudsen ? RaT[a] / (p.kfac[n] * sqrt(RaT[a])) : 0.0;   // eq tauak
-        sh.itk[a][lane] = itk[a];
-        A[a][a] = 1.0 + 0.5 * it + 0.5 * itk[a];
-      }
-      // second-order species momenta (eq transform1 with the Knudsen terms)
-      double x[M][D];
-#pragma unroll
-      for (int a = 0; a < M; ++a)
-#pragma unroll
-        for (int d = 0; d < D; ++d) x[a][d] = sh.m1[a][d][lane];
-#pragma unroll
-      for (int k = 0; k < M; ++k) {
-        const double inv = 1.0 / A[k][k];
-#pragma unroll
-        for (int r = k + 1; r < M; ++r) {
-          const double l = A[r][k] * inv;
-#pragma unroll
-          for (int c = k + 1; c < M; ++c) A[r][c] -= l * A[k][c];
-#pragma unroll
-          for (int d = 0; d < D; ++d) x[r][d] -= l * x[k][d];
-        }
-      }
-#pragma unroll
-      for (int k = M - 1; k >= 0; --k) {
-#pragma unroll
-        for (int d = 0; d < D; ++d) {
-          double sacc = x[k][d];
-#pragma unroll
-          for (int c = k + 1; c < M; ++c) sacc -= A[k][c] * x[c][d];
-          x[k][d] = sacc / A[k][k];
-        }
-      }
-#pragma unroll
-      for (int a = 0; a < M; ++a) {
-        const bool pos = rho_a[a] > 0.0;
-        const double den = pos ? phi * rho_a[a] : 1.0;
-#pragma unroll
-        for (int d = 0; d < D; ++d) sh.xi[a][d][lane] = pos ? x[a][d] / den : 0.0;
-      }
-      // records for the chemistry and mixture kernels and for the next step
 #pragma unroll
       for (int d = 0; d < D; ++d) {
         double fk = 0.0;
 #pragma unroll
-        for (int c = 0; c < M; ++c) fk -= x[c][d] * itk[c];              // eq netKnudsenForce
-        p.rA[(size_t)d * N + n] = rho * u[d] * (1.0 - 3.0 * RT) - rho * u[d] * u[d] * u[d] / (phi * phi);
+        for (int c = 0; c < M; ++c) fk -= x[c][d] * itk[c];   // eq netKnudsenForce
+        p.rA[(size_t)d * N + n] =
+            s.rho * s.u[d] * (1.0 - 3.0 * s.RT) - s.rho * s.u[d] * s.u[d] * s.u[d] / (phi * phi);
         if (p.knudsen) p.rFk[(size_t)d * N + n] = fk;
-        if (p.need_v) p.rec_cur[(size_t)n * kRec + d] = v[d];
+        if (p.need_v) p.rec_cur[(size_t)n * kRec + d] = s.v[d];
       }
-      p.rRT[n] = RT;
+      p.rRT[n] = s.RT;
       if (p.chem) {
 #pragma unroll
-        for (int a = 0; a < M; ++a) p.rrho[(size_t)a * N + n] = rho_a[a];
+        for (int a = 0; a < M; ++a) p.rrho[(size_t)a * N + n] = s.rho_a[a];
       }
-      if (ENERGY) {
-        p.T_cur[n] = T;
+      if constexpr (ENERGY) {
+        p.T_cur[n] = s.T;
 #pragma unroll
         for (int d = 0; d < D; ++d) {
           double ub = 0.0;
 #pragma unroll
-          for (int c = 0; c < M; ++c) ub += Y[c] * ((rho_a[c] > 0.0) ? x[c][d] / rho_a[c] : u[d]);
+          for (int c = 0; c < M; ++c) ub += s.Y[c] * ((s.rho_a[c] > 0.0) ? x[c][d] / s.rho_a[c] : s.u[d]);
           double sacc = 0.0;
 #pragma unroll
           for (int a = 0; a < M; ++a) {
-            const double ua = (rho_a[a] > 0.0) ? x[a][d] / rho_a[a] : u[d];
-            const double Ha = p.uf[a] + p.cv[a] * T + RaT[a];
-            sacc += Ha * Y[a] * (ua - ub);
+            const double ua = (s.rho_a[a] > 0.0) ? x[a][d] / s.rho_a[a] : s.u[d];
+            const double Ha = p.uf[a] + p.cv[a] * s.T + s.RaT[a];
+            sacc += Ha * s.Y[a] * (ua - ub);
           }
           p.rqd[(size_t)d * N + n] = sacc;
         }
 #pragma unroll
-        for (int a = 0; a < M; ++a) p.rY[(size_t)a * N + n] = Y[a];
+        for (int a = 0; a < M; ++a) p.rY[(size_t)a * N + n] = s.Y[a];
       }
     }
     __syncthreads();
-  } else if constexpr (ENERGY) {
-    // ================= energy wave: zeroth moment of g =================
-    if (valid) {
-      double f[Q];
-      pull_lattice<D, M>(p, nd, geo, M + 1, phi, vb, inlet_node, f);
-      double s0 = 0.0;
-#pragma unroll
-      for (int i = 0; i < Q; ++i) s0 += f[i];
-      sh.m0[M + 1][lane] = s0;
-    }
     __syncthreads();
+  } else {
+    __syncthreads();                              // energy wave: nothing after its pull
     __syncthreads();
   }
 }
