@@ -137,6 +137,55 @@ def cpu_baseline(name, budget_s=20.0):
             "sample": f"{sample}: {steps} steps of {w.N} nodes in {el:.1f} s, numpy single thread"}
 
 
+def bench_c4(args, lbm, torch):
+    """Batched ragged 1-D columns (64 D1Q3 button-cell columns, L ~ U{200..2000}) in one
+    context with the graph step loop, against the same 64 columns run one after another,
+    each in its own context with plain launches."""
+    from workloads import synth
+    lengths, phis, currents = synth.config4_columns()
+    cols = [synth.config4_column(int(L), float(p_), float(i)) for L, p_, i in zip(lengths, phis, currents)]
+    stream = torch.cuda.Stream()
+    cat = lambda k: np.concatenate([getattr(c, k) for c in cols], axis=-1)
+    w0 = cols[0]
+    N = int(sum(lengths))
+    lat = lbm.Lattice(1, N, 1, 1, w0.molar_mass, w0.D_ref_lat, cat("X0"), cat("T0"), cat("P0"),
+                      T_ref=w0.T_ref, bc_lo=w0.bc_lo, bc_hi=w0.bc_hi, inlet_lo_X=w0.inlet_lo_X,
+                      inlet_T=w0.inlet_T, col_len=[int(L) for L in lengths], stream=stream.cuda_stream)
+    lat.set_porous_field(cat("phi"), cat("tort"), w0.pore_radius)
+    lat.set_faradaic_source(cat("faradaic_rate"), 0, 1)
+    lat.set_mechanism(w0.mech)
+    lat.set_graph(args.graph_steps)
+    log(f"batched: {len(cols)} columns, {N} nodes; warmup {args.warmup}")
+    lat.step(args.warmup)
+    stream.synchronize()
+    t0 = time.perf_counter()
+    lat.step(args.steps)
+    stream.synchronize()
+    t_batched = time.perf_counter() - t0
+    lat.close()
+    log(f"batched {args.steps} steps: {t_batched:.3f} s; sequential baseline")
+    t_seq = 0.0
+    for c in cols:
+        pl = lbm.lattice_from_workload(c, stream=stream.cuda_stream)
+        pl.step(args.warmup)
+        stream.synchronize()
+        t0 = time.perf_counter()
+        pl.step(args.steps)
+        stream.synchronize()
+        t_seq += time.perf_counter() - t0
+        pl.close()
+    mlups = N * args.steps / t_batched / 1e6
+    out = {"metric": "MLUPS", "value": mlups, "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": t_batched * 1e3 / args.steps, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"c4 {len(cols)} packed D1Q3 columns, {N} nodes, M=5 K=10 R=20, "
+                                  f"graph step loop of {args.graph_steps} steps",
+                      "nodes": N, "parallelism": "single GPU"},
+           "batched_vs_sequential": t_seq / t_batched,
+           "sequential_ms_per_step_all_columns": t_seq * 1e3 / args.steps}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -146,6 +195,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--chem-kernel", choices=["specialized", "generic"], default="specialized",
                     help="mechanism-specialised (default) or generic chemistry kernel")
+    ap.add_argument("--graph-steps", type=int, default=32,
+                    help="c4: steps per captured graph of the batched run (0 = plain launches)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -167,6 +218,8 @@ def main():
         torch.cuda.synchronize()
         log(f"copy calibration: 3 copies of {nbytes} bytes")
         del src, dst
+    if args.workload == "c4":
+        return bench_c4(args, lbm, torch)
     log(f"building workload {args.workload}")
     w = make_workload(args.workload)
     stream = torch.cuda.current_stream()

@@ -163,6 +163,17 @@ int lbm_set_faradaic_source(lbm_ctx *ctx, const double *rate, int32_t fuel, int3
 /* Advances n_steps time steps, asynchronously on the configured stream. */
 int lbm_step(lbm_ctx *ctx, int64_t n_steps);
 
+/* Graph step loop: with steps_per_graph = G (even, >= 2), lbm_step captures G
+ * consecutive steps into a HIP graph once the run is past its first step (and,
+ * with the generated chemistry kernel, once that kernel exists) and then
+ * replays the graph for every whole G-step block; the remaining steps and any
+ * step that would break the buffer parity run as plain launches.  Results are
+ * bitwise those of plain launches.  Needs a non-null stream in the
+ * configuration (LBM_EINVAL otherwise); 0 switches it off (default).  Per-kernel
+ * timing (lbm_get_timing) covers the plain-launch steps only.  For launch-bound
+ * runs such as the batched 1-D columns. */
+int lbm_set_graph(lbm_ctx *ctx, int32_t steps_per_graph);
+
 /* Writes the macroscopic fields selected by `mask` at the current time level,
  * SoA FP64 in mask-bit order, into out (device pointer if out_on_device != 0,
  * else host).  Synchronises the stream.  Returns LBM_EINVAL for an empty mask. */

@@ -65,6 +65,12 @@ struct lbm_ctx {
   hipFunction_t chem_fn = nullptr;      // specialised kernel of the installed mechanism
   int chem_perm[16] = {};               // its elimination order (kept in snapshots)
   int have_perm = 0;
+  // graph step loop: a captured sequence of graph_steps (even) steps, replayed
+  int graph_steps = 0;
+  hipGraphExec_t gexec = nullptr;
+  int gexec_cur = -1;                   // population buffer index the capture started from
+  int gexec_q = -1;                     // record buffer parity (steps_done & 1) it started from
+  hipFunction_t gexec_chem = nullptr;   // chemistry kernel the capture launched
   int K = 0;
   // timing
   int timing = 0;
@@ -473,6 +479,53 @@ int enqueue_step(lbm_ctx *c, int record_slot) {
   return LBM_OK;
 }
 
+void drop_graph(lbm_ctx *c) {
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  c->gexec = nullptr;
+  c->gexec_cur = -1;
+  c->gexec_q = -1;
+  c->gexec_chem = nullptr;
+}
+
+// Captures graph_steps steps starting from the current state into c->gexec.
+// Nothing runs during the capture; the context's step state is restored after it.
+int capture_steps(lbm_ctx *c) {
+  drop_graph(c);
+  const int cur0 = c->cur, first0 = c->first_step;
+  const long long done0 = c->steps_done;
+  HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+  int rc = LBM_OK;
+  for (int s = 0; s < c->graph_steps && rc == LBM_OK; ++s) rc = enqueue_step(c, -1);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(c->stream, &g);
+  c->cur = cur0;
+  c->first_step = first0;
+  c->steps_done = done0;
+  if (rc) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess || !g) return fail(c, LBM_EHIP, "graph capture failed: %s", hipGetErrorString(e));
+  const hipError_t ei = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (ei != hipSuccess) {
+    c->gexec = nullptr;
+    return fail(c, LBM_EHIP, "graph instantiation failed: %s", hipGetErrorString(ei));
+  }
+  c->gexec_cur = cur0;
+  c->gexec_q = (int)(done0 & 1);
+  c->gexec_chem = c->chem_fn;
+  return LBM_OK;
+}
+
+// Steady state for the graph: past the first (identity-pull) step and with the
+// chemistry kernel of the remaining run in place.
+bool graph_ready(const lbm_ctx *c) {
+  if (!c->graph_steps || c->first_step || c->steps_done < 1) return false;
+  if (c->has_mech && c->chem_kernel == LBM_CHEM_SPECIALIZED && !c->chem_fn) return false;
+  return true;
+}
+
 }  // namespace
 
 extern "C" {
@@ -660,6 +713,16 @@ int lbm_set_faradaic_source(lbm_ctx *c, const double *rate, int32_t fuel, int32_
   return LBM_OK;
 }
 
+int lbm_set_graph(lbm_ctx *c, int32_t steps_per_graph) {
+  if (!c) return LBM_EINVAL;
+  if (steps_per_graph != 0 && (steps_per_graph < 2 || steps_per_graph % 2))
+    return fail(c, LBM_EINVAL, "steps_per_graph must be 0 or an even number >= 2");
+  if (steps_per_graph && !c->stream) return fail(c, LBM_EINVAL, "the graph step loop needs a non-null stream");
+  c->graph_steps = steps_per_graph;
+  drop_graph(c);
+  return LBM_OK;
+}
+
 int lbm_step(lbm_ctx *c, int64_t n_steps) {
   if (!c) return LBM_EINVAL;
   if (n_steps < 0) return fail(c, LBM_EINVAL, "negative step count");
@@ -669,14 +732,27 @@ int lbm_step(lbm_ctx *c, int64_t n_steps) {
   }
   const int64_t first_timed = n_steps > kTimingRing ? n_steps - kTimingRing : 0;
   int slot = 0;
-  for (int64_t s = 0; s < n_steps; ++s) {
+  for (int64_t s = 0; s < n_steps;) {
     if (c->has_mech && c->chem_kernel == LBM_CHEM_SPECIALIZED && !c->chem_fn && c->steps_done >= 1) {
       const int rc = specialize_chemistry(c);   // after the first step (generic kernel)
       if (rc) return rc;
     }
+    // graph replay: whole captured sequences from the parity the capture started at
+    if (graph_ready(c) && n_steps - s >= c->graph_steps &&
+        (!c->gexec || (c->gexec_cur == c->cur && c->gexec_q == (int)(c->steps_done & 1)))) {
+      if (!c->gexec || c->gexec_chem != c->chem_fn) {
+        const int rc = capture_steps(c);
+        if (rc) return rc;
+      }
+      HIPCHK(c, hipGraphLaunch(c->gexec, c->stream));
+      c->steps_done += c->graph_steps;          // an even count: the buffer parity is unchanged
+      s += c->graph_steps;
+      continue;
+    }
     const int rec = (c->timing && s >= first_timed) ? slot++ : -1;
     int rc = enqueue_step(c, rec);
     if (rc) return rc;
+    ++s;
   }
   if (c->timing) {
     HIPCHK(c, hipEventRecord(c->ev_all[1], c->stream));
@@ -861,6 +937,7 @@ int lbm_load(lbm_ctx *c, const void *buf, size_t size) {
   const size_t npop = (size_t)c->L * c->Q * N;
   const size_t nrec = (size_t)kRec * N + (c->energy ? N : 0) + (c->has_mech ? (size_t)c->K * N : 0);
   if (size < sizeof(SnapHeader) + sizeof(double) * (npop + nrec)) return fail(c, LBM_EINVAL, "snapshot truncated");
+  drop_graph(c);
   c->steps_done = h.steps_done;
   c->first_step = h.first_step;
   if (h.have_perm && c->have_perm && memcmp(h.perm, c->chem_perm, sizeof(h.perm)) != 0) c->chem_fn = nullptr;
@@ -887,6 +964,7 @@ const char *lbm_last_error(const lbm_ctx *c) { return c ? c->err : "null context
 
 void lbm_destroy(lbm_ctx *c) {
   if (!c) return;
+  drop_graph(c);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   else (void)hipDeviceSynchronize();
   if (c->timing) lbm_set_timing(c, 0);

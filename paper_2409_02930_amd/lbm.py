@@ -83,6 +83,7 @@ def _load():
         "lbm_set_faradaic_source": ([vp, _dp, C.c_int32, C.c_int32], C.c_int),
         "lbm_set_chem_kernel": ([vp, C.c_int32], C.c_int),
         "lbm_step": ([vp, C.c_int64], C.c_int),
+        "lbm_set_graph": ([vp, C.c_int32], C.c_int),
         "lbm_moments": ([vp, C.c_uint32, vp, C.c_int32], C.c_int),
         "lbm_moment_rows": ([vp, C.c_uint32, _ip], C.c_int),
         "lbm_get_diagnostics": ([vp, C.POINTER(lbm_diag)], C.c_int),
@@ -103,7 +104,7 @@ def _load():
 _lib = _load()
 
 EXPORTED = ["lbm_init", "lbm_init_columns", "lbm_set_porous_field", "lbm_set_mechanism",
-            "lbm_set_chem_kernel", "lbm_set_faradaic_source", "lbm_step", "lbm_moments", "lbm_moment_rows",
+            "lbm_set_chem_kernel", "lbm_set_faradaic_source", "lbm_step", "lbm_set_graph", "lbm_moments", "lbm_moment_rows",
             "lbm_get_diagnostics", "lbm_set_timing", "lbm_get_timing", "lbm_save", "lbm_load",
             "lbm_last_error", "lbm_destroy"]
 
@@ -220,6 +221,10 @@ class Lattice:
     # -- run -------------------------------------------------------------------
     def step(self, n=1):
         self._check(_lib.lbm_step(self.ctx, int(n)))
+
+    def set_graph(self, steps_per_graph):
+        """Replay whole blocks of `steps_per_graph` (even) steps as a HIP graph; 0 = off."""
+        self._check(_lib.lbm_set_graph(self.ctx, int(steps_per_graph)))
 
     def moment_rows(self, mask):
         r = C.c_int32()
