@@ -174,6 +174,22 @@ int lbm_step(lbm_ctx *ctx, int64_t n_steps);
  * runs such as the batched 1-D columns. */
 int lbm_set_graph(lbm_ctx *ctx, int32_t steps_per_graph);
 
+/* Gradient of an outlet-flux objective by the adjoint of the step (isothermal,
+ * no surface mechanism or Faradaic source, D2Q9 grid; LBM_EINVAL otherwise),
+ * starting from the initial state (LBM_ESTATE after a step has been taken):
+ *   J = (1/T) sum_{t=1..T} sum_{nodes with x = nx-1} j_{s,x}(t) / m_s,
+ * with j_s the second-order species momentum of the species solve (eq
+ * transform1) at the time level each of the T steps collides (0..T-1), in
+ * lattice units divided by the molar mass in kg/mol.  Writes J, dJ/dphi per
+ * node into grad_phi[N] (device pointer if out_on_device != 0, else host;
+ * tortuosity held fixed, the initial populations and the inlet equilibria
+ * included) and dJ/dr_p (1/m, 0 with Knudsen diffusion off).  Runs the T steps
+ * forward with checkpoints every ceil(sqrt(T)) steps, then the reverse sweep,
+ * recomputing each segment; leaves the context at step T.  Allocates a
+ * workspace of about (2 sqrt(T) + 4) population fields for the call. */
+int lbm_adjoint_outlet_flux(lbm_ctx *ctx, int64_t n_steps, int32_t species, double *J, double *grad_phi,
+                            double *grad_rp, int32_t out_on_device);
+
 /* Writes the macroscopic fields selected by `mask` at the current time level,
  * SoA FP64 in mask-bit order, into out (device pointer if out_on_device != 0,
  * else host).  Synchronises the stream.  Returns LBM_EINVAL for an empty mask. */

@@ -570,6 +570,19 @@ class Oracle:
         return new
 
     # ----- outputs -----------------------------------------------------------
+    def outlet_flux(self, steps, species=0):
+        """Objective of the adjoint: J = (1/T) sum over the T steps of
+        sum_{x = nx-1} j_{s,x} / m_s, with j_s the solved second-order species
+        momentum (eq transform1) at the time level each step starts from
+        (0..T-1), lattice units over kg/mol.  Advances the oracle by T steps."""
+        outlet = (np.arange(self.N) % self.w.nx) == self.w.nx - 1
+        acc = 0.0
+        for _ in range(steps):
+            ja = self.macro()["ja"]                                                      # (M, D, N)
+            acc += float(np.sum(ja[species, 0, outlet])) / self.m[species]
+            self.step(1)
+        return acc / steps
+
     def moments(self):
         """Macroscopic fields at the current time level (the library's moment set)."""
         mac = self.macro()

@@ -8,7 +8,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(OUT_DIR, "liblbm.so")
-SOURCES = ["lbm_kernels.hip", "lbm_api.hip", "chem_jit.hip"]
+SOURCES = ["lbm_kernels.hip", "lbm_api.hip", "chem_jit.hip", "lbm_adjoint.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

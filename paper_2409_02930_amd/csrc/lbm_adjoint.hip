@@ -1,0 +1,702 @@
+// lbm_adjoint.hip -- reverse (adjoint) of the isothermal, reaction-free step
+// for the gradient of an outlet-flux objective with respect to the porosity
+// field and the pore radius.
+//
+// Forward map of one step at one node (Sections 2-3): post-stream populations
+// F_t (all lattices) -> moments -> composition, relaxation rates (eqs tauab,
+// taua, betaa, tauak), species momenta (eq transform1 with the Knudsen terms),
+// Knudsen force (eq netKnudsenForce), extended momentum equilibrium (eqs Pex,
+// feqmix with the Galilean correction G from neighbour records) -> collision
+// (eqs finalNumericalEquationsReactive, f) -> stream to F_{t+1}.
+//
+// The adjoint of one step runs in two passes over the nodes:
+//   pass 1: lambda'_t = transpose of the stream applied to Lambda_{t+1} (a
+//           gather over the same pull addresses), then dJ/dG at the node;
+//   pass 2: the adjoint of the node's collision: the population-level formulas
+//           (Psi products, the collision update) are differentiated by hand;
+//           the small coefficient map from the moments, phi and the Knudsen
+//           factor to the collision coefficients (composition, rates, the M x M
+//           solve, omega, u^ex, P^ex, the record rA, the objective) is
+//           differentiated in forward mode with dual numbers, one pass per
+//           moment-space input.  Lambda_t = explicit population terms + the
+//           moment chain; phi and the Knudsen factor accumulate their adjoints.
+// Objective: J = (1/T) sum_{t=1..T} sum_{x = nx-1} j_{s,x}(F_t) / m_s, the
+// solved momentum of species s through the last x plane, averaged over the
+// collision steps (time levels 0..T-1).
+#include "lbm_device.h"
+
+namespace {
+
+// ---- dual numbers (value, one tangent) -------------------------------------
+struct Dual {
+  double v, d;
+};
+__device__ __forceinline__ Dual mkd(double v, double d = 0.0) { return Dual{v, d}; }
+__device__ __forceinline__ Dual operator+(Dual a, Dual b) { return {a.v + b.v, a.d + b.d}; }
+__device__ __forceinline__ Dual operator-(Dual a, Dual b) { return {a.v - b.v, a.d - b.d}; }
+__device__ __forceinline__ Dual operator-(Dual a) { return {-a.v, -a.d}; }
+__device__ __forceinline__ Dual operator*(Dual a, Dual b) { return {a.v * b.v, a.d * b.v + a.v * b.d}; }
+__device__ __forceinline__ Dual operator/(Dual a, Dual b) {
+  const double q = a.v / b.v;
+  return {q, (a.d - q * b.d) / b.v};
+}
+__device__ __forceinline__ Dual operator+(Dual a, double b) { return {a.v + b, a.d}; }
+__device__ __forceinline__ Dual operator+(double a, Dual b) { return {a + b.v, b.d}; }
+__device__ __forceinline__ Dual operator-(Dual a, double b) { return {a.v - b, a.d}; }
+__device__ __forceinline__ Dual operator-(double a, Dual b) { return {a - b.v, -b.d}; }
+__device__ __forceinline__ Dual operator*(Dual a, double b) { return {a.v * b, a.d * b}; }
+__device__ __forceinline__ Dual operator*(double a, Dual b) { return {a * b.v, a * b.d}; }
+__device__ __forceinline__ Dual operator/(Dual a, double b) { return {a.v / b, a.d / b}; }
+__device__ __forceinline__ Dual operator/(double a, Dual b) {
+  const double q = a / b.v;
+  return {q, -q * b.d / b.v};
+}
+__device__ __forceinline__ Dual sqrt(Dual a) {
+  const double r = ::sqrt(a.v);
+  return {r, a.d / (2.0 * r)};
+}
+__device__ __forceinline__ double val(double a) { return a; }
+__device__ __forceinline__ double val(Dual a) { return a.v; }
+__device__ __forceinline__ double tan_(Dual a) { return a.d; }
+
+// ---- coefficient map --------------------------------------------------------
+// Inputs: raw lattice sums s0_l = sum_i f_li, s1_ld = sum_i f_li c_id (species
+// l < M, momentum l = M), the Galilean-correction gradient G (already x3),
+// phi and the Knudsen factor kfac.  Everything the collision needs besides the
+// populations themselves.
+template <class S, int D, int M>
+struct Coef {
+  S beta[M], Y[M], iab[M][M], itk[M], pra[M], xs[M][D], v[D];
+  S omega, gfac, xi[D], Pex[D], phirho, rA[D], N;
+};
+
+template <class S, int D, int M>
+__device__ __forceinline__ void coef_map(const KParams &p, const S (&s0)[M + 1], const S (&s1)[M + 1][D],
+                                         const S (&G)[D], S phi, S kfac, double T, int out_species,
+                                         Coef<S, D, M> &c) {
+  S rho_a[M], rs = s0[0] / phi;
+  rho_a[0] = rs;
+#pragma unroll
+  for (int a = 1; a < M; ++a) {
+    rho_a[a] = s0[a] / phi;
+    rs = rs + rho_a[a];
+  }
+  S im{};
+#pragma unroll
+  for (int a = 0; a < M; ++a) {
+    c.Y[a] = rho_a[a] / rs;
+    im = im + c.Y[a] * p.inv_m[a];
+  }
+  double RaT[M];
+#pragma unroll
+  for (int a = 0; a < M; ++a) RaT[a] = p.theta_ref * p.mmin_over_m[a] * (T * p.inv_T_ref);
+  S RT = c.Y[0] * RaT[0], Ps = rho_a[0] * RaT[0];
+#pragma unroll
+  for (int a = 1; a < M; ++a) {
+    RT = RT + c.Y[a] * RaT[a];
+    Ps = Ps + rho_a[a] * RaT[a];
+  }
+  const double Tr = T * p.inv_T_ref;
+  const S dfac = (Tr * ::sqrt(Tr)) / Ps;             // D_ab(T, P) = D_ab^ref (T/T_ref)^1.5 / P
+  S A[M][M];
+#pragma unroll
+  for (int a = 0; a < M; ++a) {
+    S it = S{};
+#pragma unroll
+    for (int b = 0; b < M; ++b) {
+      c.iab[a][b] = S{};
+      if (b != a) {
+        c.iab[a][b] = RaT[a] / (p.Dref[a * LBM_MMAX + b] * dfac * (im / p.inv_m[b]));   // eq tauab
+        it = it + c.Y[b] * c.iab[a][b];
+      }
+    }
+    c.beta[a] = it / (2.0 + it);                     // eq betaa
+    c.itk[a] = p.knudsen ? RaT[a] / (kfac * ::sqrt(RaT[a])) : S{};   // eq tauak
+#pragma unroll
+    for (int b = 0; b < M; ++b) A[a][b] = (b == a) ? 1.0 + 0.5 * it + 0.5 * c.itk[a] : -0.5 * c.Y[a] * c.iab[a][b];
+  }
+  // second-order species momenta: A x = s1 (Gaussian elimination, no exchanges)
+  S x[M][D];
+#pragma unroll
+  for (int a = 0; a < M; ++a)
+#pragma unroll
+    for (int d = 0; d < D; ++d) x[a][d] = s1[a][d];
+#pragma unroll
+  for (int k = 0; k < M; ++k) {
+    const S inv = 1.0 / A[k][k];
+#pragma unroll
+    for (int r = k + 1; r < M; ++r) {
+      const S l = A[r][k] * inv;
+#pragma unroll
+      for (int cc = k + 1; cc < M; ++cc) A[r][cc] = A[r][cc] - l * A[k][cc];
+#pragma unroll
+      for (int d = 0; d < D; ++d) x[r][d] = x[r][d] - l * x[k][d];
+    }
+  }
+#pragma unroll
+  for (int k = M - 1; k >= 0; --k) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      S sacc = x[k][d];
+#pragma unroll
+      for (int cc = k + 1; cc < M; ++cc) sacc = sacc - A[k][cc] * x[cc][d];
+      x[k][d] = sacc / A[k][k];
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < M; ++a) {
+    c.pra[a] = s0[a];
+    const bool pos = val(s0[a]) > 0.0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) c.xs[a][d] = pos ? x[a][d] / s0[a] : S{};
+  }
+  c.N = S{};
+#pragma unroll
+  for (int a = 0; a < M; ++a)
+    if (a == out_species) c.N = x[a][0];
+  // momentum lattice
+  const S rho = s0[M] / phi;
+  S u[D];
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    u[d] = s1[M][d] / rho;
+    c.v[d] = u[d] / phi;
+  }
+  c.omega = 1.0 / (p.nu / RT + 0.5);
+  c.gfac = (2.0 - c.omega) / (2.0 * phi * rho * c.omega);
+  c.phirho = phi * rho;
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    S Fk = S{};
+#pragma unroll
+    for (int a = 0; a < M; ++a) Fk = Fk - x[a][d] * c.itk[a];      // eq netKnudsenForce
+    c.Pex[d] = RT + c.v[d] * c.v[d] + c.gfac * G[d];
+    c.xi[d] = (u[d] + Fk / (c.omega * rho)) / phi;                 // u^ex / phi
+    c.rA[d] = rho * u[d] * (1.0 - 3.0 * RT) - rho * u[d] * u[d] * u[d] / (phi * phi);
+  }
+}
+
+// Psi_c(xi, P) and its partial derivatives.
+__device__ __forceinline__ double dpsi_dxi(int c) { return c == 0 ? 0.0 : (c > 0 ? 0.5 : -0.5); }
+__device__ __forceinline__ double dpsi_dP(int c) { return c == 0 ? -1.0 : 0.5; }
+// Psi_c(v, v^2 + R) as a function of v
+__device__ __forceinline__ double dpsiv_dv(int c, double v) { return c == 0 ? -2.0 * v : (c > 0 ? 0.5 + v : -0.5 + v); }
+
+// Product over axes of Psi and its derivative along axis e.
+template <int D>
+__device__ __forceinline__ void psi_prod(int i, const double *xi, const double *P, double &prod,
+                                         double *dxi, double *dP) {
+  double f[D];
+#pragma unroll
+  for (int d = 0; d < D; ++d) f[d] = psi1(cdir(i, d), xi[d], P[d]);
+  prod = 1.0;
+#pragma unroll
+  for (int d = 0; d < D; ++d) prod *= f[d];
+#pragma unroll
+  for (int e = 0; e < D; ++e) {
+    double o = 1.0;
+#pragma unroll
+    for (int d = 0; d < D; ++d)
+      if (d != e) o *= f[d];
+    if (dxi) dxi[e] = dpsi_dxi(cdir(i, e)) * o;
+    if (dP) dP[e] = dpsi_dP(cdir(i, e)) * o;
+  }
+}
+
+// Psi_i(v, v^2 + R) and its derivative with respect to v_e.
+template <int D>
+__device__ __forceinline__ double psiv_prod(int i, const double *v, double R, double *dv) {
+  double f[D];
+#pragma unroll
+  for (int d = 0; d < D; ++d) f[d] = psi1(cdir(i, d), v[d], v[d] * v[d] + R);
+  double prod = 1.0;
+#pragma unroll
+  for (int d = 0; d < D; ++d) prod *= f[d];
+  if (dv) {
+#pragma unroll
+    for (int e = 0; e < D; ++e) {
+      double o = 1.0;
+#pragma unroll
+      for (int d = 0; d < D; ++d)
+        if (d != e) o *= f[d];
+      dv[e] = dpsiv_dv(cdir(i, e), v[e]) * o;
+    }
+  }
+  return prod;
+}
+
+// Node geometry from its index (grids only).
+__device__ __forceinline__ Node node_of(const KParams &p, int n) {
+  Node nd;
+  nd.n = n;
+  nd.x = n % p.nx;
+  const int r = n / p.nx;
+  nd.y = r % p.ny;
+  nd.z = r / p.ny;
+  nd.flag = (nd.x == 0 ? 1 : 0) | (nd.x == p.nx - 1 ? 2 : 0);
+  return nd;
+}
+
+// Node at integer offset (dx, dy, dz) with periodic wrap in y, z and in x when x
+// is periodic; -1 when it leaves a non-periodic x end.
+__device__ __forceinline__ int offset_node(const KParams &p, const Node &nd, int dx, int dy, int dz) {
+  int x = nd.x + dx, y = nd.y + dy, z = nd.z + dz;
+  if (x < 0 || x >= p.nx) {
+    if (p.bc_lo != BC_PERIODIC) return -1;
+    x += (x < 0) ? p.nx : -p.nx;
+  }
+  y += (y < 0) ? p.ny : 0;
+  y -= (y >= p.ny) ? p.ny : 0;
+  z += (z < 0) ? p.nz : 0;
+  z -= (z >= p.nz) ? p.nz : 0;
+  return x + p.nx * (y + p.ny * z);
+}
+
+template <int D, int M>
+struct AdjParams {
+  KParams k;                 // pin = f'_{t-1}, rec_prev = v_{t-1}, rA = rA_t, first_step = (t == 1)
+  const double *lam_next;    // Lambda_{t+1} [L][Q][N]; NULL at t = T
+  double *lam_cur;           // Lambda_t
+  double *lamp;              // lambda'_t (pass 1 writes, pass 2 reads)
+  double *gbar;              // dJ/dG [D][N]
+  double *phibar, *kfacbar;  // [N] accumulated
+  double *jacc;              // [N] objective, outlet nodes
+  double wN;                 // 1 / (T m_s)
+  int out_species;
+};
+
+// lambda'_t(x, l, i): sum of Lambda_{t+1} over the (node, direction) pairs whose
+// pull at step t+1 reads the post-collision population (x, l, i).
+template <int D, int M>
+__device__ __forceinline__ void stream_transpose(const AdjParams<D, M> &a, const Node &nd,
+                                                 double (&lp)[M + 1][LQ<D>::Q]) {
+  constexpr int Q = LQ<D>::Q;
+  const KParams &p = a.k;
+  const int N = p.N;
+#pragma unroll
+  for (int l = 0; l <= M; ++l)
+#pragma unroll
+    for (int i = 0; i < Q; ++i) lp[l][i] = 0.0;
+  if (!a.lam_next) return;
+  KParams pn = p;
+  pn.first_step = 0;                                  // geometry of the pull at step t+1
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const int cx = cdir(i, 0), cy = D > 1 ? cdir(i, 1) : 0, cz = D > 2 ? cdir(i, 2) : 0;
+    int cand[3], cdirn[3];
+    cand[0] = offset_node(p, nd, cx, cy, cz);        // regular
+    cdirn[0] = i;
+    cand[1] = offset_node(p, nd, 0, cy, cz);         // outflow copy along the same x
+    cdirn[1] = i;
+    cand[2] = nd.n;                                  // bounce-back
+    cdirn[2] = Q - 1 - i;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const int y = cand[k];
+      if (y < 0) continue;
+      bool dup = false;
+      for (int k2 = 0; k2 < k; ++k2) dup |= (cand[k2] == y && cdirn[k2] == cdirn[k]);
+      if (dup) continue;
+      const Node ny = node_of(pn, y);
+      const PullGeo<D> g = pull_geo<D>(pn, ny);
+      int dir;
+      const int src = pull_addr<D>(pn, ny, g, cdirn[k], dir);
+      if (src != nd.n || dir != i || inlet_kind<D>(pn, ny, cdirn[k]) != 0) continue;
+#pragma unroll
+      for (int l = 0; l <= M; ++l) lp[l][i] += a.lam_next[(size_t)(l * Q + cdirn[k]) * N + y];
+    }
+  }
+}
+
+// Moments, G and the stored populations of node n at step t.
+template <int D, int M>
+__device__ __forceinline__ void node_inputs(const KParams &p, const Node &nd, double (&f)[M + 1][LQ<D>::Q],
+                                            double (&s0)[M + 1], double (&s1)[M + 1][D], double (&G)[D],
+                                            double &phi) {
+  constexpr int Q = LQ<D>::Q;
+  const int n = nd.n;
+  phi = p.phi[n];
+  const bool inlet_node = is_inlet_node(p, nd);
+  double vb[D];
+#pragma unroll
+  for (int d = 0; d < D; ++d) vb[d] = inlet_node ? p.rec_prev[(size_t)n * kRec + d] : 0.0;
+  const PullGeo<D> geo = pull_geo<D>(p, nd);
+#pragma unroll
+  for (int l = 0; l <= M; ++l) {
+    pull_lattice<D, M>(p, nd, geo, l, phi, vb, inlet_node, f[l]);
+    s0[l] = 0.0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) s1[l][d] = 0.0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      s0[l] += f[l][i];
+#pragma unroll
+      for (int d = 0; d < D; ++d) s1[l][d] += cdir(i, d) * f[l][i];
+    }
+  }
+#pragma unroll
+  for (int d = 0; d < D; ++d) G[d] = 0.0;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    if (cnorm2<D>(i) == 0) continue;
+    const int m = nb_node<D>(p, nd, i);
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      const int c = cdir(i, d);
+      if (c != 0) G[d] += wdir<D>(i) * c * p.rA[(size_t)d * p.N + m];
+    }
+  }
+#pragma unroll
+  for (int d = 0; d < D; ++d) G[d] *= 3.0;
+}
+
+// Adjoint of the population-level collision at fixed coefficients: coefficient
+// adjoints (cb) and the explicit population adjoints (fbar).
+template <int D, int M>
+__device__ __forceinline__ void collision_adjoint(const KParams &p, double T, const double (&f)[M + 1][LQ<D>::Q],
+                                                  const double (&lp)[M + 1][LQ<D>::Q], const Coef<double, D, M> &c,
+                                                  Coef<double, D, M> &cb, double (&fbar)[M + 1][LQ<D>::Q]) {
+  constexpr int Q = LQ<D>::Q;
+  double RaT[M];
+#pragma unroll
+  for (int a = 0; a < M; ++a) RaT[a] = p.theta_ref * p.mmin_over_m[a] * (T * p.inv_T_ref);
+  // zero the coefficient adjoints
+#pragma unroll
+  for (int a = 0; a < M; ++a) {
+    cb.beta[a] = cb.Y[a] = cb.itk[a] = cb.pra[a] = 0.0;
+#pragma unroll
+    for (int b = 0; b < M; ++b) cb.iab[a][b] = 0.0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) cb.xs[a][d] = 0.0;
+  }
+#pragma unroll
+  for (int d = 0; d < D; ++d) cb.v[d] = cb.xi[d] = cb.Pex[d] = cb.rA[d] = 0.0;
+  cb.omega = cb.gfac = cb.phirho = cb.N = 0.0;
+
+  double v[D];
+#pragma unroll
+  for (int d = 0; d < D; ++d) v[d] = c.v[d];
+  // dlt_ci = feq_ci - fst_ci for every species and direction
+  double dlt[M][Q];
+#pragma unroll
+  for (int a = 0; a < M; ++a) {
+    const bool pos = c.pra[a] > 0.0;
+    double xs[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) xs[d] = c.xs[a][d];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const double E = psiv_prod<D>(i, v, RaT[a], nullptr);
+      const double Sx = pos ? psiv_prod<D>(i, xs, RaT[a], nullptr) : 0.0;
+      dlt[a][i] = c.pra[a] * (E - Sx);
+    }
+  }
+  // species lattices
+  double dltb[M][Q];
+#pragma unroll
+  for (int a = 0; a < M; ++a)
+#pragma unroll
+    for (int i = 0; i < Q; ++i) dltb[a][i] = 0.0;
+#pragma unroll
+  for (int a = 0; a < M; ++a) {
+    const bool pos = c.pra[a] > 0.0;
+    double xs[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) xs[d] = c.xs[a][d];
+    const double beta = c.beta[a], Ya = c.Y[a], itk = c.itk[a];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      double dE[D], dS[D];
+      const double E = psiv_prod<D>(i, v, RaT[a], dE);
+      const double Sx = pos ? psiv_prod<D>(i, xs, RaT[a], dS) : 0.0;
+      double K = 1.0;
+#pragma unroll
+      for (int d = 0; d < D; ++d) K *= psi1(cdir(i, d), 0.0, RaT[a]);
+      const double feq = c.pra[a] * E, fst = pos ? c.pra[a] * Sx : 0.0, fk = c.pra[a] * K;
+      double cross = 0.0;
+#pragma unroll
+      for (int b = 0; b < M; ++b) cross += c.iab[a][b] * dlt[b][i];
+      const double Fai = Ya * cross + itk * (fst - fk);
+      const double lam = lp[a][i];
+      fbar[a][i] = lam * (1.0 - 2.0 * beta);
+      cb.beta[a] += lam * (2.0 * (feq - f[a][i]) + Fai);
+      const double Fb = (beta - 1.0) * lam;
+      cb.Y[a] += Fb * cross;
+#pragma unroll
+      for (int b = 0; b < M; ++b) {
+        cb.iab[a][b] += Fb * Ya * dlt[b][i];
+        dltb[b][i] += Fb * Ya * c.iab[a][b];
+      }
+      cb.itk[a] += Fb * (fst - fk);
+      const double feqb = 2.0 * beta * lam;
+      const double fstb = Fb * itk;
+      const double fkb = -Fb * itk;
+      cb.pra[a] += feqb * E + (pos ? fstb * Sx : 0.0) + fkb * K;
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        cb.v[d] += feqb * c.pra[a] * dE[d];
+        if (pos) cb.xs[a][d] += fstb * c.pra[a] * dS[d];
+      }
+    }
+  }
+  // the cross-term differences dlt_bi = pra_b (E_bi - S_bi)
+#pragma unroll
+  for (int b = 0; b < M; ++b) {
+    const bool pos = c.pra[b] > 0.0;
+    double xs[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) xs[d] = c.xs[b][d];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const double g = dltb[b][i];
+      if (g == 0.0) continue;
+      double dE[D], dS[D];
+      const double E = psiv_prod<D>(i, v, RaT[b], dE);
+      const double Sx = pos ? psiv_prod<D>(i, xs, RaT[b], dS) : 0.0;
+      cb.pra[b] += g * (E - Sx);
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        cb.v[d] += g * c.pra[b] * dE[d];
+        if (pos) cb.xs[b][d] -= g * c.pra[b] * dS[d];
+      }
+    }
+  }
+  // momentum lattice
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    double X, dX[D], dP[D];
+    double xi[D], P[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      xi[d] = c.xi[d];
+      P[d] = c.Pex[d];
+    }
+    psi_prod<D>(i, xi, P, X, dX, dP);
+    const double fex = c.phirho * X;
+    const double lam = lp[M][i];
+    fbar[M][i] = lam * (1.0 - c.omega);
+    cb.omega += lam * (fex - f[M][i]);
+    const double fexb = c.omega * lam;
+    cb.phirho += fexb * X;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      cb.xi[d] += fexb * c.phirho * dX[d];
+      cb.Pex[d] += fexb * c.phirho * dP[d];
+    }
+  }
+}
+
+template <class S, int D, int M>
+__device__ __forceinline__ double coef_dot(const Coef<S, D, M> &c, const Coef<double, D, M> &cb) {
+  double s = 0.0;
+#pragma unroll
+  for (int a = 0; a < M; ++a) {
+    s += cb.beta[a] * tan_(c.beta[a]) + cb.Y[a] * tan_(c.Y[a]) + cb.itk[a] * tan_(c.itk[a]) +
+         cb.pra[a] * tan_(c.pra[a]);
+#pragma unroll
+    for (int b = 0; b < M; ++b) s += cb.iab[a][b] * tan_(c.iab[a][b]);
+#pragma unroll
+    for (int d = 0; d < D; ++d) s += cb.xs[a][d] * tan_(c.xs[a][d]);
+  }
+#pragma unroll
+  for (int d = 0; d < D; ++d)
+    s += cb.v[d] * tan_(c.v[d]) + cb.xi[d] * tan_(c.xi[d]) + cb.Pex[d] * tan_(c.Pex[d]) + cb.rA[d] * tan_(c.rA[d]);
+  s += cb.omega * tan_(c.omega) + cb.gfac * tan_(c.gfac) + cb.phirho * tan_(c.phirho) + cb.N * tan_(c.N);
+  return s;
+}
+
+// ---- pass 1: lambda'_t and dJ/dG ------------------------------------------
+template <int D, int M>
+__global__ __launch_bounds__(128) void k_adj_pass1(const AdjParams<D, M> a) {
+  constexpr int Q = LQ<D>::Q;
+  const KParams &p = a.k;
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= p.N) return;
+  const int N = p.N;
+  const Node nd = node_of(p, n);
+  double lp[M + 1][Q];
+  stream_transpose<D, M>(a, nd, lp);
+#pragma unroll
+  for (int l = 0; l <= M; ++l)
+#pragma unroll
+    for (int i = 0; i < Q; ++i) a.lamp[(size_t)(l * Q + i) * N + n] = lp[l][i];
+  double f[M + 1][Q], s0[M + 1], s1[M + 1][D], G[D], phi;
+  node_inputs<D, M>(p, nd, f, s0, s1, G, phi);
+  Coef<double, D, M> c;
+  coef_map<double, D, M>(p, s0, s1, G, phi, p.kfac[n], p.Tfield[n], a.out_species, c);
+  // dJ/dG_d = gfac * dJ/dPex_d, from the momentum lattice only
+  double Gb[D];
+#pragma unroll
+  for (int d = 0; d < D; ++d) Gb[d] = 0.0;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    double X, dP[D];
+    psi_prod<D>(i, c.xi, c.Pex, X, nullptr, dP);
+    const double fexb = c.omega * lp[M][i];
+#pragma unroll
+    for (int d = 0; d < D; ++d) Gb[d] += fexb * c.phirho * dP[d];
+  }
+#pragma unroll
+  for (int d = 0; d < D; ++d) a.gbar[(size_t)d * N + n] = Gb[d] * c.gfac;
+}
+
+// ---- pass 2: Lambda_t, phi and Knudsen-factor adjoints, objective ----------
+template <int D, int M>
+__global__ __launch_bounds__(64) void k_adj_pass2(const AdjParams<D, M> a) {
+  constexpr int Q = LQ<D>::Q;
+  const KParams &p = a.k;
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= p.N) return;
+  const int N = p.N;
+  const Node nd = node_of(p, n);
+  double f[M + 1][Q], s0[M + 1], s1[M + 1][D], G[D], phi;
+  node_inputs<D, M>(p, nd, f, s0, s1, G, phi);
+  const double kfac = p.kfac[n], T = p.Tfield[n];
+  double lp[M + 1][Q];
+#pragma unroll
+  for (int l = 0; l <= M; ++l)
+#pragma unroll
+    for (int i = 0; i < Q; ++i) lp[l][i] = a.lamp[(size_t)(l * Q + i) * N + n];
+  Coef<double, D, M> c, cb;
+  coef_map<double, D, M>(p, s0, s1, G, phi, kfac, T, a.out_species, c);
+  double fbar[M + 1][Q];
+  collision_adjoint<D, M>(p, T, f, lp, c, cb, fbar);
+
+  // rA_t(x) feeds G of the nodes whose stencil reaches x
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    if (cnorm2<D>(i) == 0) continue;
+    const int cx = cdir(i, 0), cy = D > 1 ? cdir(i, 1) : 0, cz = D > 2 ? cdir(i, 2) : 0;
+    const int cand0 = offset_node(p, nd, -cx, -cy, -cz);
+    int cands[2] = {cand0, (cand0 == n) ? -1 : n};
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int xx = cands[k];
+      if (xx < 0) continue;
+      if (nb_node<D>(p, node_of(p, xx), i) != n) continue;
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        const int cc = cdir(i, d);
+        if (cc != 0) cb.rA[d] += 3.0 * wdir<D>(i) * cc * a.gbar[(size_t)d * N + xx];
+      }
+    }
+  }
+  // the inlet equilibria of step t+1 use this node's v_t and phi
+  double phib = 0.0;
+  if (a.lam_next) {
+    KParams pn = p;
+    pn.first_step = 0;
+    if (is_inlet_node(pn, nd)) {
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        const int kind = inlet_kind<D>(pn, nd, i);
+        if (!kind) continue;
+        const InletSel in = inlet_sel(p, kind, -1);
+#pragma unroll
+        for (int l = 0; l <= M; ++l) {
+          const double L = a.lam_next[(size_t)(l * Q + i) * N + n];
+          double R, rho;
+          if (l < M) {
+            const InletSel is = inlet_sel(p, kind, l);
+            R = is.RaT;
+            rho = is.rho_a;
+          } else {
+            R = in.RT;
+            rho = in.rho;
+          }
+          double dv[D];
+          const double pr = psiv_prod<D>(i, c.v, R, dv);
+          phib += L * rho * pr;                      // F^in = phi rho Psi(v, v^2 + R)
+#pragma unroll
+          for (int d = 0; d < D; ++d) cb.v[d] += L * phi * rho * dv[d];
+        }
+      }
+    }
+  }
+  // objective
+  if (nd.flag & 2) {
+    a.jacc[n] += c.N * a.wN;
+    cb.N += a.wN;
+  }
+  // moment-space adjoints by forward mode through the coefficient map
+  constexpr int NI = (M + 1) * (1 + D) + 2;   // s0, s1, phi, kfac (G is done in pass 1)
+  double ib[NI];
+#pragma unroll 1
+  for (int k = 0; k < NI; ++k) {
+    Dual ds0[M + 1], ds1[M + 1][D], dG[D];
+#pragma unroll
+    for (int l = 0; l <= M; ++l) {
+      ds0[l] = mkd(s0[l], k == l ? 1.0 : 0.0);
+#pragma unroll
+      for (int d = 0; d < D; ++d) ds1[l][d] = mkd(s1[l][d], k == (M + 1) + l * D + d ? 1.0 : 0.0);
+    }
+#pragma unroll
+    for (int d = 0; d < D; ++d) dG[d] = mkd(G[d]);
+    const Dual dphi = mkd(phi, k == NI - 2 ? 1.0 : 0.0);
+    const Dual dkf = mkd(kfac, k == NI - 1 ? 1.0 : 0.0);
+    Coef<Dual, D, M> cd;
+    coef_map<Dual, D, M>(p, ds0, ds1, dG, dphi, dkf, T, a.out_species, cd);
+    ib[k] = coef_dot<Dual, D, M>(cd, cb);
+  }
+#pragma unroll
+  for (int l = 0; l <= M; ++l)
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      double s = fbar[l][i] + ib[l];
+#pragma unroll
+      for (int d = 0; d < D; ++d) s += cdir(i, d) * ib[(M + 1) + l * D + d];
+      a.lam_cur[(size_t)(l * Q + i) * N + n] = s;
+    }
+  a.phibar[n] += ib[NI - 2] + phib;
+  a.kfacbar[n] += ib[NI - 1];
+}
+
+// Initial populations are phi times a phi-free equilibrium: dJ/dphi += Lambda_1 . F_1 / phi.
+template <int D, int M>
+__global__ __launch_bounds__(256) void k_adj_initial(const AdjParams<D, M> a) {
+  constexpr int Q = LQ<D>::Q;
+  const KParams &p = a.k;
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= p.N) return;
+  const int N = p.N;
+  double s = 0.0;
+  for (int l = 0; l <= M; ++l)
+    for (int i = 0; i < Q; ++i)
+      s += a.lam_next[(size_t)(l * Q + i) * N + n] * p.pin[(size_t)(l * Q + i) * N + n];
+  a.phibar[n] += s / p.phi[n];
+}
+
+template <int D, int M>
+hipError_t adj_dispatch_m(const KParams &k, const AdjBuffers &b, int stage, hipStream_t s) {
+  AdjParams<D, M> a;
+  a.k = k;
+  a.lam_next = b.lam_next;
+  a.lam_cur = b.lam_cur;
+  a.lamp = b.lamp;
+  a.gbar = b.gbar;
+  a.phibar = b.phibar;
+  a.kfacbar = b.kfacbar;
+  a.jacc = b.jacc;
+  a.wN = b.wN;
+  a.out_species = b.out_species;
+  if (stage == 1)
+    hipLaunchKernelGGL((k_adj_pass1<D, M>), dim3((k.N + 127) / 128), dim3(128), 0, s, a);
+  else if (stage == 2)
+    hipLaunchKernelGGL((k_adj_pass2<D, M>), dim3((k.N + 63) / 64), dim3(64), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_adj_initial<D, M>), dim3((k.N + 255) / 256), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_adjoint(int dim, const KParams &k, const AdjBuffers &b, int stage, hipStream_t s) {
+  if (dim != 2) return hipErrorInvalidValue;
+  switch (k.M) {
+    case 2: return adj_dispatch_m<2, 2>(k, b, stage, s);
+    case 3: return adj_dispatch_m<2, 3>(k, b, stage, s);
+    case 4: return adj_dispatch_m<2, 4>(k, b, stage, s);
+    case 5: return adj_dispatch_m<2, 5>(k, b, stage, s);
+  }
+  return hipErrorInvalidValue;
+}

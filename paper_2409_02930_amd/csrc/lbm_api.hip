@@ -762,6 +762,140 @@ int lbm_step(lbm_ctx *c, int64_t n_steps) {
   return LBM_OK;
 }
 
+int lbm_adjoint_outlet_flux(lbm_ctx *c, int64_t n_steps, int32_t species, double *J, double *grad_phi,
+                            double *grad_rp, int32_t out_on_device) {
+  if (!c || !J || !grad_phi || !grad_rp) return LBM_EINVAL;
+  if (n_steps < 1) return fail(c, LBM_EINVAL, "n_steps must be >= 1");
+  if (species < 0 || species >= c->M) return fail(c, LBM_EINVAL, "species out of range");
+  if (c->dim != 2 || c->energy || c->has_mech || c->has_faradaic || c->colflag)
+    return fail(c, LBM_EINVAL, "the adjoint covers isothermal, reaction-free D2Q9 grids");
+  if (c->steps_done != 0) return fail(c, LBM_ESTATE, "the adjoint starts from the initial state (no step taken)");
+  const size_t N = c->N, L = c->L, Q = c->Q, D = c->dim;
+  const size_t P = L * Q * N, R = (size_t)kRec * N, A = D * N;
+  const int64_t T = n_steps;
+  int64_t K = 1;
+  while (K * K < T) ++K;                              // sqrt(T) checkpoints, sqrt(T) steps per segment
+  const int64_t nseg = (T + K - 1) / K;
+  // workspace: checkpoints, segment states, adjoint fields
+  const size_t need = (size_t)nseg * (P + R) + (size_t)(K + 1) * (P + R + A) + 3 * P + A + 3 * N;
+  double *ws = nullptr;
+  if (hipMalloc((void **)&ws, sizeof(double) * need) != hipSuccess)
+    return fail(c, LBM_ENOMEM, "adjoint workspace of %.2f GB", 8.0 * need / 1e9);
+  double *ck = ws;                                    // [nseg][P + R]
+  double *seg = ck + (size_t)nseg * (P + R);          // [K + 1][P + R + A]
+  double *lam[2] = {seg + (size_t)(K + 1) * (P + R + A), nullptr};
+  lam[1] = lam[0] + P;
+  double *lamp = lam[1] + P, *gbar = lamp + P, *phibar = gbar + A, *kfacbar = phibar + N, *jacc = kfacbar + N;
+  auto slot_pop = [&](int64_t k) { return seg + (size_t)k * (P + R + A); };
+  auto slot_rec = [&](int64_t k) { return slot_pop(k) + P; };
+  auto slot_rA = [&](int64_t k) { return slot_pop(k) + P + R; };
+  int rc = LBM_OK;
+  double *pop0 = c->pop[0], *pop1 = c->pop[1], *rec0 = c->rec[0], *rec1 = c->rec[1], *rA0 = c->rA;
+  auto restore_ptrs = [&]() {
+    c->pop[0] = pop0;
+    c->pop[1] = pop1;
+    c->rec[0] = rec0;
+    c->rec[1] = rec1;
+    c->rA = rA0;
+  };
+  auto hipck = [&](hipError_t e, const char *what) {
+    if (e != hipSuccess && rc == LBM_OK) rc = fail(c, LBM_EHIP, "%s: %s", what, hipGetErrorString(e));
+    return e == hipSuccess;
+  };
+  hipck(hipMemsetAsync(lam[0], 0, sizeof(double) * (3 * P + A + 3 * N), c->stream), "clear");
+  // forward pass with checkpoints (state before steps 1, K+1, 2K+1, ...)
+  for (int64_t s = 0; s < nseg && rc == LBM_OK; ++s) {
+    const int q_last = (int)((c->steps_done + 1) & 1);
+    hipck(hipMemcpyAsync(ck + (size_t)s * (P + R), c->pop[c->cur], sizeof(double) * P, hipMemcpyDeviceToDevice,
+                         c->stream), "checkpoint");
+    hipck(hipMemcpyAsync(ck + (size_t)s * (P + R) + P, c->rec[q_last], sizeof(double) * R, hipMemcpyDeviceToDevice,
+                         c->stream), "checkpoint");
+    const int64_t t1 = (s + 1) * K < T ? (s + 1) * K : T;
+    for (int64_t t = s * K; t < t1 && rc == LBM_OK; ++t) rc = enqueue_step(c, -1);
+  }
+  const int cur_f = c->cur, first_f = c->first_step;
+  const long long done_f = c->steps_done;
+  const double wN = 1.0 / ((double)T * c->m[species]);
+  // reverse sweep, segment by segment
+  for (int64_t s = nseg - 1; s >= 0 && rc == LBM_OK; --s) {
+    const int64_t t0 = s * K, t1 = (s + 1) * K < T ? (s + 1) * K : T;
+    hipck(hipMemcpyAsync(slot_pop(0), ck + (size_t)s * (P + R), sizeof(double) * (P + R), hipMemcpyDeviceToDevice,
+                         c->stream), "restore");
+    c->steps_done = t0;
+    c->first_step = t0 == 0;
+    c->cur = 0;
+    // recompute the segment: step t reads slot t-t0-1 and writes slot t-t0
+    for (int64_t t = t0 + 1; t <= t1 && rc == LBM_OK; ++t) {
+      const int64_t k = t - t0 - 1;
+      const int q = (int)(c->steps_done & 1);
+      c->pop[c->cur] = slot_pop(k);
+      c->pop[1 - c->cur] = slot_pop(k + 1);
+      c->rec[1 - q] = slot_rec(k);
+      c->rec[q] = slot_rec(k + 1);
+      c->rA = slot_rA(k);
+      rc = enqueue_step(c, -1);
+    }
+    restore_ptrs();
+    // adjoint of the segment's steps, last first
+    for (int64_t t = t1; t > t0 && rc == LBM_OK; --t) {
+      const int64_t k = t - t0 - 1;
+      KParams ka = base_params(c);
+      ka.pin = slot_pop(k);
+      ka.rec_prev = slot_rec(k);
+      ka.rA = slot_rA(k);
+      ka.first_step = t == 1;
+      AdjBuffers b;
+      b.lam_next = t == T ? nullptr : lam[(t + 1) & 1];
+      b.lam_cur = lam[t & 1];
+      b.lamp = lamp;
+      b.gbar = gbar;
+      b.phibar = phibar;
+      b.kfacbar = kfacbar;
+      b.jacc = jacc;
+      b.wN = wN;
+      b.out_species = species;
+      hipck(launch_adjoint(c->dim, ka, b, 1, c->stream), "adjoint pass 1");
+      hipck(launch_adjoint(c->dim, ka, b, 2, c->stream), "adjoint pass 2");
+    }
+  }
+  restore_ptrs();
+  if (rc == LBM_OK) {
+    KParams ka = base_params(c);
+    ka.pin = ck;                                      // initial populations
+    AdjBuffers b;
+    memset(&b, 0, sizeof(b));
+    b.lam_next = lam[1];                              // Lambda_1
+    b.phibar = phibar;
+    hipck(launch_adjoint(c->dim, ka, b, 3, c->stream), "adjoint initial state");
+  }
+  c->cur = cur_f;
+  c->first_step = first_f;
+  c->steps_done = done_f;
+  if (rc == LBM_OK) {
+    std::vector<double> hb(3 * N), kf(N), ph(N);
+    hipck(hipStreamSynchronize(c->stream), "synchronize");
+    hipck(hipMemcpy(hb.data(), phibar, sizeof(double) * 3 * N, hipMemcpyDeviceToHost), "copy");
+    hipck(hipMemcpy(kf.data(), c->kfac, sizeof(double) * N, hipMemcpyDeviceToHost), "copy");
+    hipck(hipMemcpy(ph.data(), c->phi, sizeof(double) * N, hipMemcpyDeviceToHost), "copy");
+    double jsum = 0.0, rsum = 0.0;
+    std::vector<double> g(N);
+    for (size_t n = 0; n < N; ++n) {
+      const double kb = hb[N + n];
+      const double dkf = c->knudsen ? kb * kf[n] : 0.0;   // kfac is proportional to phi and to r_p
+      g[n] = hb[n] + dkf / ph[n];
+      rsum += dkf;
+      jsum += hb[2 * N + n];
+    }
+    *J = jsum;
+    *grad_rp = c->knudsen && c->pore_radius > 0 ? rsum / c->pore_radius : 0.0;
+    hipck(hipMemcpy(grad_phi, g.data(), sizeof(double) * N,
+                    out_on_device ? hipMemcpyHostToDevice : hipMemcpyHostToHost), "copy gradient");
+  }
+  (void)hipStreamSynchronize(c->stream);
+  (void)hipFree(ws);
+  return rc;
+}
+
 int lbm_moment_rows(const lbm_ctx *c, uint32_t mask, int32_t *rows) {
   if (!c || !rows) return LBM_EINVAL;
   const int M = c->M, D = c->dim;

@@ -126,6 +126,20 @@ hipError_t launch_diag(int L, int D, int Mmom, int N, const double *pop, double 
                        hipStream_t s);
 int chem_supported(int M, int K);
 
+// adjoint of the isothermal reaction-free step (lbm_adjoint.hip)
+struct AdjBuffers {
+  const double *lam_next;   // Lambda_{t+1} [L][Q][N] or NULL
+  double *lam_cur, *lamp;   // Lambda_t, lambda'_t
+  double *gbar;             // [D][N]
+  double *phibar, *kfacbar; // [N]
+  double *jacc;             // [N]
+  double wN;                // 1 / (T m_s)
+  int out_species;
+};
+// stage 1: lambda'_t and dJ/dG; stage 2: Lambda_t and parameter adjoints;
+// stage 3: the initial-state term (k.pin = initial populations, lam_next = Lambda_1)
+hipError_t launch_adjoint(int dim, const KParams &k, const AdjBuffers &b, int stage, hipStream_t s);
+
 // specialised chemistry (chem_jit.hip)
 std::string chem_specialized_source(const ChemSpec &spec);
 void chem_choose_order(ChemSpec &spec, int ns, const double *T, const double *phi, const double *C, double h,

@@ -84,6 +84,7 @@ def _load():
         "lbm_set_chem_kernel": ([vp, C.c_int32], C.c_int),
         "lbm_step": ([vp, C.c_int64], C.c_int),
         "lbm_set_graph": ([vp, C.c_int32], C.c_int),
+        "lbm_adjoint_outlet_flux": ([vp, C.c_int64, C.c_int32, _dp, vp, _dp, C.c_int32], C.c_int),
         "lbm_moments": ([vp, C.c_uint32, vp, C.c_int32], C.c_int),
         "lbm_moment_rows": ([vp, C.c_uint32, _ip], C.c_int),
         "lbm_get_diagnostics": ([vp, C.POINTER(lbm_diag)], C.c_int),
@@ -104,7 +105,7 @@ def _load():
 _lib = _load()
 
 EXPORTED = ["lbm_init", "lbm_init_columns", "lbm_set_porous_field", "lbm_set_mechanism",
-            "lbm_set_chem_kernel", "lbm_set_faradaic_source", "lbm_step", "lbm_set_graph", "lbm_moments", "lbm_moment_rows",
+            "lbm_set_chem_kernel", "lbm_set_faradaic_source", "lbm_step", "lbm_set_graph", "lbm_adjoint_outlet_flux", "lbm_moments", "lbm_moment_rows",
             "lbm_get_diagnostics", "lbm_set_timing", "lbm_get_timing", "lbm_save", "lbm_load",
             "lbm_last_error", "lbm_destroy"]
 
@@ -221,6 +222,21 @@ class Lattice:
     # -- run -------------------------------------------------------------------
     def step(self, n=1):
         self._check(_lib.lbm_step(self.ctx, int(n)))
+
+    def adjoint_outlet_flux(self, n_steps, species=0, grad_out=None):
+        """Runs n_steps from the initial state and returns (J, dJ/dphi [N], dJ/dr_p) for the
+        outlet flux of `species` (see lbm_adjoint_outlet_flux).  grad_out: optional torch
+        CUDA tensor of N float64 that receives dJ/dphi on the device."""
+        J = C.c_double()
+        grp = C.c_double()
+        if grad_out is not None:
+            self._check(_lib.lbm_adjoint_outlet_flux(self.ctx, int(n_steps), int(species), C.byref(J),
+                                                     C.c_void_p(grad_out.data_ptr()), C.byref(grp), 1))
+            return J.value, grad_out, grp.value
+        g = np.zeros(self.N)
+        self._check(_lib.lbm_adjoint_outlet_flux(self.ctx, int(n_steps), int(species), C.byref(J),
+                                                 g.ctypes.data_as(C.c_void_p), C.byref(grp), 0))
+        return J.value, g, grp.value
 
     def set_graph(self, steps_per_graph):
         """Replay whole blocks of `steps_per_graph` (even) steps as a HIP graph; 0 = off."""

@@ -1,0 +1,99 @@
+"""Adjoint of the isothermal reaction-free step (through the C ABI) against the
+oracle: the objective itself to 1e-11, and its gradient with respect to the
+porosity field and the pore radius against central finite differences of the
+oracle (relative step 1e-6, tortuosity held fixed)."""
+import sys
+from dataclasses import replace
+
+import numpy as np
+import pytest
+
+from oracle.lbm_oracle import Oracle
+from workloads import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lbm():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2409_02930_amd import lbm as _lbm
+    return _lbm
+
+
+def _log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _case(name):
+    if name == "c5_inlet_outflow":
+        return synth.config5(nx=36, ny=8), 24
+    w = synth.config5(nx=24, ny=8)
+    w = replace(w, bc_lo=synth.BC_PERIODIC, bc_hi=synth.BC_PERIODIC, inlet_lo_X=None)
+    if name == "periodic_no_knudsen":
+        w = replace(w, pore_radius=float("inf"))
+    return w, 20
+
+
+def _oracle_J(w, T):
+    return Oracle(w).outlet_flux(T, 0)
+
+
+def _gpu(lbm, w, T):
+    _log(f"adjoint {w.name} {w.nx}x{w.ny} T={T}")
+    lat = lbm.lattice_from_workload(w)
+    J, g, grp = lat.adjoint_outlet_flux(T, 0)
+    lat.close()
+    return J, g, grp
+
+
+CASES = ["periodic_no_knudsen", "periodic_knudsen", "c5_inlet_outflow"]
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_adjoint_objective_matches_oracle(lbm, name):
+    w, T = _case(name)
+    J, _, _ = _gpu(lbm, w, T)
+    Jo = _oracle_J(w, T)
+    assert abs(J - Jo) <= 1e-11 * abs(Jo) + 1e-300, (J, Jo)
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_adjoint_gradient_matches_oracle_finite_differences(lbm, name):
+    w, T = _case(name)
+    J, g, grp = _gpu(lbm, w, T)
+    rng = np.random.default_rng(7)
+    N = w.N
+    x = np.arange(N) % w.nx
+    nodes = sorted(set([0, w.nx // 2, w.nx - 1, w.nx - 2, N - 1]) | set(rng.integers(0, N, 5).tolist()))
+    fd, ad = [], []
+    for k in nodes:
+        h = 1e-6 * w.phi[k]
+        pp, pm = w.phi.copy(), w.phi.copy()
+        pp[k] += h
+        pm[k] -= h
+        d = (_oracle_J(replace(w, phi=pp), T) - _oracle_J(replace(w, phi=pm), T)) / (2 * h)
+        fd.append(d)
+        ad.append(g[k])
+    # two smooth directions
+    y = np.arange(N) // w.nx
+    for kx, ky in ((1, 1), (2, 0)):
+        v = np.sin(2 * np.pi * kx * (x + 0.5) / w.nx) * np.cos(2 * np.pi * ky * y / w.ny) * w.phi
+        h = 1e-6
+        d = (_oracle_J(replace(w, phi=w.phi + h * v), T) - _oracle_J(replace(w, phi=w.phi - h * v), T)) / (2 * h)
+        fd.append(d)
+        ad.append(float(np.dot(g, v)))
+    fd, ad = np.array(fd), np.array(ad)
+    scale = np.max(np.abs(fd))
+    _log(f"{name}: J={J:.6e} max|dJ/dphi| sample {scale:.3e}; worst rel err {np.max(np.abs(ad - fd)) / scale:.2e}")
+    assert np.all(np.abs(ad - fd) <= 2e-6 * scale + 1e-12 * abs(J)), np.c_[fd, ad]
+    if np.isfinite(w.pore_radius):
+        rp = w.pore_radius
+        d = (_oracle_J(replace(w, pore_radius=rp * (1 + 1e-6)), T)
+             - _oracle_J(replace(w, pore_radius=rp * (1 - 1e-6)), T)) / (2e-6 * rp)
+        _log(f"{name}: dJ/dr_p adjoint {grp:.6e} fd {d:.6e}")
+        assert abs(grp - d) <= 2e-6 * abs(d) + 1e-12 * abs(J) / rp, (grp, d)
+    else:
+        assert grp == 0.0
