@@ -186,6 +186,41 @@ def bench_c4(args, lbm, torch):
     print(json.dumps(out), flush=True)
 
 
+def bench_c5_adjoint(args, lbm, torch):
+    """C5 (D2Q9 1024x256, 3 species, GRF porosity, inlet/outflow): forward steps
+    alone vs the adjoint gradient of the outlet flux (forward with checkpoints,
+    segment recompute and reverse sweep) over the same number of steps."""
+    from workloads import synth
+    # uniform porosity: with a spatially varying porosity and Knudsen drag the
+    # method develops a growing mode after a few hundred steps (oracle and GPU alike)
+    w = synth.config5(porosity="uniform")
+    stream = torch.cuda.Stream()
+    lat = lbm.lattice_from_workload(w, stream=stream.cuda_stream)
+    stream.synchronize()
+    t0 = time.perf_counter()
+    lat.step(args.steps)
+    stream.synchronize()
+    t_fwd = time.perf_counter() - t0
+    lat.close()
+    lat = lbm.lattice_from_workload(w, stream=stream.cuda_stream)
+    g = torch.empty(w.N, dtype=torch.float64, device="cuda")
+    stream.synchronize()
+    t0 = time.perf_counter()
+    J, g, grp = lat.adjoint_outlet_flux(args.steps, 0, grad_out=g)
+    stream.synchronize()
+    t_adj = time.perf_counter() - t0
+    lat.close()
+    out = {"metric": "MLUPS", "value": w.N * args.steps / t_fwd / 1e6, "unit": "MLUPS", "n_gpus": 1,
+           "steps": args.steps, "warmup": 0, "ms_per_step": t_fwd * 1e3 / args.steps, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"c5 D2Q9 {w.nx}x{w.ny} M=3 inlet/outflow, uniform porosity 0.45, "
+                                  f"outlet-flux adjoint",
+                      "nodes": w.N, "parallelism": "single GPU"},
+           "adjoint_s": t_adj, "forward_s": t_fwd, "adjoint_over_forward": t_adj / t_fwd,
+           "J": J, "grad_rp": grp, "grad_phi_absmax": float(g.abs().max())}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -220,6 +255,8 @@ def main():
         del src, dst
     if args.workload == "c4":
         return bench_c4(args, lbm, torch)
+    if args.workload == "c5_adjoint":
+        return bench_c5_adjoint(args, lbm, torch)
     log(f"building workload {args.workload}")
     w = make_workload(args.workload)
     stream = torch.cuda.current_stream()

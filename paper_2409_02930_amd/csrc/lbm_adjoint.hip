@@ -176,6 +176,257 @@ __device__ __forceinline__ void coef_map(const KParams &p, const S (&s0)[M + 1],
   }
 }
 
+// Reverse of coef_map: given the adjoints cb of its outputs, the adjoints of
+// s0, s1, phi and kfac (G is handled in pass 1).  Recomputes the forward
+// values, then runs the chain rule backwards through every intermediate.
+template <int D, int M>
+__device__ __forceinline__ void coef_map_reverse(const KParams &p, const double (&s0)[M + 1],
+                                                 const double (&s1)[M + 1][D], const double (&G)[D], double phi,
+                                                 double kfac, double T, int out_species,
+                                                 const Coef<double, D, M> &cb, double (&s0b)[M + 1],
+                                                 double (&s1b)[M + 1][D], double &phib, double &kfacb) {
+  // ---- forward values
+  double rho_a[M], rs = 0.0, Y[M], im = 0.0, RaT[M];
+#pragma unroll
+  for (int a = 0; a < M; ++a) {
+    rho_a[a] = s0[a] / phi;
+    rs += rho_a[a];
+  }
+#pragma unroll
+  for (int a = 0; a < M; ++a) {
+    Y[a] = rho_a[a] / rs;
+    im += Y[a] * p.inv_m[a];
+    RaT[a] = p.theta_ref * p.mmin_over_m[a] * (T * p.inv_T_ref);
+  }
+  double RT = 0.0, Ps = 0.0;
+#pragma unroll
+  for (int a = 0; a < M; ++a) {
+    RT += Y[a] * RaT[a];
+    Ps += rho_a[a] * RaT[a];
+  }
+  const double Tr = T * p.inv_T_ref;
+  const double dfac = Tr * ::sqrt(Tr) / Ps;
+  double iab[M][M], it[M], beta[M], itk[M], A[M][M];
+#pragma unroll
+  for (int a = 0; a < M; ++a) {
+    it[a] = 0.0;
+#pragma unroll
+    for (int b = 0; b < M; ++b) {
+      iab[a][b] = 0.0;
+      if (b != a) {
+        iab[a][b] = RaT[a] / (p.Dref[a * LBM_MMAX + b] * dfac * (im / p.inv_m[b]));
+        it[a] += Y[b] * iab[a][b];
+      }
+    }
+    beta[a] = it[a] / (2.0 + it[a]);
+    itk[a] = p.knudsen ? RaT[a] / (kfac * ::sqrt(RaT[a])) : 0.0;
+#pragma unroll
+    for (int b = 0; b < M; ++b) A[a][b] = (b == a) ? 1.0 + 0.5 * it[a] + 0.5 * itk[a] : -0.5 * Y[a] * iab[a][b];
+  }
+  double LU[M][M], x[M][D];
+#pragma unroll
+  for (int a = 0; a < M; ++a) {
+#pragma unroll
+    for (int b = 0; b < M; ++b) LU[a][b] = A[a][b];
+#pragma unroll
+    for (int d = 0; d < D; ++d) x[a][d] = s1[a][d];
+  }
+#pragma unroll
+  for (int k = 0; k < M; ++k) {
+    const double inv = 1.0 / LU[k][k];
+#pragma unroll
+    for (int r = k + 1; r < M; ++r) {
+      const double l = LU[r][k] * inv;
+      LU[r][k] = l;                                  // multiplier kept for the transposed solve
+#pragma unroll
+      for (int cc = k + 1; cc < M; ++cc) LU[r][cc] -= l * LU[k][cc];
+#pragma unroll
+      for (int d = 0; d < D; ++d) x[r][d] -= l * x[k][d];
+    }
+  }
+#pragma unroll
+  for (int k = M - 1; k >= 0; --k)
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      double sacc = x[k][d];
+#pragma unroll
+      for (int cc = k + 1; cc < M; ++cc) sacc -= LU[k][cc] * x[cc][d];
+      x[k][d] = sacc / LU[k][k];
+    }
+  const double rho = s0[M] / phi;
+  double u[D], v[D], Fk[D];
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    u[d] = s1[M][d] / rho;
+    v[d] = u[d] / phi;
+    Fk[d] = 0.0;
+#pragma unroll
+    for (int a = 0; a < M; ++a) Fk[d] -= x[a][d] * itk[a];
+  }
+  const double omega = 1.0 / (p.nu / RT + 0.5);
+  const double gfac = (2.0 - omega) / (2.0 * phi * rho * omega);
+
+  // ---- reverse
+  double rhob = 0.0, RTb = 0.0, omegab = cb.omega, gfacb = cb.gfac, ub[D], vb[D], Fkb[D], xb[M][D];
+  phib = 0.0;
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    ub[d] = 0.0;
+    vb[d] = cb.v[d];
+    Fkb[d] = 0.0;
+  }
+#pragma unroll
+  for (int a = 0; a < M; ++a)
+#pragma unroll
+    for (int d = 0; d < D; ++d) xb[a][d] = 0.0;
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    // rA_d = rho u_d (1 - 3RT) - rho u_d^3 / phi^2
+    const double rAb = cb.rA[d], u3 = u[d] * u[d] * u[d];
+    rhob += rAb * (u[d] * (1.0 - 3.0 * RT) - u3 / (phi * phi));
+    ub[d] += rAb * (rho * (1.0 - 3.0 * RT) - 3.0 * rho * u[d] * u[d] / (phi * phi));
+    RTb += rAb * (-3.0 * rho * u[d]);
+    phib += rAb * (2.0 * rho * u3 / (phi * phi * phi));
+    // xi_d = (u_d + Fk_d / (omega rho)) / phi
+    const double xib = cb.xi[d];
+    const double xi = (u[d] + Fk[d] / (omega * rho)) / phi;
+    ub[d] += xib / phi;
+    Fkb[d] += xib / (phi * omega * rho);
+    omegab -= xib * Fk[d] / (phi * omega * omega * rho);
+    rhob -= xib * Fk[d] / (phi * omega * rho * rho);
+    phib -= xib * xi / phi;
+    // Pex_d = RT + v_d^2 + gfac G_d
+    RTb += cb.Pex[d];
+    vb[d] += 2.0 * v[d] * cb.Pex[d];
+    gfacb += cb.Pex[d] * G[d];
+  }
+  double itkb[M], itb[M], Yb[M], iabb[M][M], s0sp[M];
+#pragma unroll
+  for (int a = 0; a < M; ++a) {
+    itkb[a] = cb.itk[a];
+    itb[a] = 0.0;
+    Yb[a] = cb.Y[a];
+    s0sp[a] = cb.pra[a];
+#pragma unroll
+    for (int b = 0; b < M; ++b) iabb[a][b] = cb.iab[a][b];
+  }
+  // Fk_d = - sum_a x_ad itk_a
+#pragma unroll
+  for (int d = 0; d < D; ++d)
+#pragma unroll
+    for (int a = 0; a < M; ++a) {
+      xb[a][d] -= Fkb[d] * itk[a];
+      itkb[a] -= Fkb[d] * x[a][d];
+    }
+  // phirho = phi rho
+  phib += cb.phirho * rho;
+  rhob += cb.phirho * phi;
+  // gfac = (2 - omega) / (2 phi rho omega)
+  omegab += gfacb * (-1.0 / (phi * rho * omega * omega));
+  phib += gfacb * (-gfac / phi);
+  rhob += gfacb * (-gfac / rho);
+  // omega = 1 / (nu / RT + 1/2)
+  RTb += omegab * omega * omega * p.nu / (RT * RT);
+  // v = u / phi, u = s1_M / rho, rho = s0_M / phi
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    ub[d] += vb[d] / phi;
+    phib -= vb[d] * v[d] / phi;
+    s1b[M][d] = ub[d] / rho;
+    rhob -= ub[d] * u[d] / rho;
+  }
+  s0b[M] = rhob / phi;
+  phib -= rhob * rho / phi;
+  // N = x[s][0]; xs_ad = x_ad / s0_a
+#pragma unroll
+  for (int a = 0; a < M; ++a) {
+    if (a == out_species) xb[a][0] += cb.N;
+    if (s0[a] > 0.0) {
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        xb[a][d] += cb.xs[a][d] / s0[a];
+        s0sp[a] -= cb.xs[a][d] * x[a][d] / (s0[a] * s0[a]);
+      }
+    }
+  }
+  // x = A^-1 s1: z = A^-T xb, s1b += z, Ab = - z x^T
+  double z[M][D];
+#pragma unroll
+  for (int a = 0; a < M; ++a)
+#pragma unroll
+    for (int d = 0; d < D; ++d) z[a][d] = xb[a][d];
+  // A^T = U^T L^T: forward with U^T, back with L^T (unit diagonal)
+#pragma unroll
+  for (int k = 0; k < M; ++k)
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      double sacc = z[k][d];
+#pragma unroll
+      for (int r = 0; r < k; ++r) sacc -= LU[r][k] * z[r][d];
+      z[k][d] = sacc / LU[k][k];
+    }
+#pragma unroll
+  for (int k = M - 1; k >= 0; --k)
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      double sacc = z[k][d];
+#pragma unroll
+      for (int r = k + 1; r < M; ++r) sacc -= LU[r][k] * z[r][d];
+      z[k][d] = sacc;
+    }
+#pragma unroll
+  for (int a = 0; a < M; ++a) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) s1b[a][d] = z[a][d];
+#pragma unroll
+    for (int b = 0; b < M; ++b) {
+      double Ab = 0.0;
+#pragma unroll
+      for (int d = 0; d < D; ++d) Ab -= z[a][d] * x[b][d];
+      if (b == a) {
+        itb[a] += 0.5 * Ab;
+        itkb[a] += 0.5 * Ab;
+      } else {
+        Yb[a] -= 0.5 * Ab * iab[a][b];
+        iabb[a][b] -= 0.5 * Ab * Y[a];
+      }
+    }
+  }
+  kfacb = 0.0;
+  double dfacb = 0.0, imb = 0.0;
+#pragma unroll
+  for (int a = 0; a < M; ++a) {
+    if (p.knudsen) kfacb -= itkb[a] * itk[a] / kfac;          // itk = sqrt(R_a T) / kfac
+    itb[a] += cb.beta[a] * 2.0 / ((2.0 + it[a]) * (2.0 + it[a]));
+#pragma unroll
+    for (int b = 0; b < M; ++b) {
+      if (b == a) continue;
+      Yb[b] += itb[a] * iab[a][b];
+      iabb[a][b] += itb[a] * Y[b];
+      dfacb -= iabb[a][b] * iab[a][b] / dfac;
+      imb -= iabb[a][b] * iab[a][b] / im;
+    }
+  }
+  const double Psb = -dfacb * dfac / Ps;
+  double rhoab[M], rsb = 0.0;
+#pragma unroll
+  for (int a = 0; a < M; ++a) {
+    rhoab[a] = Psb * RaT[a];
+    Yb[a] += RTb * RaT[a] + imb * p.inv_m[a];
+  }
+#pragma unroll
+  for (int a = 0; a < M; ++a) {
+    rhoab[a] += Yb[a] / rs;
+    rsb -= Yb[a] * Y[a] / rs;
+  }
+#pragma unroll
+  for (int a = 0; a < M; ++a) {
+    rhoab[a] += rsb;
+    s0b[a] = s0sp[a] + rhoab[a] / phi;
+    phib -= rhoab[a] * rho_a[a] / phi;
+  }
+}
+
 // Psi_c(xi, P) and its partial derivatives.
 __device__ __forceinline__ double dpsi_dxi(int c) { return c == 0 ? 0.0 : (c > 0 ? 0.5 : -0.5); }
 __device__ __forceinline__ double dpsi_dP(int c) { return c == 0 ? -1.0 : 0.5; }
@@ -618,37 +869,20 @@ __global__ __launch_bounds__(64) void k_adj_pass2(const AdjParams<D, M> a) {
     a.jacc[n] += c.N * a.wN;
     cb.N += a.wN;
   }
-  // moment-space adjoints by forward mode through the coefficient map
-  constexpr int NI = (M + 1) * (1 + D) + 2;   // s0, s1, phi, kfac (G is done in pass 1)
-  double ib[NI];
-#pragma unroll 1
-  for (int k = 0; k < NI; ++k) {
-    Dual ds0[M + 1], ds1[M + 1][D], dG[D];
-#pragma unroll
-    for (int l = 0; l <= M; ++l) {
-      ds0[l] = mkd(s0[l], k == l ? 1.0 : 0.0);
-#pragma unroll
-      for (int d = 0; d < D; ++d) ds1[l][d] = mkd(s1[l][d], k == (M + 1) + l * D + d ? 1.0 : 0.0);
-    }
-#pragma unroll
-    for (int d = 0; d < D; ++d) dG[d] = mkd(G[d]);
-    const Dual dphi = mkd(phi, k == NI - 2 ? 1.0 : 0.0);
-    const Dual dkf = mkd(kfac, k == NI - 1 ? 1.0 : 0.0);
-    Coef<Dual, D, M> cd;
-    coef_map<Dual, D, M>(p, ds0, ds1, dG, dphi, dkf, T, a.out_species, cd);
-    ib[k] = coef_dot<Dual, D, M>(cd, cb);
-  }
+  // moment-space adjoints: reverse sweep through the coefficient map
+  double s0b[M + 1], s1b[M + 1][D], phib_c, kfacb;
+  coef_map_reverse<D, M>(p, s0, s1, G, phi, kfac, T, a.out_species, cb, s0b, s1b, phib_c, kfacb);
 #pragma unroll
   for (int l = 0; l <= M; ++l)
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-      double s = fbar[l][i] + ib[l];
+      double s = fbar[l][i] + s0b[l];
 #pragma unroll
-      for (int d = 0; d < D; ++d) s += cdir(i, d) * ib[(M + 1) + l * D + d];
+      for (int d = 0; d < D; ++d) s += cdir(i, d) * s1b[l][d];
       a.lam_cur[(size_t)(l * Q + i) * N + n] = s;
     }
-  a.phibar[n] += ib[NI - 2] + phib;
-  a.kfacbar[n] += ib[NI - 1];
+  a.phibar[n] += phib_c + phib;
+  a.kfacbar[n] += kfacb;
 }
 
 // Initial populations are phi times a phi-free equilibrium: dJ/dphi += Lambda_1 . F_1 / phi.

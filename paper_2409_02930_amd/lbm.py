@@ -319,3 +319,32 @@ def lattice_from_workload(w, stream=None, col_len=None) -> Lattice:
     if w.mech is not None:
         lat.set_mechanism(w.mech)
     return lat
+
+
+def outlet_flux(phi, pore_radius, workload, n_steps, species=0, stream=None):
+    """Outlet-flux objective J(phi, r_p) of `workload` (porosity and pore radius replaced)
+    as a differentiable torch scalar: the forward runs the library, the backward returns
+    the adjoint gradients (lbm_adjoint_outlet_flux).  phi: float64 tensor [N] (any device),
+    pore_radius: float64 scalar tensor (metres)."""
+    import torch
+
+    class _OutletFlux(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, phi_t, rp_t):
+            from dataclasses import replace
+            w = replace(workload, phi=phi_t.detach().double().cpu().numpy(),
+                        pore_radius=float(rp_t.detach().cpu()))
+            lat = lattice_from_workload(w, stream=stream)
+            dev = phi_t.device if phi_t.is_cuda else torch.device("cuda")
+            g = torch.empty(lat.N, dtype=torch.float64, device=dev)
+            J, g, grp = lat.adjoint_outlet_flux(n_steps, species, grad_out=g)
+            lat.close()
+            ctx.save_for_backward(g.to(phi_t.device), torch.tensor(grp, dtype=torch.float64, device=rp_t.device))
+            return torch.tensor(J, dtype=torch.float64, device=phi_t.device)
+
+        @staticmethod
+        def backward(ctx, gJ):
+            g, grp = ctx.saved_tensors
+            return gJ * g, gJ * grp
+
+    return _OutletFlux.apply(phi, pore_radius)

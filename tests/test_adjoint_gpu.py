@@ -97,3 +97,17 @@ def test_adjoint_gradient_matches_oracle_finite_differences(lbm, name):
         assert abs(grp - d) <= 2e-6 * abs(d) + 1e-12 * abs(J) / rp, (grp, d)
     else:
         assert grp == 0.0
+
+
+def test_adjoint_as_torch_autograd_function(lbm):
+    """torch.autograd through the library: gradients equal the C ABI's adjoint output."""
+    import torch
+    w, T = _case("c5_inlet_outflow")
+    phi = torch.tensor(w.phi, dtype=torch.float64, device="cuda", requires_grad=True)
+    rp = torch.tensor(w.pore_radius, dtype=torch.float64, requires_grad=True)
+    J = lbm.outlet_flux(phi, rp, w, T, 0)
+    J.backward()
+    J2, g2, grp2 = _gpu(lbm, w, T)
+    assert float(J) == J2
+    assert np.array_equal(phi.grad.cpu().numpy(), g2)
+    assert float(rp.grad) == grp2

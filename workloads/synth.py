@@ -305,12 +305,17 @@ def config4_column(length: int, phi: float, current_A_cm2: float, seed: int = 4,
                     meta={"current_A_cm2": current_A_cm2})
 
 
-def config5(nx: int = 1024, ny: int = 256, steps: int = 2000, seed: int = 5) -> Workload:
-    """D2Q9 1024x256, 3 species (2, 18, 28), GRF porosity [0.3, 0.6], tortuosity phi^-1/2,
-    r_p 1 micron, 1073 K; inlet X=(0.8,0.1,0.1) at x=0, outflow at x=nx-1, X0 linear."""
+def config5(nx: int = 1024, ny: int = 256, steps: int = 2000, seed: int = 5,
+            porosity: str = "grf") -> Workload:
+    """D2Q9 1024x256, 3 species (2, 18, 28), GRF porosity [0.3, 0.6] (porosity="grf") or
+    uniform 0.45 (porosity="uniform"), tortuosity phi^-1/2, r_p 1 micron, 1073 K;
+    inlet X=(0.8,0.1,0.1) at x=0, outflow at x=nx-1, X0 linear."""
     m = np.array([2.0, 18.0, 28.0])
     m_kg = m * 1e-3
-    phi = gaussian_random_field((ny, nx), 8.0, 0.3, 0.6, seed + 100).reshape(-1)
+    if porosity == "uniform":
+        phi = np.full(nx * ny, 0.45)
+    else:
+        phi = gaussian_random_field((ny, nx), 8.0, 0.3, 0.6, seed + 100).reshape(-1)
     N = nx * ny
     x = np.tile(np.arange(nx), ny)
     s = x / max(nx - 1, 1)
