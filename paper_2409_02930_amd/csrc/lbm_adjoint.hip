@@ -601,20 +601,21 @@ __device__ __forceinline__ void node_inputs(const KParams &p, const Node &nd, do
   for (int d = 0; d < D; ++d) G[d] *= 3.0;
 }
 
-// Adjoint of the population-level collision at fixed coefficients: coefficient
-// adjoints (cb) and the explicit population adjoints (fbar).
-template <int D, int M>
-__device__ __forceinline__ void collision_adjoint(const KParams &p, double T, const double (&f)[M + 1][LQ<D>::Q],
-                                                  const double (&lp)[M + 1][LQ<D>::Q], const Coef<double, D, M> &c,
-                                                  Coef<double, D, M> &cb, double (&fbar)[M + 1][LQ<D>::Q]) {
+// Adjoint of the population-level collision at fixed coefficients: the
+// coefficient adjoints cb.  Directions outermost, so only per-species values of
+// one direction are live; lam(l, i) reads lambda'_t, dotf[l] = sum_i lambda'_li f_li.
+template <int D, int M, class Lam>
+__device__ __forceinline__ void collision_adjoint(const KParams &p, double T, const Lam &lam,
+                                                  const double (&dotf)[M + 1], const Coef<double, D, M> &c,
+                                                  Coef<double, D, M> &cb) {
   constexpr int Q = LQ<D>::Q;
   double RaT[M];
 #pragma unroll
   for (int a = 0; a < M; ++a) RaT[a] = p.theta_ref * p.mmin_over_m[a] * (T * p.inv_T_ref);
-  // zero the coefficient adjoints
 #pragma unroll
   for (int a = 0; a < M; ++a) {
-    cb.beta[a] = cb.Y[a] = cb.itk[a] = cb.pra[a] = 0.0;
+    cb.beta[a] = -2.0 * dotf[a];                      // d f'/d beta has -2 f
+    cb.Y[a] = cb.itk[a] = cb.pra[a] = 0.0;
 #pragma unroll
     for (int b = 0; b < M; ++b) cb.iab[a][b] = 0.0;
 #pragma unroll
@@ -622,112 +623,72 @@ __device__ __forceinline__ void collision_adjoint(const KParams &p, double T, co
   }
 #pragma unroll
   for (int d = 0; d < D; ++d) cb.v[d] = cb.xi[d] = cb.Pex[d] = cb.rA[d] = 0.0;
-  cb.omega = cb.gfac = cb.phirho = cb.N = 0.0;
-
-  double v[D];
+  cb.omega = -dotf[M];
+  cb.gfac = cb.phirho = cb.N = 0.0;
+  bool pos[M];
 #pragma unroll
-  for (int d = 0; d < D; ++d) v[d] = c.v[d];
-  // dlt_ci = feq_ci - fst_ci for every species and direction
-  double dlt[M][Q];
+  for (int a = 0; a < M; ++a) pos[a] = c.pra[a] > 0.0;
+#pragma unroll 1
+  for (int i = 0; i < Q; ++i) {
+    double E[M], S[M], K[M], dlt[M], dE[M][D], dS[M][D], dltb[M];
 #pragma unroll
-  for (int a = 0; a < M; ++a) {
-    const bool pos = c.pra[a] > 0.0;
-    double xs[D];
+    for (int a = 0; a < M; ++a) {
+      double xs[D];
 #pragma unroll
-    for (int d = 0; d < D; ++d) xs[d] = c.xs[a][d];
+      for (int d = 0; d < D; ++d) xs[d] = c.xs[a][d];
+      E[a] = psiv_prod<D>(i, c.v, RaT[a], dE[a]);
+      S[a] = 0.0;
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      const double E = psiv_prod<D>(i, v, RaT[a], nullptr);
-      const double Sx = pos ? psiv_prod<D>(i, xs, RaT[a], nullptr) : 0.0;
-      dlt[a][i] = c.pra[a] * (E - Sx);
+      for (int d = 0; d < D; ++d) dS[a][d] = 0.0;
+      if (pos[a]) S[a] = psiv_prod<D>(i, xs, RaT[a], dS[a]);
+      K[a] = 1.0;
+#pragma unroll
+      for (int d = 0; d < D; ++d) K[a] *= psi1(cdir(i, d), 0.0, RaT[a]);
+      dlt[a] = c.pra[a] * (E[a] - S[a]);
+      dltb[a] = 0.0;
     }
-  }
-  // species lattices
-  double dltb[M][Q];
 #pragma unroll
-  for (int a = 0; a < M; ++a)
-#pragma unroll
-    for (int i = 0; i < Q; ++i) dltb[a][i] = 0.0;
-#pragma unroll
-  for (int a = 0; a < M; ++a) {
-    const bool pos = c.pra[a] > 0.0;
-    double xs[D];
-#pragma unroll
-    for (int d = 0; d < D; ++d) xs[d] = c.xs[a][d];
-    const double beta = c.beta[a], Ya = c.Y[a], itk = c.itk[a];
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      double dE[D], dS[D];
-      const double E = psiv_prod<D>(i, v, RaT[a], dE);
-      const double Sx = pos ? psiv_prod<D>(i, xs, RaT[a], dS) : 0.0;
-      double K = 1.0;
-#pragma unroll
-      for (int d = 0; d < D; ++d) K *= psi1(cdir(i, d), 0.0, RaT[a]);
-      const double feq = c.pra[a] * E, fst = pos ? c.pra[a] * Sx : 0.0, fk = c.pra[a] * K;
+    for (int a = 0; a < M; ++a) {
+      const double beta = c.beta[a], Ya = c.Y[a], itk = c.itk[a];
+      const double feq = c.pra[a] * E[a], fst = pos[a] ? c.pra[a] * S[a] : 0.0, fk = c.pra[a] * K[a];
       double cross = 0.0;
 #pragma unroll
-      for (int b = 0; b < M; ++b) cross += c.iab[a][b] * dlt[b][i];
+      for (int b = 0; b < M; ++b) cross += c.iab[a][b] * dlt[b];
       const double Fai = Ya * cross + itk * (fst - fk);
-      const double lam = lp[a][i];
-      fbar[a][i] = lam * (1.0 - 2.0 * beta);
-      cb.beta[a] += lam * (2.0 * (feq - f[a][i]) + Fai);
-      const double Fb = (beta - 1.0) * lam;
+      const double l = lam(a, i);
+      cb.beta[a] += l * (2.0 * feq + Fai);
+      const double Fb = (beta - 1.0) * l;
       cb.Y[a] += Fb * cross;
 #pragma unroll
       for (int b = 0; b < M; ++b) {
-        cb.iab[a][b] += Fb * Ya * dlt[b][i];
-        dltb[b][i] += Fb * Ya * c.iab[a][b];
+        cb.iab[a][b] += Fb * Ya * dlt[b];
+        dltb[b] += Fb * Ya * c.iab[a][b];
       }
       cb.itk[a] += Fb * (fst - fk);
-      const double feqb = 2.0 * beta * lam;
-      const double fstb = Fb * itk;
-      const double fkb = -Fb * itk;
-      cb.pra[a] += feqb * E + (pos ? fstb * Sx : 0.0) + fkb * K;
+      const double feqb = 2.0 * beta * l, fstb = Fb * itk, fkb = -Fb * itk;
+      cb.pra[a] += feqb * E[a] + (pos[a] ? fstb * S[a] : 0.0) + fkb * K[a];
 #pragma unroll
       for (int d = 0; d < D; ++d) {
-        cb.v[d] += feqb * c.pra[a] * dE[d];
-        if (pos) cb.xs[a][d] += fstb * c.pra[a] * dS[d];
+        cb.v[d] += feqb * c.pra[a] * dE[a][d];
+        cb.xs[a][d] += fstb * c.pra[a] * dS[a][d];
       }
     }
-  }
-  // the cross-term differences dlt_bi = pra_b (E_bi - S_bi)
+    // the cross-term differences dlt_b = pra_b (E_b - S_b)
 #pragma unroll
-  for (int b = 0; b < M; ++b) {
-    const bool pos = c.pra[b] > 0.0;
-    double xs[D];
-#pragma unroll
-    for (int d = 0; d < D; ++d) xs[d] = c.xs[b][d];
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      const double g = dltb[b][i];
-      if (g == 0.0) continue;
-      double dE[D], dS[D];
-      const double E = psiv_prod<D>(i, v, RaT[b], dE);
-      const double Sx = pos ? psiv_prod<D>(i, xs, RaT[b], dS) : 0.0;
-      cb.pra[b] += g * (E - Sx);
+    for (int b = 0; b < M; ++b) {
+      cb.pra[b] += dltb[b] * (E[b] - S[b]);
 #pragma unroll
       for (int d = 0; d < D; ++d) {
-        cb.v[d] += g * c.pra[b] * dE[d];
-        if (pos) cb.xs[b][d] -= g * c.pra[b] * dS[d];
+        cb.v[d] += dltb[b] * c.pra[b] * dE[b][d];
+        cb.xs[b][d] -= dltb[b] * c.pra[b] * dS[b][d];
       }
     }
-  }
-  // momentum lattice
-#pragma unroll
-  for (int i = 0; i < Q; ++i) {
+    // momentum lattice
     double X, dX[D], dP[D];
-    double xi[D], P[D];
-#pragma unroll
-    for (int d = 0; d < D; ++d) {
-      xi[d] = c.xi[d];
-      P[d] = c.Pex[d];
-    }
-    psi_prod<D>(i, xi, P, X, dX, dP);
-    const double fex = c.phirho * X;
-    const double lam = lp[M][i];
-    fbar[M][i] = lam * (1.0 - c.omega);
-    cb.omega += lam * (fex - f[M][i]);
-    const double fexb = c.omega * lam;
+    psi_prod<D>(i, c.xi, c.Pex, X, dX, dP);
+    const double l = lam(M, i);
+    cb.omega += l * c.phirho * X;
+    const double fexb = c.omega * l;
     cb.phirho += fexb * X;
 #pragma unroll
     for (int d = 0; d < D; ++d) {
@@ -800,18 +761,59 @@ __global__ __launch_bounds__(64) void k_adj_pass2(const AdjParams<D, M> a) {
   if (n >= p.N) return;
   const int N = p.N;
   const Node nd = node_of(p, n);
-  double f[M + 1][Q], s0[M + 1], s1[M + 1][D], G[D], phi;
-  node_inputs<D, M>(p, nd, f, s0, s1, G, phi);
+  const double *lamp = a.lamp;
+  auto lam = [&](int l, int i) { return lamp[(size_t)(l * Q + i) * N + n]; };
+  // pull, moments and sum_i lambda'_li f_li; the populations are not kept
+  const double phi = p.phi[n];
+  double s0[M + 1], s1[M + 1][D], dotf[M + 1], G[D];
+  {
+    const bool inlet_node = is_inlet_node(p, nd);
+    double vbp[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) vbp[d] = inlet_node ? p.rec_prev[(size_t)n * kRec + d] : 0.0;
+    const PullGeo<D> geo = pull_geo<D>(p, nd);
+#pragma unroll 1
+    for (int l = 0; l <= M; ++l) {
+      double f[Q];
+      pull_lattice<D, M>(p, nd, geo, l, phi, vbp, inlet_node, f);
+      double t0 = 0.0, t1[D], df = 0.0;
+#pragma unroll
+      for (int d = 0; d < D; ++d) t1[d] = 0.0;
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        t0 += f[i];
+#pragma unroll
+        for (int d = 0; d < D; ++d) t1[d] += cdir(i, d) * f[i];
+        df += lam(l, i) * f[i];
+      }
+#pragma unroll
+      for (int ll = 0; ll <= M; ++ll)               // select without indexing by the run-time l
+        if (ll == l) {
+          s0[ll] = t0;
+          dotf[ll] = df;
+#pragma unroll
+          for (int d = 0; d < D; ++d) s1[ll][d] = t1[d];
+        }
+    }
+#pragma unroll
+    for (int d = 0; d < D; ++d) G[d] = 0.0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      if (cnorm2<D>(i) == 0) continue;
+      const int m = nb_node<D>(p, nd, i);
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        const int cc = cdir(i, d);
+        if (cc != 0) G[d] += wdir<D>(i) * cc * p.rA[(size_t)d * N + m];
+      }
+    }
+#pragma unroll
+    for (int d = 0; d < D; ++d) G[d] *= 3.0;
+  }
   const double kfac = p.kfac[n], T = p.Tfield[n];
-  double lp[M + 1][Q];
-#pragma unroll
-  for (int l = 0; l <= M; ++l)
-#pragma unroll
-    for (int i = 0; i < Q; ++i) lp[l][i] = a.lamp[(size_t)(l * Q + i) * N + n];
   Coef<double, D, M> c, cb;
   coef_map<double, D, M>(p, s0, s1, G, phi, kfac, T, a.out_species, c);
-  double fbar[M + 1][Q];
-  collision_adjoint<D, M>(p, T, f, lp, c, cb, fbar);
+  collision_adjoint<D, M>(p, T, lam, dotf, c, cb);
 
   // rA_t(x) feeds G of the nodes whose stencil reaches x
 #pragma unroll
@@ -873,14 +875,19 @@ __global__ __launch_bounds__(64) void k_adj_pass2(const AdjParams<D, M> a) {
   double s0b[M + 1], s1b[M + 1][D], phib_c, kfacb;
   coef_map_reverse<D, M>(p, s0, s1, G, phi, kfac, T, a.out_species, cb, s0b, s1b, phib_c, kfacb);
 #pragma unroll
-  for (int l = 0; l <= M; ++l)
+  for (int l = 0; l <= M; ++l) {
+    double keep = 1.0 - c.omega;                      // explicit f term of the collision
+#pragma unroll
+    for (int aa = 0; aa < M; ++aa)
+      if (aa == l) keep = 1.0 - 2.0 * c.beta[aa];
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-      double s = fbar[l][i] + s0b[l];
+      double s = lam(l, i) * keep + s0b[l];
 #pragma unroll
       for (int d = 0; d < D; ++d) s += cdir(i, d) * s1b[l][d];
       a.lam_cur[(size_t)(l * Q + i) * N + n] = s;
     }
+  }
   a.phibar[n] += phib_c + phib;
   a.kfacbar[n] += kfacb;
 }
