@@ -162,6 +162,8 @@ KParams base_params(const lbm_ctx *c) {
     p.uf[a] = c->uf_lat[a];
   }
   memcpy(p.Dref, c->Dref, sizeof(p.Dref));
+  for (int a = 0; a < c->M; ++a)
+    for (int b = 0; b < c->M; ++b) p.imD[a * LBM_MMAX + b] = (1.0 / c->m[b]) / c->Dref[a * LBM_MMAX + b];
   p.inlet[0] = c->inlet[0];
   p.inlet[1] = c->inlet[1];
   p.phi = c->phi;

@@ -39,6 +39,7 @@ struct KParams {
   double mmin_over_m[LBM_MMAX];   // m_min / m_a
   double inv_m[LBM_MMAX];         // 1 / m_a
   double Dref[LBM_MMAX * LBM_MMAX];
+  double imD[LBM_MMAX * LBM_MMAX];  // inv_m[b] / Dref[a][b]
   double cv[LBM_MMAX], uf[LBM_MMAX];   // lattice units (per kelvin, absolute)
   InletState inlet[2];            // x = 0 and x = nx - 1
   // populations [lattice][direction][node]

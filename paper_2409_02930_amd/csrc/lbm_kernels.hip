@@ -240,32 +240,38 @@ struct SpeciesShared {
 template <int D, int M>
 struct NodeState {
   double rho_a[M], Y[M], RaT[M];
-  double rho, u[D], v[D], im, T, RT, Ps, dfac;
+  double rho, u[D], v[D], im, T, RT, Ps;
+  double g;                   // 1 / (dfac im): 1/tau_ab = R_a T g / (m_b D_ab^ref)
 };
 
+// Reciprocals replace the per-species divisions (fewer dependent chains, fewer
+// live registers); the results differ from the divided forms by rounding only.
 template <int D, int M, bool ENERGY>
 __device__ __forceinline__ void node_state(const KParams &p, const SpeciesShared<D, M, ENERGY> &sh, int lane,
                                            double phi, double Tfield, NodeState<D, M> &s) {
-  s.rho = sh.m0[M][lane] / phi;
+  const double iphi = 1.0 / phi;
+  s.rho = sh.m0[M][lane] * iphi;
+  const double irho = 1.0 / s.rho;
 #pragma unroll
   for (int d = 0; d < D; ++d) {
-    s.u[d] = sh.u.s.m1[M][d][lane] / s.rho;
-    s.v[d] = s.u[d] / phi;
+    s.u[d] = sh.u.s.m1[M][d][lane] * irho;
+    s.v[d] = s.u[d] * iphi;
   }
   double rs = 0.0;
 #pragma unroll
   for (int a = 0; a < M; ++a) {
-    s.rho_a[a] = sh.m0[a][lane] / phi;
+    s.rho_a[a] = sh.m0[a][lane] * iphi;
     rs += s.rho_a[a];
   }
+  const double irs = 1.0 / rs;
   s.im = 0.0;
 #pragma unroll
   for (int a = 0; a < M; ++a) {
-    s.Y[a] = s.rho_a[a] / rs;
+    s.Y[a] = s.rho_a[a] * irs;
     s.im += s.Y[a] * p.inv_m[a];
   }
   if constexpr (ENERGY) {
-    const double E = sh.m0[M + 1][lane] / (phi * s.rho);
+    const double E = sh.m0[M + 1][lane] * iphi * irho;
     double v2 = 0.0;
 #pragma unroll
     for (int d = 0; d < D; ++d) v2 += s.v[d] * s.v[d];
@@ -288,7 +294,8 @@ __device__ __forceinline__ void node_state(const KParams &p, const SpeciesShared
     s.Ps += s.rho_a[a] * s.RaT[a];
   }
   const double Tr = s.T * p.inv_T_ref;
-  s.dfac = Tr * sqrt(Tr) / s.Ps;                      // D_ab(T, P) = D_ab^ref (T/T_ref)^1.5 / P
+  // D_ab(T, P) = D_ab^ref (T/T_ref)^1.5 / P  ->  1/tau_ab = R_a T P / ((T/T_ref)^1.5 m_b D_ab^ref im)
+  s.g = s.Ps / (Tr * sqrt(Tr) * s.im);
 }
 
 // Second-order species momenta (eq transform1 with the Knudsen terms): solves
@@ -304,12 +311,13 @@ __device__ __forceinline__ void species_momenta(const SpeciesShared<D, M, ENERGY
 #pragma unroll
     for (int d = 0; d < D; ++d) x[a][d] = sh.u.s.m1[a][d][lane];
   }
+  double inv[M];
 #pragma unroll
   for (int k = 0; k < M; ++k) {
-    const double inv = 1.0 / A[k][k];
+    inv[k] = 1.0 / A[k][k];
 #pragma unroll
     for (int r = k + 1; r < M; ++r) {
-      const double l = A[r][k] * inv;
+      const double l = A[r][k] * inv[k];
 #pragma unroll
       for (int c = k + 1; c < M; ++c) A[r][c] -= l * A[k][c];
 #pragma unroll
@@ -323,7 +331,7 @@ __device__ __forceinline__ void species_momenta(const SpeciesShared<D, M, ENERGY
       double sacc = x[k][d];
 #pragma unroll
       for (int c = k + 1; c < M; ++c) sacc -= A[k][c] * x[c][d];
-      x[k][d] = sacc / A[k][k];
+      x[k][d] = sacc * inv[k];
     }
   }
 }
@@ -401,24 +409,19 @@ __global__ __launch_bounds__(64 * (M + 1 + (ENERGY ? 1 : 0))) void k_species(con
     node_state<D, M, ENERGY>(p, sh, lane, phi, Tfield, s);
     if (w < M) {
       const int a = w;
-      double Dr[M];
 #pragma unroll
       for (int c = 0; c < M; ++c) {              // select without indexing by the run-time a
         if (c == a) { RaTa = s.RaT[c]; Ya = s.Y[c]; }
       }
-#pragma unroll
-      for (int c = 0; c < M; ++c) Dr[c] = p.Dref[a * LBM_MMAX + c];
+      const double rg = RaTa * s.g;
       double it = 0.0;
 #pragma unroll
       for (int c = 0; c < M; ++c) {
-        iab[c] = 0.0;
-        if (c != a) {
-          iab[c] = RaTa / (Dr[c] * s.dfac * (s.im / p.inv_m[c]));   // 1/tau_ab (eq tauab)
-          it += s.Y[c] * iab[c];
-        }
+        iab[c] = (c != a) ? rg * p.imD[a * LBM_MMAX + c] : 0.0;   // 1/tau_ab (eq tauab)
+        it += s.Y[c] * iab[c];
       }
       beta = it / (2.0 + it);                   // eq betaa
-      itk_a = p.knudsen ? RaTa / (p.kfac[n] * sqrt(RaTa)) : 0.0;   // eq tauak
+      itk_a = p.knudsen ? sqrt(RaTa) / p.kfac[n] : 0.0;   // eq tauak: R_a T / (kfac sqrt(R_a T))
 #pragma unroll
       for (int c = 0; c < M; ++c)
         sh.u.s.A[a][c][lane] = (c == a) ? 1.0 + 0.5 * it + 0.5 * itk_a : -0.5 * Ya * iab[c];
@@ -438,10 +441,11 @@ __global__ __launch_bounds__(64 * (M + 1 + (ENERGY ? 1 : 0))) void k_species(con
     double te[D][3], ts[D][3], tk[D][3];
     const double pra = sh.m0[a][lane];            // phi rho_a
     const bool pos = pra > 0.0;
+    const double ipra = pos ? 1.0 / pra : 0.0;
     if (valid) {
 #pragma unroll
       for (int d = 0; d < D; ++d) {
-        const double xs = pos ? sh.x[a][d][lane] / pra : 0.0;   // j_a / (phi rho_a)
+        const double xs = sh.x[a][d][lane] * ipra;   // j_a / (phi rho_a), 0 when rho_a = 0
         const double Pe = s.v[d] * s.v[d] + RaTa, Ps = xs * xs + RaTa;
         te[d][0] = 0.5 * (-s.v[d] + Pe); te[d][1] = 1.0 - Pe; te[d][2] = 0.5 * (s.v[d] + Pe);
         ts[d][0] = 0.5 * (-xs + Ps);     ts[d][1] = 1.0 - Ps; ts[d][2] = 0.5 * (xs + Ps);
@@ -491,8 +495,8 @@ __global__ __launch_bounds__(64 * (M + 1 + (ENERGY ? 1 : 0))) void k_species(con
         double fk = 0.0;
 #pragma unroll
         for (int c = 0; c < M; ++c) fk -= x[c][d] * itk[c];   // eq netKnudsenForce
-        p.rA[(size_t)d * N + n] =
-            s.rho * s.u[d] * (1.0 - 3.0 * s.RT) - s.rho * s.u[d] * s.u[d] * s.u[d] / (phi * phi);
+        p.rA[(size_t)d * N + n] =                    // rho u (1 - 3RT) - rho u^3 / phi^2, with v = u / phi
+            s.rho * s.u[d] * (1.0 - 3.0 * s.RT) - s.rho * s.u[d] * s.v[d] * s.v[d];
         if (p.knudsen) p.rFk[(size_t)d * N + n] = fk;
         if (p.need_v) p.rec_cur[(size_t)n * kRec + d] = s.v[d];
       }

@@ -1,0 +1,138 @@
+"""Parity at the benchmark sizes, in the configuration bench.py times.
+
+After k steps a node's state depends only on the initial state within radius 2k
+(one node for the pull and one for the gradient stencil per step), and the
+surface chemistry is local.  So for sampled nodes the oracle reproduces the
+full-size run exactly on a small periodic patch of radius R >= 2k + 1 cut from
+the full-size initial fields around the node: its edges are wrong, the centre is
+not.  C3 (D3Q27 256x128x128, chemistry, the default generated chemistry kernel)
+and C5 (D2Q9 1024x256, inlet/outflow, interior samples) are checked this way;
+the 64 C4 columns are checked whole for two columns of the batched run.
+"""
+import sys
+from dataclasses import replace
+
+import numpy as np
+import pytest
+
+from oracle.lbm_oracle import Oracle
+from workloads import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-11
+FLOOR = {"u": 1e-3, "j_a": 1e-2}
+
+
+@pytest.fixture(scope="module")
+def lbm():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2409_02930_amd import lbm as _lbm
+    return _lbm
+
+
+def _log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _patch(w, center, R):
+    """Periodic patch of radius R around `center` (x, y, z) cut from workload w."""
+    n = 2 * R + 1
+    off = np.arange(-R, R + 1)
+    xs = (center[0] + off) % w.nx
+    ys = (center[1] + off) % w.ny if w.lattice > 1 else np.zeros(1, int)
+    zs = (center[2] + off) % w.nz if w.lattice > 2 else np.zeros(1, int)
+    idx = (xs[None, None, :] + w.nx * (ys[None, :, None] + w.ny * zs[:, None, None])).reshape(-1)
+    pw = replace(w, nx=n, ny=n if w.lattice > 1 else 1, nz=n if w.lattice > 2 else 1,
+                 X0=w.X0[:, idx], P0=w.P0[idx], T0=w.T0[idx], phi=w.phi[idx], tort=w.tort[idx],
+                 bc_lo=synth.BC_PERIODIC, bc_hi=synth.BC_PERIODIC, inlet_lo_X=None, inlet_hi_X=None)
+    c = R + n * (R + (n * R if w.lattice > 2 else 0)) if w.lattice > 1 else R
+    return pw, c
+
+
+def _sample_compare(got_at, ref_at, keys):
+    errs = {}
+    for k in keys:
+        g = np.asarray(got_at[k], dtype=np.float64)
+        r = np.asarray(ref_at[k], dtype=np.float64)
+        scale = max(float(np.max(np.abs(r))), FLOOR.get(k, 0.0))
+        errs[k] = 0.0 if scale == 0 else float(np.max(np.abs(g - r)) / scale)
+        assert np.all(np.isfinite(g)), k
+    bad = {k: e for k, e in errs.items() if not e <= TOL}
+    assert not bad, f"errors above {TOL}: {bad} (all {errs})"
+    return errs
+
+
+def _field_at(f, n):
+    out = {}
+    for k, v in f.items():
+        a = np.asarray(v)
+        out[k] = a[..., n]
+    return out
+
+
+def _run_sampled(lbm, w, steps, centers, keys):
+    lat = lbm.lattice_from_workload(w)
+    lat.step(steps)
+    f = lat.fields()
+    d = lat.diagnostics(check=False)
+    lat.close()
+    assert d["n_nonfinite"] == 0
+    got, ref = {k: [] for k in keys}, {k: [] for k in keys}
+    R = 2 * steps + 1
+    for ctr in centers:
+        n = ctr[0] + w.nx * (ctr[1] + w.ny * ctr[2])
+        pw, c = _patch(w, ctr, R)
+        o = Oracle(pw)
+        o.step(steps)
+        m = o.moments()
+        for k in keys:
+            got[k].append(_field_at(f, n)[k])
+            ref[k].append(np.asarray(m[k])[..., c])
+    errs = _sample_compare(got, ref, keys)
+    _log(f"{w.name}: {len(centers)} sampled nodes after {steps} steps, errors {errs}")
+
+
+def test_c3_full_size_sampled_nodes(lbm):
+    w = synth.config3()
+    rng = np.random.default_rng(11)
+    centers = [(0, 0, 0), (w.nx - 1, w.ny - 1, w.nz - 1), (128, 64, 64)]
+    centers += [tuple(int(v) for v in (rng.integers(w.nx), rng.integers(w.ny), rng.integers(w.nz))) for _ in range(5)]
+    # 3 steps: the first runs the generic chemistry kernel, the next two the generated one
+    _run_sampled(lbm, w, 3, centers, ("rho_a", "u", "P", "X", "j_a", "rho", "theta"))
+
+
+def test_c5_full_size_sampled_interior_nodes(lbm):
+    w = synth.config5()
+    rng = np.random.default_rng(12)
+    centers = [(int(rng.integers(40, w.nx - 40)), int(rng.integers(w.ny)), 0) for _ in range(8)]
+    _run_sampled(lbm, w, 6, centers, ("rho_a", "u", "P", "X", "j_a", "rho"))
+
+
+def test_c4_full_batched_columns_vs_oracle(lbm):
+    lengths, phis, currents = synth.config4_columns()
+    cols = [synth.config4_column(int(L), float(p), float(i)) for L, p, i in zip(lengths, phis, currents)]
+    cat = lambda k: np.concatenate([getattr(c, k) for c in cols], axis=-1)
+    w0 = cols[0]
+    lat = lbm.Lattice(1, int(sum(lengths)), 1, 1, w0.molar_mass, w0.D_ref_lat, cat("X0"), cat("T0"), cat("P0"),
+                      T_ref=w0.T_ref, bc_lo=w0.bc_lo, bc_hi=w0.bc_hi, inlet_lo_X=w0.inlet_lo_X,
+                      inlet_T=w0.inlet_T, col_len=[int(L) for L in lengths])
+    lat.set_porous_field(cat("phi"), cat("tort"), w0.pore_radius)
+    lat.set_faradaic_source(cat("faradaic_rate"), 0, 1)
+    lat.set_mechanism(w0.mech)
+    steps = 12
+    lat.step(steps)
+    f = lat.fields()
+    lat.close()
+    offs = np.concatenate([[0], np.cumsum(lengths)])
+    for c_idx in (0, int(np.argmax(lengths)), len(cols) - 1):
+        c = cols[c_idx]
+        o = Oracle(c)
+        o.step(steps)
+        m = o.moments()
+        sl = slice(int(offs[c_idx]), int(offs[c_idx + 1]))
+        got = {k: np.asarray(f[k])[..., sl] for k in ("rho_a", "u", "P", "X", "j_a", "theta")}
+        errs = _sample_compare(got, {k: m[k] for k in got}, got.keys())
+        _log(f"c4 column {c_idx} (L={c.nx}, i={c.meta['current_A_cm2']:.2f} A/cm2): {errs}")
