@@ -68,6 +68,7 @@ def kernel_bytes_per_node(w, kernel):
     if kernel == "species":
         rd = (M + 1 + E) * Q + 3                      # species + momentum (+ energy) pops, phi, kfac, T
         wr = M * Q + D + 1 + (D if w.pore_radius and np.isfinite(w.pore_radius) else 0)
+        rd += (M + D) if chem else 0                  # previous step's source and velocity (source populations)
         wr += (M + D) if chem else 0                  # chemistry input densities, node velocity
         wr += (1 + M + D) if E else 0
         return 8 * (rd + wr)
@@ -77,8 +78,6 @@ def kernel_bytes_per_node(w, kernel):
         return 8 * (rd + wr)
     if kernel == "chem":
         return 8 * (M + 2 + K + K + M + 1)          # rho_a, T, phi, theta in/out, source, sum
-    if kernel == "source":
-        return 8 * (2 * M * Q + M + D + 1)         # species pops read + written, record, T
     raise ValueError(kernel)
 
 
@@ -278,11 +277,10 @@ def main():
 
     ms_step = wall * 1e3 / args.steps
     mlups = w.N * args.steps / wall / 1e6
-    kernels = {"species": tk["species_ms"], "chem": tk["chem_ms"], "source": tk["source_ms"],
-               "mixture": tk["mixture_ms"]}
+    kernels = {"species": tk["species_ms"], "chem": tk["chem_ms"], "mixture": tk["mixture_ms"]}
     per_kernel = {}
     for k, ms in kernels.items():
-        if ms <= 0 or (k in ("chem", "source") and w.mech is None and w.faradaic_rate is None):
+        if ms <= 0 or (k == "chem" and w.mech is None and w.faradaic_rate is None):
             continue
         b = kernel_bytes_per_node(w, k) * w.N
         per_kernel[k] = {"ms": ms, "GBps": b / (ms * 1e-3) / 1e9}

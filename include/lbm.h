@@ -215,7 +215,10 @@ int lbm_get_diagnostics(lbm_ctx *ctx, lbm_diag *out);
 /* Kernel time of the last lbm_step call's launches, measured with HIP events
  * on the configured stream: total ms of the call and, over its last <= 64
  * steps, the per-step averages of the species kernel, the chemistry kernel,
- * the source kernel and the mixture kernel.  Enabled with lbm_set_timing(ctx, 1). */
+ * the source pass and the mixture kernel.  The reaction populations of a step
+ * (eq fsourceHetero) are added inside the next species kernel's pull, so
+ * source_ms is the empty interval between the chemistry and mixture launches
+ * (kept for a stable signature).  Enabled with lbm_set_timing(ctx, 1). */
 int lbm_set_timing(lbm_ctx *ctx, int32_t enable);
 int lbm_get_timing(lbm_ctx *ctx, double *total_ms, double *species_ms, double *chem_ms,
                    double *source_ms, double *mixture_ms);

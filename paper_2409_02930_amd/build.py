@@ -14,6 +14,11 @@ HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function",
+    # The kernels take their parameter block by value and read it from many
+    # unrolled places; past LLVM's default of 300 such reads instcombine stops
+    # forwarding them to the kernel-argument segment and copies the whole block
+    # to scratch memory (about 1 KB per lane).
+    "-mllvm", "-instcombine-max-copied-from-constant-users=4096",
 ]
 
 

@@ -377,7 +377,7 @@ struct Gen {
     o("  }");
     o("  double ssum = 0.0;");
     for (int a = 0; a < M; ++a) {
-      o("  rec[(size_t)n * KREC + KRECSRC + %d] = src[%d];", a, a);
+      o("  rec[(size_t)(KRECSRC + %d) * N + n] = src[%d];", a, a);
       o("  ssum += src[%d];", a);
     }
     o("  srcsum[n] = ssum;");

@@ -570,11 +570,11 @@ __device__ __forceinline__ void node_inputs(const KParams &p, const Node &nd, do
   const bool inlet_node = is_inlet_node(p, nd);
   double vb[D];
 #pragma unroll
-  for (int d = 0; d < D; ++d) vb[d] = inlet_node ? p.rec_prev[(size_t)n * kRec + d] : 0.0;
+  for (int d = 0; d < D; ++d) vb[d] = inlet_node ? p.rec_prev[(size_t)d * p.N + n] : 0.0;
   const PullGeo<D> geo = pull_geo<D>(p, nd);
 #pragma unroll
   for (int l = 0; l <= M; ++l) {
-    pull_lattice<D, M>(p, nd, geo, l, phi, vb, inlet_node, f[l]);
+    pull_lattice<D, M, false>(p, nd, geo, l, phi, vb, inlet_node, f[l]);
     s0[l] = 0.0;
 #pragma unroll
     for (int d = 0; d < D; ++d) s1[l][d] = 0.0;
@@ -770,12 +770,12 @@ __global__ __launch_bounds__(64) void k_adj_pass2(const AdjParams<D, M> a) {
     const bool inlet_node = is_inlet_node(p, nd);
     double vbp[D];
 #pragma unroll
-    for (int d = 0; d < D; ++d) vbp[d] = inlet_node ? p.rec_prev[(size_t)n * kRec + d] : 0.0;
+    for (int d = 0; d < D; ++d) vbp[d] = inlet_node ? p.rec_prev[(size_t)d * p.N + n] : 0.0;
     const PullGeo<D> geo = pull_geo<D>(p, nd);
 #pragma unroll 1
     for (int l = 0; l <= M; ++l) {
       double f[Q];
-      pull_lattice<D, M>(p, nd, geo, l, phi, vbp, inlet_node, f);
+      pull_lattice<D, M, false>(p, nd, geo, l, phi, vbp, inlet_node, f);
       double t0 = 0.0, t1[D], df = 0.0;
 #pragma unroll
       for (int d = 0; d < D; ++d) t1[d] = 0.0;

@@ -178,6 +178,14 @@ KParams base_params(const lbm_ctx *c) {
   return p;
 }
 
+// The last completed step wrote species sources into its records that the
+// stored populations do not hold yet: every pull of a species lattice adds
+// them.  Records of steps without chemistry hold zero sources; freshly built
+// populations (first_step) have none to take.
+int src_pending(const lbm_ctx *c) {
+  return (c->has_mech || c->has_faradaic) && !c->first_step ? 1 : 0;
+}
+
 bool needs_v(const lbm_ctx *c) {
   return c->has_mech || c->has_faradaic || c->bc_lo == BC_INLET || c->bc_hi == BC_INLET;
 }
@@ -188,6 +196,7 @@ void fill_prev(const lbm_ctx *c, KParams &p) {
   const int q_last = (int)((c->steps_done + 1) & 1);   // parity of the last completed step
   p.pin = c->pop[c->cur];
   p.first_step = c->first_step;
+  p.src_prev = src_pending(c);
   p.rec_prev = c->rec[q_last];
   p.T_prev = c->energy ? c->T[q_last] : c->Tfield;
 }
@@ -440,6 +449,7 @@ int enqueue_step(lbm_ctx *c, int record_slot) {
   const int chem = c->has_mech || c->has_faradaic;
   p.chem = chem;
   p.need_v = needs_v(c) ? 1 : 0;
+  p.src_prev = src_pending(c);
   p.rec_prev = c->rec[1 - q];
   p.rec_cur = c->rec[q];
   p.T_prev = c->energy ? c->T[1 - q] : c->Tfield;
@@ -471,8 +481,7 @@ int enqueue_step(lbm_ctx *c, int record_slot) {
       HIPCHK(c, launch_chem(cp, c->stream));
   }
   if (ev) HIPCHK(c, hipEventRecord(ev[2], c->stream));
-  if (chem) HIPCHK(c, launch_source(c->dim, p, c->stream));
-  if (ev) HIPCHK(c, hipEventRecord(ev[3], c->stream));
+  if (ev) HIPCHK(c, hipEventRecord(ev[3], c->stream));   // no separate source pass (added at the pull)
   HIPCHK(c, launch_mixture(c->dim, p, c->stream));
   if (ev) HIPCHK(c, hipEventRecord(ev[4], c->stream));
   c->cur = 1 - c->cur;
@@ -948,7 +957,9 @@ int lbm_get_diagnostics(lbm_ctx *c, lbm_diag *out) {
   if (!c || !out) return LBM_EINVAL;
   memset(out, 0, sizeof(*out));
   const int W = c->L + c->dim + 2;
-  HIPCHK(c, launch_diag(c->L, c->dim, c->M, c->N, c->pop[c->cur], c->partials, c->diag_blocks, c->stream));
+  KParams p = base_params(c);
+  fill_prev(c, p);
+  HIPCHK(c, launch_diag(c->dim, c->L, c->M, p, c->pop[c->cur], c->partials, c->diag_blocks, c->stream));
   std::vector<double> h((size_t)c->diag_blocks * W);
   HIPCHK(c, hipMemcpyAsync(h.data(), c->partials, sizeof(double) * h.size(), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));

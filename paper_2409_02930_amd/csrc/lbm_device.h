@@ -230,10 +230,74 @@ __device__ __forceinline__ double inlet_population(const KParams &p, int kind, i
 
 // Post-stream populations of lattice `lat` at node nd (pull scheme).  All Q
 // loads are issued unconditionally; the inlet fix-up runs on inlet nodes only.
-template <int D, int M>
-__device__ __forceinline__ void pull_lattice(const KParams &p, const Node &nd, const PullGeo<D> &g,
-                                             int lat, double phi, const double *vb, bool inlet_node,
-                                             double *f) {
+// Reaction population that the previous step added to species a in direction i
+// at node y after its collision (eq fsourceHetero):
+//   rho_dot_a dt prod_d Psi_{c_id}(v_d, v_d^2 + R_a T), all at node y.
+// Adding it when the population is pulled, instead of writing it into the
+// stored populations, saves a read-modify-write pass over every species
+// population; the sum is the same.
+//
+// SrcVals: the record values of one source node: rho_dot_a dt, T, v.
+template <int D>
+struct SrcVals {
+  double sa, T, v[D];
+};
+
+// rec: node records of the previous step (velocity planes first), sa: its
+// source plane of species a, T: temperature of the previous step.
+template <int D>
+__device__ __forceinline__ SrcVals<D> load_src(const double *__restrict__ rec, const double *__restrict__ sa,
+                                               const double *__restrict__ T, size_t N, int y) {
+  SrcVals<D> r;
+  r.sa = sa[y];
+  r.T = T[y];
+#pragma unroll
+  for (int d = 0; d < D; ++d) r.v[d] = rec[d * N + y];
+  return r;
+}
+
+// km = theta_ref m_min / m_a, so R_a T = km T / T_ref.
+template <int D>
+__device__ __forceinline__ double source_population(const SrcVals<D> &s, double km, double inv_T_ref, int i) {
+  const double RaT = km * (s.T * inv_T_ref);
+  double psi = s.sa;
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    const double P = s.v[d] * s.v[d] + RaT;
+    const int c = cdir(i, d);
+    psi *= (c == 0) ? 1.0 - P : 0.5 * (c * s.v[d] + P);
+  }
+  return psi;
+}
+
+// Adds the reaction populations of species lattice a (source plane sa, km for
+// a) to the pulled populations f, gathering every source node's record.
+template <int D>
+__device__ __forceinline__ void add_source_populations(const KParams &p, const Node &nd, const PullGeo<D> &g,
+                                                       const double *sa, double km, double *f) {
+  constexpr int Q = LQ<D>::Q;
+  const size_t N = (size_t)p.N;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    int dir;
+    const int src = pull_addr<D>(p, nd, g, i, dir);
+    f[i] += source_population<D>(load_src<D>(p.rec_prev, sa, p.T_prev, N, src), km, p.inv_T_ref, dir);
+  }
+}
+
+// km = theta_ref m_min / m_lat without a run-time index into the parameters.
+template <int M>
+__device__ __forceinline__ double species_km(const KParams &p, int lat) {
+  double km = 0.0;
+#pragma unroll
+  for (int c = 0; c < M; ++c) km += (c == lat ? 1.0 : 0.0) * p.mmin_over_m[c];
+  return km * p.theta_ref;
+}
+
+// Raw pull of lattice lat: stored populations that stream into this node.
+template <int D>
+__device__ __forceinline__ void pull_populations(const KParams &p, const Node &nd, const PullGeo<D> &g, int lat,
+                                                 double *f) {
   constexpr int Q = LQ<D>::Q;
   const int N = p.N;
   const double *base = p.pin + (size_t)lat * Q * N;
@@ -243,13 +307,31 @@ __device__ __forceinline__ void pull_lattice(const KParams &p, const Node &nd, c
     const int src = pull_addr<D>(p, nd, g, i, dir);
     f[i] = base[(size_t)dir * N + src];
   }
-  if (inlet_node) {
+}
+
+// Inlet directions of an inlet node take the inlet equilibrium.
+template <int D, int M>
+__device__ __forceinline__ void inlet_replace(const KParams &p, const Node &nd, int lat, double phi,
+                                              const double *vb, double *f) {
+  constexpr int Q = LQ<D>::Q;
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      const int kind = inlet_kind<D>(p, nd, i);
-      if (kind) f[i] = inlet_population<D, M>(p, kind, lat, i, phi, vb);
-    }
+  for (int i = 0; i < Q; ++i) {
+    const int kind = inlet_kind<D>(p, nd, i);
+    if (kind) f[i] = inlet_population<D, M>(p, kind, lat, i, phi, vb);
   }
+}
+
+// Pulls lattice lat into f (post-stream populations of this node).  With SRC,
+// species lattices also take the reaction population of the previous step at
+// the source node and direction.
+template <int D, int M, bool SRC = true>
+__device__ __forceinline__ void pull_lattice(const KParams &p, const Node &nd, const PullGeo<D> &g,
+                                             int lat, double phi, const double *vb, bool inlet_node,
+                                             double *f) {
+  pull_populations<D>(p, nd, g, lat, f);
+  if (SRC && lat < M && p.src_prev)
+    add_source_populations<D>(p, nd, g, p.rec_prev + (size_t)(kRecSrc + lat) * p.N, species_km<M>(p, lat), f);
+  if (inlet_node) inlet_replace<D, M>(p, nd, lat, phi, vb, f);
 }
 
 // Node at x + c for the gradient stencil: periodic wrap, mirror ghost (the node

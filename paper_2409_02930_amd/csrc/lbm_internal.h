@@ -13,8 +13,8 @@
 
 enum { BC_PERIODIC = 0, BC_BOUNCEBACK = 1, BC_INLET = 2, BC_OUTFLOW = 3 };
 
-constexpr int kRec = 8;     // doubles per node record (velocity + species source)
-constexpr int kRecSrc = 3;  // offset of the species source in a record
+constexpr int kRec = 8;     // planes of the node records (velocity + species source)
+constexpr int kRecSrc = 3;  // first plane of the species source
 
 // Equilibrium state of a prescribed inlet mixture (lattice units).
 struct InletState {
@@ -33,7 +33,7 @@ struct KParams {
   int knudsen;              // Knudsen relaxation on
   int chem;                 // a chemistry source is computed this step
   int need_v;               // node velocities are needed by the next step
-  int pad0;
+  int src_prev;             // species pulls add the reaction populations of the previous step
   const int8_t *colflag;    // packed 1-D columns: bit0 = left end, bit1 = right end; NULL = grid
   double theta_ref, inv_T_ref, nu, prandtl;
   double mmin_over_m[LBM_MMAX];   // m_min / m_a
@@ -56,8 +56,8 @@ struct KParams {
   double *rrho;             // [M][N] species densities (chemistry input)
   double *rY;               // [M][N] mass fractions (energy lattice)
   double *rqd;              // [D][N] sum_a H_a Y_a (u_a - u_bar) (energy lattice)
-  // ping-pong node records between consecutive steps, kRec doubles per node:
-  //   [0..2] v = u/phi, [3..7] species source rho_dot_a dt (lattice units)
+  // ping-pong node records between consecutive steps, kRec planes of N doubles:
+  //   planes 0..2 v = u/phi, planes 3..7 species source rho_dot_a dt (lattice units)
   const double *rec_prev;   // written by the previous step
   double *rec_cur;          // written by this step
   const double *T_prev;     // [N] temperature of the previous step (energy) or Tfield
@@ -84,7 +84,7 @@ struct ChemParams {
   const double *phi;        // [N]
   const double *faradaic;   // [N] mol m^-3 s^-1 or NULL
   double *theta;            // [K][N] in place
-  double *rec;              // node records of this step: source written at kRecSrc + a
+  double *rec;              // node records of this step: source written to plane kRecSrc + a
   double *srcsum;           // [N]
 };
 
@@ -120,11 +120,10 @@ struct ChemSpec {
 hipError_t launch_init(int dim, const InitParams &ip, hipStream_t s);
 hipError_t launch_species(int dim, const KParams &p, hipStream_t s);
 hipError_t launch_mixture(int dim, const KParams &p, hipStream_t s);
-hipError_t launch_source(int dim, const KParams &p, hipStream_t s);
 hipError_t launch_chem(const ChemParams &cp, hipStream_t s);
 hipError_t launch_moments(int dim, const KParams &p, double *out, hipStream_t s);
-hipError_t launch_diag(int L, int D, int Mmom, int N, const double *pop, double *partials, int nblocks,
-                       hipStream_t s);
+hipError_t launch_diag(int dim, int L, int Mmom, const KParams &p, const double *pop, double *partials,
+                       int nblocks, hipStream_t s);
 int chem_supported(int M, int K);
 
 // adjoint of the isothermal reaction-free step (lbm_adjoint.hip)

@@ -1,18 +1,19 @@
 // HIP kernels of the mean-field reactive porous-media lattice Boltzmann step (gfx950).
 //
-// One time step is three to four launches:
+// One time step is two or three launches:
 //   k_species  : pull-stream of every lattice, moments, composition, relaxation
 //                rates, the M x M species-momentum solve, the species collision
 //                (Section 2.3, eq finalNumericalEquationsReactive) and the small
 //                per-node records the next kernels need;
 //   k_chem     : the local surface-chemistry update (Section 4.2), only when a
-//                mechanism or a Faradaic source is installed;
-//   k_source   : adds that step's reaction populations to the post-collision
-//                species populations (eq fsourceHetero), only with chemistry;
+//                mechanism or a Faradaic source is installed; it writes the
+//                species source of the step into the node records;
 //   k_mixture  : momentum (eqs f_source, feqmix, Pex) and energy (eqs g_source,
 //                geq_i, gstar) collisions, which need gradients of node records.
-// Keeping the chemistry and its source out of k_species keeps that kernel a
-// pure bandwidth kernel.
+// The reaction populations of a step (eq fsourceHetero) are added to the
+// species populations when the next step pulls them (source_population), so
+// no pass rewrites the stored populations.  Keeping the chemistry out of
+// k_species keeps that kernel a bandwidth kernel.
 //
 // Populations are FP64 SoA [lattice][direction][node], one thread per node,
 // node index x-fastest so every direction is a coalesced (shifted) stream.
@@ -45,7 +46,7 @@ __device__ __forceinline__ void species_front(const KParams &p, const Node &nd, 
   double vb[D];
   const bool inlet_node = is_inlet_node(p, nd);
 #pragma unroll
-  for (int d = 0; d < D; ++d) vb[d] = inlet_node ? p.rec_prev[(size_t)n * kRec + d] : 0.0;
+  for (int d = 0; d < D; ++d) vb[d] = inlet_node ? p.rec_prev[(size_t)d * p.N + n] : 0.0;
   const PullGeo<D> geo = pull_geo<D>(p, nd);
 
   // ---- momentum lattice: sum f = phi rho (eq fdensity), sum f c = rho u
@@ -226,15 +227,126 @@ struct SpeciesShared {
   static constexpr int Q = LQ<D>::Q;
   double m0[L][64];             // zeroth moments: phi rho_a, phi rho, phi rho E
   double x[M][D][64];           // second-order species momenta, from the momentum wave
+  // records of the previous step around the block's nodes (reaction populations):
+  // row r of directions, field (source of species 0..M-1, T, v), node x0 - 1 + j
+  static constexpr int R = Q / 3, F = M + 1 + D, W = 64 + 2;
   union {
     struct {
       double m1[M + 1][D][64];  // first moments of species and momentum lattices
       double A[M][M][64];       // species-momentum system, row a from species wave a
       double itk[M][64];        // 1 / tau^k_a
+      double stage[R][F][W];    // before the moments only
     } s;
     double dlt[M][Q][64];       // phi rho_c (Psi_i(v) - Psi_i(xi_c)), after the solves
   } u;
 };
+
+// The block's 64 nodes lie on one x row, inside the x walls, and all exist:
+// then the pull sources of the three c_x of one (c_y, c_z) row of directions are
+// that row's nodes x - 1 .. x + 1, and the block can stage them once.
+template <int D>
+__device__ __forceinline__ bool row_block(const KParams &p, const Node &nd, const PullGeo<D> &g, bool valid) {
+  if (p.colflag || p.first_step) return false;
+  const unsigned long long all = __builtin_amdgcn_read_exec();
+  const unsigned long long good = __builtin_amdgcn_uicmp((valid && !g.lo_wall && !g.hi_wall) ? 1u : 0u, 0u, 33);
+  if (all != ~0ull || good != ~0ull) return false;
+  const int x0 = __builtin_amdgcn_readlane(nd.x, 0), x63 = __builtin_amdgcn_readlane(nd.x, 63);
+  return x63 - x0 == 63;
+}
+
+// Record field fi of the previous step: source of species fi (< M), T (= M),
+// v_{fi - M - 1}.
+template <int M>
+__device__ __forceinline__ const double *src_field(const KParams &p, int fi) {
+  const size_t N = (size_t)p.N;
+  return fi < M ? p.rec_prev + (size_t)(kRecSrc + fi) * N
+                : (fi == M ? p.T_prev : p.rec_prev + (size_t)(fi - M - 1) * N);
+}
+
+// Node of row r = (c_y + 1) + 3 (c_z + 1) of directions at x for the nodes of
+// a row block (y, z periodic; the block has no wall nodes).
+template <int D>
+__device__ __forceinline__ int row_node(const KParams &p, const Node &nd, int r, int x) {
+  int ys = nd.y, zs = nd.z;
+  if (D > 1) { ys -= r % 3 - 1; ys += (ys < 0) ? p.ny : 0; ys -= (ys >= p.ny) ? p.ny : 0; }
+  if (D > 2) { zs -= r / 3 - 1; zs += (zs < 0) ? p.nz : 0; zs -= (zs >= p.nz) ? p.nz : 0; }
+  return x + p.nx * (ys + p.ny * zs);
+}
+
+// Staged records of a row block, spread over its L waves: wave w loads the
+// (row r, field fi) pairs k = r F + fi with k = w mod L at its 64 nodes' x, and
+// the fields fi with R F + fi = w mod L at the two wave-end sources of every
+// row (lane 2r: x0 - 1, lane 2r + 1: x0 + 64, periodic in x).  load_stage only
+// issues the loads, so that they overlap the pull; store_stage writes them.
+template <int D, int M, bool ENERGY>
+struct Stage {
+  using SS = SpeciesShared<D, M, ENERGY>;
+  static constexpr int R = SS::R, F = SS::F, L = SS::L;
+  static constexpr int NC = (R * F + L - 1) / L, NH = (F + L - 1) / L;
+  double c[NC], h[NH];
+};
+
+template <int D, int M, bool ENERGY>
+__device__ __forceinline__ void load_stage(const KParams &p, const Node &nd, int w, int lane,
+                                           Stage<D, M, ENERGY> &st) {
+  using S = Stage<D, M, ENERGY>;
+  constexpr int R = S::R, F = S::F, L = S::L;
+#pragma unroll
+  for (int m = 0; m < S::NC; ++m) {
+    const int k = w + m * L;
+    st.c[m] = 0.0;
+    if (k < R * F) st.c[m] = src_field<M>(p, k % F)[row_node<D>(p, nd, k / F, nd.x)];
+  }
+  const int x0 = __builtin_amdgcn_readlane(nd.x, 0);
+  const int xe = (lane & 1) ? (x0 + 64 >= p.nx ? x0 + 64 - p.nx : x0 + 64) : (x0 == 0 ? p.nx - 1 : x0 - 1);
+  const int hy = row_node<D>(p, nd, lane >> 1, xe);
+  const int f0 = ((w - (R * F) % L) % L + L) % L;
+#pragma unroll
+  for (int m = 0; m < S::NH; ++m) {
+    const int fi = f0 + m * L;
+    st.h[m] = 0.0;
+    if (fi < F && lane < 2 * R) st.h[m] = src_field<M>(p, fi)[hy];
+  }
+}
+
+template <int D, int M, bool ENERGY>
+__device__ __forceinline__ void store_stage(int w, int lane, const Stage<D, M, ENERGY> &st,
+                                            SpeciesShared<D, M, ENERGY> &sh) {
+  using S = Stage<D, M, ENERGY>;
+  constexpr int R = S::R, F = S::F, L = S::L;
+#pragma unroll
+  for (int m = 0; m < S::NC; ++m) {
+    const int k = w + m * L;
+    if (k < R * F) sh.u.s.stage[k / F][k % F][lane + 1] = st.c[m];
+  }
+  const int f0 = ((w - (R * F) % L) % L + L) % L;
+#pragma unroll
+  for (int m = 0; m < S::NH; ++m) {
+    const int fi = f0 + m * L;
+    if (fi < F && lane < 2 * R) sh.u.s.stage[lane >> 1][fi][(lane & 1) ? 65 : 0] = st.h[m];
+  }
+}
+
+// Species wave a adds its reaction populations from the staged records.
+template <int D, int M, bool ENERGY>
+__device__ __forceinline__ void add_staged_sources(const KParams &p, const SpeciesShared<D, M, ENERGY> &sh, int a,
+                                                   int lane, double km, double *f) {
+  using SS = SpeciesShared<D, M, ENERGY>;
+  constexpr int R = SS::R;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+#pragma unroll
+    for (int cx = -1; cx <= 1; ++cx) {
+      const int i = 3 * r + 1 + cx, j = lane + 1 - cx;
+      SrcVals<D> v;
+      v.sa = sh.u.s.stage[r][a][j];
+      v.T = sh.u.s.stage[r][M][j];
+#pragma unroll
+      for (int d = 0; d < D; ++d) v.v[d] = sh.u.s.stage[r][M + 1 + d][j];
+      f[i] += source_population<D>(v, km, p.inv_T_ref, i);
+    }
+  }
+}
 
 // Per-node state every wave derives from the lattice moments in LDS.
 template <int D, int M>
@@ -376,15 +488,31 @@ __global__ __launch_bounds__(64 * (M + 1 + (ENERGY ? 1 : 0))) void k_species(con
     geo = pull_geo<D>(p, nd);
     if (inlet_node) {
 #pragma unroll
-      for (int d = 0; d < D; ++d) vb[d] = p.rec_prev[(size_t)n * kRec + d];
+      for (int d = 0; d < D; ++d) vb[d] = p.rec_prev[(size_t)d * N + n];
     }
   }
 
-  // ---- phase 1: pull this wave's lattice, moments to LDS
+  // ---- phase 1: pull this wave's lattice (species a, momentum M, energy M + 1)
+  //      with the previous step's reaction populations, moments to LDS
+  const int lat = w;
+  const bool rows = p.src_prev && row_block<D>(p, nd, geo, valid);   // the same in every wave of the block
+  Stage<D, M, ENERGY> st;
+  if (rows) load_stage<D, M, ENERGY>(p, nd, w, lane, st);
   double f[Q];
+  if (valid) pull_populations<D>(p, nd, geo, lat, f);
+  if (p.src_prev) {
+    if (rows) store_stage<D, M, ENERGY>(w, lane, st, sh);
+    __syncthreads();
+    if (valid && lat < M) {
+      const double km = species_km<M>(p, lat);
+      if (rows)
+        add_staged_sources<D, M, ENERGY>(p, sh, lat, lane, km, f);
+      else
+        add_source_populations<D>(p, nd, geo, p.rec_prev + (size_t)(kRecSrc + lat) * N, km, f);
+    }
+  }
   if (valid) {
-    const int lat = w;                       // species a, momentum M, energy M + 1
-    pull_lattice<D, M>(p, nd, geo, lat, phi, vb, inlet_node, f);
+    if (inlet_node) inlet_replace<D, M>(p, nd, lat, phi, vb, f);
     double s0 = 0.0, s1[D];
 #pragma unroll
     for (int d = 0; d < D; ++d) s1[d] = 0.0;
@@ -498,7 +626,7 @@ __global__ __launch_bounds__(64 * (M + 1 + (ENERGY ? 1 : 0))) void k_species(con
         p.rA[(size_t)d * N + n] =                    // rho u (1 - 3RT) - rho u^3 / phi^2, with v = u / phi
             s.rho * s.u[d] * (1.0 - 3.0 * s.RT) - s.rho * s.u[d] * s.v[d] * s.v[d];
         if (p.knudsen) p.rFk[(size_t)d * N + n] = fk;
-        if (p.need_v) p.rec_cur[(size_t)n * kRec + d] = s.v[d];
+        if (p.need_v) p.rec_cur[(size_t)d * N + n] = s.v[d];
       }
       p.rRT[n] = s.RT;
       if (p.chem) {
@@ -534,46 +662,6 @@ __global__ __launch_bounds__(64 * (M + 1 + (ENERGY ? 1 : 0))) void k_species(con
 }
 
 // ---------------------------------------------------------------------------
-// k_source: adds the reaction population of this step to the post-collision
-// species populations at their own node (eq fsourceHetero):
-//   f'_ai += rho_dot_a dt prod_d Psi_{c_id}(v_d, v_d^2 + R_a T).
-// The populations then stream with their source, as the paper writes it.
-// ---------------------------------------------------------------------------
-template <int D, int M>
-__global__ __launch_bounds__(256) void k_source(const KParams p) {
-  constexpr int Q = LQ<D>::Q;
-  Node nd;
-  if (!get_node(p, nd)) return;
-  const int N = p.N;
-  const int n = nd.n;
-  double v[D];
-#pragma unroll
-  for (int d = 0; d < D; ++d) v[d] = p.rec_cur[(size_t)n * kRec + d];
-  const double Tn = p.energy ? p.T_cur[n] : p.Tfield[n];
-#pragma unroll
-  for (int a = 0; a < M; ++a) {
-    const double sa = p.rec_cur[(size_t)n * kRec + kRecSrc + a];
-    const double RaT = p.theta_ref * p.mmin_over_m[a] * (Tn * p.inv_T_ref);
-    double t[D][3];
-#pragma unroll
-    for (int d = 0; d < D; ++d) {
-      const double P = v[d] * v[d] + RaT;
-      t[d][0] = 0.5 * (-v[d] + P);
-      t[d][1] = 1.0 - P;
-      t[d][2] = 0.5 * (v[d] + P);
-    }
-    double *f = p.pout + (size_t)(a * Q) * N + n;
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      double psi = t[0][i % 3];
-      if (D > 1) psi *= t[1][(i / 3) % 3];
-      if (D > 2) psi *= t[2][i / 9];
-      f[(size_t)i * N] += sa * psi;
-    }
-  }
-}
-
-// ---------------------------------------------------------------------------
 // k_mixture: momentum lattice with the extended equilibrium, energy lattice
 // ---------------------------------------------------------------------------
 template <int D, int M, bool ENERGY>
@@ -587,7 +675,7 @@ __global__ __launch_bounds__(256) void k_mixture(const KParams p) {
   double vb[D];
   const bool inlet_node = is_inlet_node(p, nd);
 #pragma unroll
-  for (int d = 0; d < D; ++d) vb[d] = inlet_node ? p.rec_prev[(size_t)n * kRec + d] : 0.0;
+  for (int d = 0; d < D; ++d) vb[d] = inlet_node ? p.rec_prev[(size_t)d * N + n] : 0.0;
   const PullGeo<D> geo = pull_geo<D>(p, nd);
 
   double f[Q];
@@ -1036,7 +1124,7 @@ void k_chem(const ChemParams cp) {
   double ssum = 0.0;
 #pragma unroll
   for (int a = 0; a < M; ++a) {
-    cp.rec[(size_t)n * kRec + kRecSrc + a] = src[a];
+    cp.rec[(size_t)(kRecSrc + a) * cp.N + n] = src[a];
     ssum += src[a];
   }
   cp.srcsum[n] = ssum;
@@ -1056,7 +1144,7 @@ __global__ __launch_bounds__(256) void k_faradaic(const ChemParams cp) {
     double s = 0.0;
     if (a == cp.fuel) s -= r * cp.m[a] / cp.rho_unit;
     if (a == cp.product) s += r * cp.m[a] / cp.rho_unit;
-    cp.rec[(size_t)n * kRec + kRecSrc + a] = s;
+    cp.rec[(size_t)(kRecSrc + a) * cp.N + n] = s;
     ssum += s;
   }
   cp.srcsum[n] = ssum;
@@ -1080,10 +1168,14 @@ __device__ __forceinline__ double block_sum(double v, double *sh) {
   return r;
 }
 
-__global__ __launch_bounds__(256) void k_diag(int L, int D, int Mmom, int N, const double *pop,
+// Totals of the stored state.  Species populations include the reaction
+// population the last step added after its collision (p.src_prev).
+template <int D>
+__global__ __launch_bounds__(256) void k_diag(int L, int Mmom, const KParams p, const double *pop,
                                               double *partials) {
   __shared__ double sh[256];
-  const int Q = (D == 1) ? 3 : (D == 2 ? 9 : 27);
+  constexpr int Q = LQ<D>::Q;
+  const int N = p.N;
   const int n = blockIdx.x * blockDim.x + threadIdx.x;
   const int t = threadIdx.x;
   const int W = L + D + 2;
@@ -1091,8 +1183,12 @@ __global__ __launch_bounds__(256) void k_diag(int L, int D, int Mmom, int N, con
   for (int l = 0; l < L; ++l) {
     double s = 0.0;
     if (n < N) {
+      const bool src = l < p.M && p.src_prev;
+      const double km = src ? p.theta_ref * p.mmin_over_m[l] : 0.0;
+      const double *sa = p.rec_prev + (size_t)(kRecSrc + l) * N;
       for (int i = 0; i < Q; ++i) {
-        const double v = pop[(size_t)(l * Q + i) * N + n];
+        double v = pop[(size_t)(l * Q + i) * N + n];
+        if (src) v += source_population<D>(load_src<D>(p.rec_prev, sa, p.T_prev, (size_t)N, n), km, p.inv_T_ref, i);
         if (!isfinite(v)) bad += 1.0;
         s += v;
         mn = fmin(mn, v);
@@ -1193,19 +1289,6 @@ hipError_t moments_dispatch(const KParams &p, double *out, hipStream_t s) {
 }
 
 template <int D>
-hipError_t source_dispatch(const KParams &p, hipStream_t s) {
-  const unsigned nb = padded_blocks(p.N, 256);
-  switch (p.M) {
-    case 2: hipLaunchKernelGGL((k_source<D, 2>), dim3(nb), dim3(256), 0, s, p); break;
-    case 3: hipLaunchKernelGGL((k_source<D, 3>), dim3(nb), dim3(256), 0, s, p); break;
-    case 4: hipLaunchKernelGGL((k_source<D, 4>), dim3(nb), dim3(256), 0, s, p); break;
-    case 5: hipLaunchKernelGGL((k_source<D, 5>), dim3(nb), dim3(256), 0, s, p); break;
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
-}
-
-template <int D>
 hipError_t init_dispatch(const InitParams &ip, hipStream_t s) {
   const unsigned nb = (unsigned)((ip.N + 255) / 256);
   switch (ip.M) {
@@ -1234,15 +1317,6 @@ hipError_t launch_species(int dim, const KParams &p, hipStream_t s) {
     case 1: return species_dispatch<1>(p, s);
     case 2: return species_dispatch<2>(p, s);
     case 3: return species_dispatch<3>(p, s);
-  }
-  return hipErrorInvalidValue;
-}
-
-hipError_t launch_source(int dim, const KParams &p, hipStream_t s) {
-  switch (dim) {
-    case 1: return source_dispatch<1>(p, s);
-    case 2: return source_dispatch<2>(p, s);
-    case 3: return source_dispatch<3>(p, s);
   }
   return hipErrorInvalidValue;
 }
@@ -1294,8 +1368,12 @@ hipError_t launch_chem(const ChemParams &cp, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_diag(int L, int D, int Mmom, int N, const double *pop, double *partials, int nblocks,
-                       hipStream_t s) {
-  hipLaunchKernelGGL(k_diag, dim3(nblocks), dim3(256), 0, s, L, D, Mmom, N, pop, partials);
+hipError_t launch_diag(int dim, int L, int Mmom, const KParams &p, const double *pop, double *partials,
+                       int nblocks, hipStream_t s) {
+  switch (dim) {
+    case 1: hipLaunchKernelGGL(k_diag<1>, dim3(nblocks), dim3(256), 0, s, L, Mmom, p, pop, partials); break;
+    case 2: hipLaunchKernelGGL(k_diag<2>, dim3(nblocks), dim3(256), 0, s, L, Mmom, p, pop, partials); break;
+    default: hipLaunchKernelGGL(k_diag<3>, dim3(nblocks), dim3(256), 0, s, L, Mmom, p, pop, partials); break;
+  }
   return hipGetLastError();
 }

@@ -184,6 +184,26 @@ def test_conservation_on_gpu(lbm):
     lat.close()
 
 
+def test_diagnostics_include_pending_reaction_populations(lbm):
+    """The last step's reaction populations live in the node records until the
+    next pull; the diagnostics must count them.  With periodic boundaries the
+    stream is a permutation, so the oracle's post-stream totals and minimum
+    equal the stored (pre-stream) ones."""
+    w = synth.config3(nx=9, ny=5, nz=3)
+    assert w.bc_lo == synth.BC_PERIODIC and w.bc_hi == synth.BC_PERIODIC
+    lat = lbm.lattice_from_workload(w)
+    lat.step(4)
+    d = lat.diagnostics()
+    lat.close()
+    o = Oracle(w)
+    o.step(4)
+    mass = o.fa.sum(axis=(1, 2))
+    rel = np.abs(d["species_mass"] - mass) / mass
+    assert np.all(rel < 1e-12), rel
+    ref_min = min(float(o.fa.min()), float(o.f.min()))
+    assert abs(d["min_population"] - ref_min) <= 1e-11 * abs(ref_min), (d["min_population"], ref_min)
+
+
 def test_save_load_roundtrip_bitwise(lbm):
     w = synth.config3(nx=9, ny=5, nz=3)
     a = lbm.lattice_from_workload(w)
