@@ -254,30 +254,32 @@ __device__ __forceinline__ bool row_block(const KParams &p, const Node &nd, cons
   return x63 - x0 == 63;
 }
 
+
 // Record field fi of the previous step: source of species fi (< M), T (= M),
-// v_{fi - M - 1}.
+// v_{fi - M - 1}; a select, no branch.
 template <int M>
 __device__ __forceinline__ const double *src_field(const KParams &p, int fi) {
-  const size_t N = (size_t)p.N;
-  return fi < M ? p.rec_prev + (size_t)(kRecSrc + fi) * N
-                : (fi == M ? p.T_prev : p.rec_prev + (size_t)(fi - M - 1) * N);
+  const int plane = fi < M ? kRecSrc + fi : fi - M - 1;
+  const double *r = p.rec_prev + (size_t)plane * p.N;
+  return fi == M ? p.T_prev : r;
 }
 
-// Node of row r = (c_y + 1) + 3 (c_z + 1) of directions at x for the nodes of
-// a row block (y, z periodic; the block has no wall nodes).
+// Offset nx (y_s + ny z_s) of row r = (c_y + 1) + 3 (c_z + 1) of directions:
+// source y_s = y - c_y, z_s = z - c_z, periodic.
 template <int D>
-__device__ __forceinline__ int row_node(const KParams &p, const Node &nd, int r, int x) {
-  int ys = nd.y, zs = nd.z;
+__device__ __forceinline__ int row_offset(const KParams &p, int y, int z, int r) {
+  int ys = y, zs = z;
   if (D > 1) { ys -= r % 3 - 1; ys += (ys < 0) ? p.ny : 0; ys -= (ys >= p.ny) ? p.ny : 0; }
   if (D > 2) { zs -= r / 3 - 1; zs += (zs < 0) ? p.nz : 0; zs -= (zs >= p.nz) ? p.nz : 0; }
-  return x + p.nx * (ys + p.ny * zs);
+  return p.nx * (ys + p.ny * zs);
 }
 
 // Staged records of a row block, spread over its L waves: wave w loads the
 // (row r, field fi) pairs k = r F + fi with k = w mod L at its 64 nodes' x, and
 // the fields fi with R F + fi = w mod L at the two wave-end sources of every
-// row (lane 2r: x0 - 1, lane 2r + 1: x0 + 64, periodic in x).  load_stage only
-// issues the loads, so that they overlap the pull; store_stage writes them.
+// row (lane 2r: x0 - 1, lane 2r + 1: x0 + 64, periodic in x).  All nodes of a
+// row block share y and z, so the row offsets are wave-uniform.  load_stage
+// only issues the loads, so that they overlap the pull; store_stage writes them.
 template <int D, int M, bool ENERGY>
 struct Stage {
   using SS = SpeciesShared<D, M, ENERGY>;
@@ -291,21 +293,20 @@ __device__ __forceinline__ void load_stage(const KParams &p, const Node &nd, int
                                            Stage<D, M, ENERGY> &st) {
   using S = Stage<D, M, ENERGY>;
   constexpr int R = S::R, F = S::F, L = S::L;
+  const int y = __builtin_amdgcn_readfirstlane(nd.y), z = __builtin_amdgcn_readfirstlane(nd.z);
 #pragma unroll
   for (int m = 0; m < S::NC; ++m) {
-    const int k = w + m * L;
-    st.c[m] = 0.0;
-    if (k < R * F) st.c[m] = src_field<M>(p, k % F)[row_node<D>(p, nd, k / F, nd.x)];
+    const int k = min(w + m * L, R * F - 1);   // the clamped pair is loaded again, not stored
+    st.c[m] = src_field<M>(p, k % F)[row_offset<D>(p, y, z, k / F) + nd.x];
   }
-  const int x0 = __builtin_amdgcn_readlane(nd.x, 0);
+  const int x0 = __builtin_amdgcn_readfirstlane(nd.x);
   const int xe = (lane & 1) ? (x0 + 64 >= p.nx ? x0 + 64 - p.nx : x0 + 64) : (x0 == 0 ? p.nx - 1 : x0 - 1);
-  const int hy = row_node<D>(p, nd, lane >> 1, xe);
+  const int hy = xe + row_offset<D>(p, y, z, min(lane >> 1, R - 1));
   const int f0 = ((w - (R * F) % L) % L + L) % L;
 #pragma unroll
   for (int m = 0; m < S::NH; ++m) {
-    const int fi = f0 + m * L;
-    st.h[m] = 0.0;
-    if (fi < F && lane < 2 * R) st.h[m] = src_field<M>(p, fi)[hy];
+    const int fi = min(f0 + m * L, F - 1);
+    st.h[m] = src_field<M>(p, fi)[hy];
   }
 }
 
