@@ -295,6 +295,8 @@ __device__ __forceinline__ double species_km(const KParams &p, int lat) {
 }
 
 // Raw pull of lattice lat: stored populations that stream into this node.
+// Every stored population is read once, so the loads are non-temporal and
+// leave the L2 to the node records that neighbouring nodes re-read.
 template <int D>
 __device__ __forceinline__ void pull_populations(const KParams &p, const Node &nd, const PullGeo<D> &g, int lat,
                                                  double *f) {
@@ -305,7 +307,7 @@ __device__ __forceinline__ void pull_populations(const KParams &p, const Node &n
   for (int i = 0; i < Q; ++i) {
     int dir;
     const int src = pull_addr<D>(p, nd, g, i, dir);
-    f[i] = base[(size_t)dir * N + src];
+    f[i] = __builtin_nontemporal_load(base + (size_t)dir * N + src);   // read once: keep L2 for records
   }
 }
 

@@ -17,6 +17,8 @@
 //
 // Populations are FP64 SoA [lattice][direction][node], one thread per node,
 // node index x-fastest so every direction is a coalesced (shifted) stream.
+// Population streams and per-step records are moved with non-temporal loads
+// and stores, so the L2 keeps what is re-read: the neighbouring nodes' records.
 #include "lbm_device.h"
 
 namespace {
@@ -604,7 +606,7 @@ __global__ __launch_bounds__(64 * (M + 1 + (ENERGY ? 1 : 0))) void k_species(con
         const double fk = pra * pk;
         const double Fi = Ya * F + itk_a * (fst - fk);
         const double f0 = f[i];
-        out[(size_t)i * N] = f0 + 2.0 * beta * (feq - f0) + (beta - 1.0) * Fi;
+        __builtin_nontemporal_store(f0 + 2.0 * beta * (feq - f0) + (beta - 1.0) * Fi, out + (size_t)i * N);
       }
     }
   } else if (w == M) {
@@ -624,15 +626,15 @@ __global__ __launch_bounds__(64 * (M + 1 + (ENERGY ? 1 : 0))) void k_species(con
         double fk = 0.0;
 #pragma unroll
         for (int c = 0; c < M; ++c) fk -= x[c][d] * itk[c];   // eq netKnudsenForce
-        p.rA[(size_t)d * N + n] =                    // rho u (1 - 3RT) - rho u^3 / phi^2, with v = u / phi
-            s.rho * s.u[d] * (1.0 - 3.0 * s.RT) - s.rho * s.u[d] * s.v[d] * s.v[d];
-        if (p.knudsen) p.rFk[(size_t)d * N + n] = fk;
-        if (p.need_v) p.rec_cur[(size_t)d * N + n] = s.v[d];
+        __builtin_nontemporal_store(                 // rho u (1 - 3RT) - rho u^3 / phi^2, with v = u / phi
+            s.rho * s.u[d] * (1.0 - 3.0 * s.RT) - s.rho * s.u[d] * s.v[d] * s.v[d], p.rA + (size_t)d * N + n);
+        if (p.knudsen) __builtin_nontemporal_store(fk, p.rFk + (size_t)d * N + n);
+        if (p.need_v) __builtin_nontemporal_store(s.v[d], p.rec_cur + (size_t)d * N + n);
       }
-      p.rRT[n] = s.RT;
+      __builtin_nontemporal_store(s.RT, p.rRT + n);
       if (p.chem) {
 #pragma unroll
-        for (int a = 0; a < M; ++a) p.rrho[(size_t)a * N + n] = s.rho_a[a];
+        for (int a = 0; a < M; ++a) __builtin_nontemporal_store(s.rho_a[a], p.rrho + (size_t)a * N + n);
       }
       if constexpr (ENERGY) {
         p.T_cur[n] = s.T;
@@ -728,7 +730,7 @@ __global__ __launch_bounds__(256) void k_mixture(const KParams p) {
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     const double fex = phirho * psi_dir<D>(i, xi, Pex);
-    p.pout[(size_t)(M * Q + i) * N + n] = f[i] + omega * (fex - f[i]) + ratio * fex;
+    __builtin_nontemporal_store(f[i] + omega * (fex - f[i]) + ratio * fex, p.pout + (size_t)(M * Q + i) * N + n);
   }
 
   if (ENERGY) {
@@ -812,7 +814,7 @@ __global__ __launch_bounds__(256) void k_mixture(const KParams p) {
         for (int d = 0; d < D; ++d) cq += cdir(i, d) * Qv[d];
         out += 0.5 * cq;
       }
-      p.pout[(size_t)((M + 1) * Q + i) * N + n] = out;
+      __builtin_nontemporal_store(out, p.pout + (size_t)((M + 1) * Q + i) * N + n);
     }
   }
 }
