@@ -361,15 +361,16 @@ struct NodeState {
 
 // Reciprocals replace the per-species divisions (fewer dependent chains, fewer
 // live registers); the results differ from the divided forms by rounding only.
+// jm: first moment of the momentum lattice (phi rho u... = rho u, eq f1momMomentum).
 template <int D, int M, bool ENERGY>
 __device__ __forceinline__ void node_state(const KParams &p, const SpeciesShared<D, M, ENERGY> &sh, int lane,
-                                           double phi, double Tfield, NodeState<D, M> &s) {
+                                           const double *jm, double phi, double Tfield, NodeState<D, M> &s) {
   const double iphi = 1.0 / phi;
   s.rho = sh.m0[M][lane] * iphi;
   const double irho = 1.0 / s.rho;
 #pragma unroll
   for (int d = 0; d < D; ++d) {
-    s.u[d] = sh.u.s.m1[M][d][lane] * irho;
+    s.u[d] = jm[d] * irho;
     s.v[d] = s.u[d] * iphi;
   }
   double rs = 0.0;
@@ -536,9 +537,14 @@ __global__ __launch_bounds__(64 * (M + 1 + (ENERGY ? 1 : 0))) void k_species(con
   // ---- phase 2: node state; species wave a publishes its rates and its row
   NodeState<D, M> s;
   double iab[M], beta = 0.0, itk_a = 0.0, RaTa = 0.0, Ya = 0.0;
-  if (valid && w <= M) {
-    node_state<D, M, ENERGY>(p, sh, lane, phi, Tfield, s);
-    if (w < M) {
+  if (valid && w < M) {
+    {
+      double jm[D];
+#pragma unroll
+      for (int d = 0; d < D; ++d) jm[d] = sh.u.s.m1[M][d][lane];
+      node_state<D, M, ENERGY>(p, sh, lane, jm, phi, Tfield, s);
+    }
+    {
       const int a = w;
 #pragma unroll
       for (int c = 0; c < M; ++c) {              // select without indexing by the run-time a
@@ -610,10 +616,13 @@ __global__ __launch_bounds__(64 * (M + 1 + (ENERGY ? 1 : 0))) void k_species(con
       }
     }
   } else if (w == M) {
-    // ---- momentum wave: node records for the chemistry and mixture kernels and
-    //      for the next step
+    // ---- momentum wave: solves the species-momentum system and publishes the
+    //      second-order momenta; after the barrier that releases the species
+    //      waves it rebuilds the node state and writes the node records for the
+    //      chemistry and mixture kernels and for the next step.
+    double jm[D], itk[M];
     if (valid) {
-      double x[M][D], itk[M];
+      double x[M][D];
       species_momenta<D, M, ENERGY>(sh, lane, x);
 #pragma unroll
       for (int c = 0; c < M; ++c) {
@@ -622,10 +631,16 @@ __global__ __launch_bounds__(64 * (M + 1 + (ENERGY ? 1 : 0))) void k_species(con
         for (int d = 0; d < D; ++d) sh.x[c][d][lane] = x[c][d];
       }
 #pragma unroll
+      for (int d = 0; d < D; ++d) jm[d] = sh.u.s.m1[M][d][lane];
+    }
+    __syncthreads();                              // x in LDS; the union now belongs to the species waves
+    if (valid) {
+      node_state<D, M, ENERGY>(p, sh, lane, jm, phi, Tfield, s);
+#pragma unroll
       for (int d = 0; d < D; ++d) {
         double fk = 0.0;
 #pragma unroll
-        for (int c = 0; c < M; ++c) fk -= x[c][d] * itk[c];   // eq netKnudsenForce
+        for (int c = 0; c < M; ++c) fk -= sh.x[c][d][lane] * itk[c];   // eq netKnudsenForce
         __builtin_nontemporal_store(                 // rho u (1 - 3RT) - rho u^3 / phi^2, with v = u / phi
             s.rho * s.u[d] * (1.0 - 3.0 * s.RT) - s.rho * s.u[d] * s.v[d] * s.v[d], p.rA + (size_t)d * N + n);
         if (p.knudsen) __builtin_nontemporal_store(fk, p.rFk + (size_t)d * N + n);
@@ -642,11 +657,12 @@ __global__ __launch_bounds__(64 * (M + 1 + (ENERGY ? 1 : 0))) void k_species(con
         for (int d = 0; d < D; ++d) {
           double ub = 0.0;
 #pragma unroll
-          for (int c = 0; c < M; ++c) ub += s.Y[c] * ((s.rho_a[c] > 0.0) ? x[c][d] / s.rho_a[c] : s.u[d]);
+          for (int c = 0; c < M; ++c)
+            ub += s.Y[c] * ((s.rho_a[c] > 0.0) ? sh.x[c][d][lane] / s.rho_a[c] : s.u[d]);
           double sacc = 0.0;
 #pragma unroll
           for (int a = 0; a < M; ++a) {
-            const double ua = (s.rho_a[a] > 0.0) ? x[a][d] / s.rho_a[a] : s.u[d];
+            const double ua = (s.rho_a[a] > 0.0) ? sh.x[a][d][lane] / s.rho_a[a] : s.u[d];
             const double Ha = p.uf[a] + p.cv[a] * s.T + s.RaT[a];
             sacc += Ha * s.Y[a] * (ua - ub);
           }
@@ -656,7 +672,6 @@ __global__ __launch_bounds__(64 * (M + 1 + (ENERGY ? 1 : 0))) void k_species(con
         for (int a = 0; a < M; ++a) p.rY[(size_t)a * N + n] = s.Y[a];
       }
     }
-    __syncthreads();
     __syncthreads();
   } else {
     __syncthreads();                              // energy wave: nothing after its pull

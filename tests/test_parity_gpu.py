@@ -102,6 +102,17 @@ def test_d3q27_porous_with_chemistry(lbm, kernel):
     _run(lbm, w, 12, chem_kernel=kind)
 
 
+@pytest.mark.parametrize("shape", [(64, 3, 8), (128, 2, 16)])
+def test_d3q27_row_blocks_with_chemistry(lbm, shape):
+    """Rows that are whole 64-node blocks: the species kernel stages the
+    previous step's records of the 3 x 3 neighbouring rows in LDS (periodic
+    wrap at the row ends, two blocks per row in the second case) and walks the
+    rows in z slabs."""
+    nx, ny, nz = shape
+    w = synth.config3(nx=nx, ny=ny, nz=nz)
+    _run(lbm, w, 6)
+
+
 def test_specialized_chemistry_matches_generic_full_newton(lbm):
     """Specialised vs generic kernel on a stiffer mechanism setting (more
     sub-steps and Newton iterations), both through lbm_step: every field
