@@ -24,7 +24,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP64_VECTOR_PEAK_TFLOPS = 78.6  # MI355X FP64 vector
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2409_02930_amd", "csrc", f)
-                  for f in ("lbm_kernels.hip", "lbm_internal.h", "chem_jit.hip")]
+                  for f in ("lbm_kernels.hip", "lbm_device.h", "lbm_internal.h", "chem_jit.hip")]
 
 
 def kernel_sources_sha256():
