@@ -59,23 +59,25 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def kernel_bytes_per_node(w, kernel):
-    """Algorithmic HBM bytes per node of one launch (each value moved once)."""
+def kernel_bytes_per_node(w, kernel, pop_bytes=8):
+    """Algorithmic HBM bytes per node of one launch (each value moved once);
+    populations take pop_bytes each (8: FP64 storage, 4: FP32), records 8."""
     D, M, Q = w.lattice, w.M, 3 ** w.lattice
     chem = w.mech is not None or w.faradaic_rate is not None
     K = w.mech.K if w.mech is not None else 0
     E = 1 if w.energy_on else 0
     if kernel == "species":
-        rd = (M + 1 + E) * Q + 3                      # species + momentum (+ energy) pops, phi, kfac, T
-        wr = M * Q + D + 1 + (D if w.pore_radius and np.isfinite(w.pore_radius) else 0)
+        pops = (M + 1 + E) * Q + M * Q                # species + momentum (+ energy) read, species written
+        rd = 3                                        # phi, kfac, T
         rd += (M + D) if chem else 0                  # previous step's source and velocity (source populations)
+        wr = D + 1 + (D if w.pore_radius and np.isfinite(w.pore_radius) else 0)
         wr += (M + D) if chem else 0                  # chemistry input densities, node velocity
         wr += (1 + M + D) if E else 0
-        return 8 * (rd + wr)
+        return pop_bytes * pops + 8 * (rd + wr)
     if kernel == "mixture":
-        rd = (1 + E) * Q + 1 + D + 1 + D + (1 if chem else 0) + ((M + D + 1) if E else 0)
-        wr = (1 + E) * Q
-        return 8 * (rd + wr)
+        pops = 2 * (1 + E) * Q
+        rd = 1 + D + 1 + D + (1 if chem else 0) + ((M + D + 1) if E else 0)
+        return pop_bytes * pops + 8 * rd
     if kernel == "chem":
         return 8 * (M + 2 + K + K + M + 1)          # rho_a, T, phi, theta in/out, source, sum
     raise ValueError(kernel)
@@ -231,6 +233,8 @@ def main():
                     help="mechanism-specialised (default) or generic chemistry kernel")
     ap.add_argument("--graph-steps", type=int, default=32,
                     help="c4: steps per captured graph of the batched run (0 = plain launches)")
+    ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64",
+                    help="population storage (arithmetic is FP64 either way)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -259,7 +263,9 @@ def main():
     log(f"building workload {args.workload}")
     w = make_workload(args.workload)
     stream = torch.cuda.current_stream()
-    lat = lbm.lattice_from_workload(w, stream=stream.cuda_stream)
+    lat = lbm.lattice_from_workload(w, stream=stream.cuda_stream,
+                                    precision=lbm.FP32 if args.precision == "fp32" else lbm.FP64)
+    pop_bytes = 4 if args.precision == "fp32" else 8
     lat.set_chem_kernel(lbm.CHEM_SPECIALIZED if args.chem_kernel == "specialized" else lbm.CHEM_GENERIC)
     log(f"lattice ready N={w.N}; warmup {args.warmup}")
     lat.step(args.warmup)
@@ -282,7 +288,7 @@ def main():
     for k, ms in kernels.items():
         if ms <= 0 or (k == "chem" and w.mech is None and w.faradaic_rate is None):
             continue
-        b = kernel_bytes_per_node(w, k) * w.N
+        b = kernel_bytes_per_node(w, k, pop_bytes) * w.N
         per_kernel[k] = {"ms": ms, "GBps": b / (ms * 1e-3) / 1e9}
         if k == "chem":   # dense-LU-equivalent flops (the specialised kernel does fewer)
             per_kernel[k]["TFLOPs_dense_equiv"] = chem_flops_per_node(w) * w.N / (ms * 1e-3) / 1e12
@@ -291,14 +297,14 @@ def main():
         ach = per_kernel["chem"]["TFLOPs_dense_equiv"]
         roof = {"bound": "alu", "achieved": ach, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": ach / FP64_VECTOR_PEAK_TFLOPS,
-                "traffic": measured_traffic(args.workload, "k_chem"), "kernel": "k_chem"}
+                "traffic": measured_traffic(args.workload + ("_fp32" if args.precision == "fp32" else ""), "k_chem"), "kernel": "k_chem"}
     else:
         ach = per_kernel[dom]["GBps"]
         roof = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": ach / HBM_PEAK_GBS, "traffic": measured_traffic(args.workload, "k_" + dom),
-                "traffic_unit": "bytes per launch", "algorithmic_bytes": kernel_bytes_per_node(w, dom) * w.N,
+                "frac": ach / HBM_PEAK_GBS, "traffic": measured_traffic(args.workload + ("_fp32" if args.precision == "fp32" else ""), "k_" + dom),
+                "traffic_unit": "bytes per launch", "algorithmic_bytes": kernel_bytes_per_node(w, dom, pop_bytes) * w.N,
                 "kernel": "k_" + dom}
-    step_bytes = sum(kernel_bytes_per_node(w, k) for k in per_kernel) * w.N
+    step_bytes = sum(kernel_bytes_per_node(w, k, pop_bytes) for k in per_kernel) * w.N
     out = {
         "metric": "MLUPS", "value": mlups, "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
@@ -307,7 +313,8 @@ def main():
                                + (f" K={w.mech.K} R={w.mech.R} n_sub={w.mech.n_sub} n_newton={w.mech.n_newton}"
                                   if w.mech is not None else "")
                                + (f" chem={args.chem_kernel}" if w.mech is not None else "")
-                               + (" energy" if w.energy_on else ""),
+                               + (" energy" if w.energy_on else "")
+                               + (" fp32-storage" if args.precision == "fp32" else ""),
                    "nodes": w.N, "parallelism": "single GPU"},
         "kernels_ms": per_kernel,
         "step_GBps_algorithmic": step_bytes / (ms_step * 1e-3) / 1e9,

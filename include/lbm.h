@@ -28,9 +28,9 @@
  *     the configuration (NULL = the null stream); lbm_moments synchronises it.
  *   - Node index n = x + nx * (y + ny * z).  Field arrays are [component][node].
  *   - Lattice units delta_x = delta_t = 1; physical inputs are SI.
- *   - Population layout in HBM: [lattice][direction][node] FP64, lattices
- *     0..M-1 species, M momentum, M+1 energy; direction
- *     i = sum_a (c_ia + 1) 3^a.
+ *   - Population layout in HBM: [lattice][direction][node] FP64 (or FP32 with
+ *     precision = LBM_FP32), lattices 0..M-1 species, M momentum, M+1 energy;
+ *     direction i = sum_a (c_ia + 1) 3^a.  All arithmetic is FP64.
  */
 #ifndef LBM_H
 #define LBM_H
@@ -55,6 +55,7 @@ typedef enum {
 
 /* x-axis boundary kinds; y and z are periodic. */
 enum { LBM_BC_PERIODIC = 0, LBM_BC_BOUNCEBACK = 1, LBM_BC_INLET = 2, LBM_BC_OUTFLOW = 3 };
+enum { LBM_FP64 = 0, LBM_FP32 = 1 };   /* population storage (lbm_config.precision) */
 
 /* lbm_moments field mask; rows are written in this order, each [rows][N] FP64. */
 enum {
@@ -74,7 +75,8 @@ typedef struct {
   int32_t n_species;       /* M, 2..5                                                      */
   int32_t energy_on;       /* 1: energy lattice and temperature from eq temperature        */
   int32_t bc_lo_x, bc_hi_x;/* LBM_BC_* at x = 0 and x = nx-1 (periodic must be both)       */
-  int32_t reserved;
+  int32_t precision;       /* LBM_FP64 (0): populations stored in FP64; LBM_FP32 (1): stored
+                              in FP32, every step's arithmetic still FP64 (half the bytes)  */
   double dx_m;             /* lattice spacing, m                                            */
   double T_ref_K;          /* reference (maximum) temperature of the unit system, K         */
   double P_ref_Pa;         /* pressure unit, Pa                                             */

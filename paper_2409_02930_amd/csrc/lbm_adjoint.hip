@@ -903,7 +903,7 @@ __global__ __launch_bounds__(256) void k_adj_initial(const AdjParams<D, M> a) {
   double s = 0.0;
   for (int l = 0; l <= M; ++l)
     for (int i = 0; i < Q; ++i)
-      s += a.lam_next[(size_t)(l * Q + i) * N + n] * p.pin[(size_t)(l * Q + i) * N + n];
+      s += a.lam_next[(size_t)(l * Q + i) * N + n] * static_cast<const double *>(p.pin)[(size_t)(l * Q + i) * N + n];
   a.phibar[n] += s / p.phi[n];
 }
 

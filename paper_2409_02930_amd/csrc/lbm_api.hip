@@ -38,7 +38,8 @@ struct lbm_ctx {
   InletState inlet[2];
   bool have_inlet[2];
   // device buffers
-  double *pop[2] = {nullptr, nullptr};
+  double *pop[2] = {nullptr, nullptr};   // raw storage: double, or float when fp32
+  int fp32 = 0;                           // populations stored as float
   double *phi = nullptr, *kfac = nullptr, *Tfield = nullptr;
   double *X0 = nullptr, *Plat = nullptr;
   int8_t *colflag = nullptr;
@@ -101,6 +102,12 @@ int fail(lbm_ctx *c, int code, const char *fmt, ...) {
       return fail(ctx, LBM_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_));           \
   } while (0)
 
+// Doubles of storage for one population field (L Q N values, 4 or 8 bytes each).
+size_t pop_words(const lbm_ctx *c) {
+  const size_t n = (size_t)c->L * c->Q * c->N;
+  return c->fp32 ? (n + 1) / 2 : n;
+}
+
 int dalloc(lbm_ctx *c, double **p, size_t n) {
   if (n == 0) n = 1;
   hipError_t e = hipMalloc((void **)p, n * sizeof(double));
@@ -151,6 +158,7 @@ KParams base_params(const lbm_ctx *c) {
   p.bc_hi = c->bc_hi;
   p.knudsen = c->knudsen;
   p.colflag = c->colflag;
+  p.fp32 = c->fp32;
   p.theta_ref = c->theta_ref;
   p.inv_T_ref = 1.0 / c->T_ref;
   p.nu = c->nu;
@@ -220,6 +228,7 @@ int rebuild_populations(lbm_ctx *c) {
   ip.T0 = c->Tfield;
   ip.phi = c->phi;
   ip.pop = c->pop[0];
+  ip.fp32 = c->fp32;
   HIPCHK(c, launch_init(c->dim, ip, c->stream));
   c->cur = 0;
   c->first_step = 1;
@@ -245,6 +254,8 @@ int check_config(const lbm_config *cfg, lbm_ctx *c) {
   }
   if (!cfg->molar_mass || !cfg->D_ref_lat) return fail(c, LBM_EINVAL, "molar_mass and D_ref_lat are required");
   if (cfg->energy_on && (!cfg->cv || !cfg->u_form)) return fail(c, LBM_EINVAL, "energy lattice needs cv and u_form");
+  if (cfg->precision != LBM_FP64 && cfg->precision != LBM_FP32)
+    return fail(c, LBM_EINVAL, "precision must be LBM_FP64 or LBM_FP32");
   if (!(cfg->dx_m > 0) || !(cfg->T_ref_K > 0) || !(cfg->P_ref_Pa > 0) || !(cfg->theta_ref > 0) ||
       !(cfg->theta_ref <= 1.0) || !(cfg->nu_lat > 0) || !(cfg->prandtl > 0))
     return fail(c, LBM_EINVAL, "dx, T_ref, P_ref, theta_ref in (0,1], nu and Pr must be positive");
@@ -267,6 +278,7 @@ int common_init(const lbm_config *cfg, int N, const double *X0, const double *P0
   c->N = N;
   c->M = cfg->n_species;
   c->energy = cfg->energy_on ? 1 : 0;
+  c->fp32 = cfg->precision == LBM_FP32 ? 1 : 0;
   c->L = c->M + 1 + c->energy;
   c->Q = cfg->dim == 1 ? 3 : (cfg->dim == 2 ? 9 : 27);
   c->bc_lo = cfg->bc_lo_x;
@@ -325,7 +337,7 @@ int common_init(const lbm_config *cfg, int N, const double *X0, const double *P0
     }
   }
   // device allocations
-  const size_t popn = (size_t)c->L * c->Q * N;
+  const size_t popn = pop_words(c);
   int rc;
   if ((rc = dalloc(c, &c->pop[0], popn)) || (rc = dalloc(c, &c->pop[1], popn))) return rc;
   if ((rc = dalloc(c, &c->phi, N)) || (rc = dalloc(c, &c->kfac, N)) || (rc = dalloc(c, &c->Tfield, N)) ||
@@ -778,8 +790,8 @@ int lbm_adjoint_outlet_flux(lbm_ctx *c, int64_t n_steps, int32_t species, double
   if (!c || !J || !grad_phi || !grad_rp) return LBM_EINVAL;
   if (n_steps < 1) return fail(c, LBM_EINVAL, "n_steps must be >= 1");
   if (species < 0 || species >= c->M) return fail(c, LBM_EINVAL, "species out of range");
-  if (c->dim != 2 || c->energy || c->has_mech || c->has_faradaic || c->colflag)
-    return fail(c, LBM_EINVAL, "the adjoint covers isothermal, reaction-free D2Q9 grids");
+  if (c->dim != 2 || c->energy || c->has_mech || c->has_faradaic || c->colflag || c->fp32)
+    return fail(c, LBM_EINVAL, "the adjoint covers isothermal, reaction-free D2Q9 grids with FP64 storage");
   if (c->steps_done != 0) return fail(c, LBM_ESTATE, "the adjoint starts from the initial state (no step taken)");
   const size_t N = c->N, L = c->L, Q = c->Q, D = c->dim;
   const size_t P = L * Q * N, R = (size_t)kRec * N, A = D * N;
@@ -1026,7 +1038,7 @@ namespace {
 struct SnapHeader {
   uint64_t magic, N, L, Q, M, K, D;
   int64_t steps_done;
-  int32_t first_step, have_perm, pad0, pad1;
+  int32_t first_step, have_perm, fp32, pad1;
   int32_t perm[16];          // elimination order of the specialised chemistry kernel
 };
 constexpr uint64_t kMagic = 0x324d424c5844ull;
@@ -1035,7 +1047,7 @@ constexpr uint64_t kMagic = 0x324d424c5844ull;
 int lbm_save(lbm_ctx *c, void *buf, size_t *size) {
   if (!c || !size) return LBM_EINVAL;
   const size_t N = c->N, D = c->dim, M = c->M;
-  const size_t npop = (size_t)c->L * c->Q * N;
+  const size_t npop = pop_words(c);
   const size_t nrec = (size_t)kRec * N + (c->energy ? N : 0) + (c->has_mech ? (size_t)c->K * N : 0);
   const size_t need = sizeof(SnapHeader) + sizeof(double) * (npop + nrec);
   if (!buf) {
@@ -1055,6 +1067,7 @@ int lbm_save(lbm_ctx *c, void *buf, size_t *size) {
   h.steps_done = c->steps_done;
   h.first_step = c->first_step;
   h.have_perm = c->have_perm;
+  h.fp32 = c->fp32;
   memcpy(h.perm, c->chem_perm, sizeof(h.perm));
   memcpy(buf, &h, sizeof(h));
   double *o = (double *)((char *)buf + sizeof(h));
@@ -1079,9 +1092,9 @@ int lbm_load(lbm_ctx *c, const void *buf, size_t size) {
   memcpy(&h, buf, sizeof(h));
   const size_t N = c->N, D = c->dim, M = c->M;
   if (h.magic != kMagic || h.N != N || h.L != (uint64_t)c->L || h.Q != (uint64_t)c->Q || h.M != M ||
-      h.D != D || h.K != (uint64_t)c->K)
+      h.D != D || h.K != (uint64_t)c->K || h.fp32 != c->fp32)
     return fail(c, LBM_EINVAL, "snapshot does not match this context");
-  const size_t npop = (size_t)c->L * c->Q * N;
+  const size_t npop = pop_words(c);
   const size_t nrec = (size_t)kRec * N + (c->energy ? N : 0) + (c->has_mech ? (size_t)c->K * N : 0);
   if (size < sizeof(SnapHeader) + sizeof(double) * (npop + nrec)) return fail(c, LBM_EINVAL, "snapshot truncated");
   drop_graph(c);

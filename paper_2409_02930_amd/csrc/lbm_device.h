@@ -297,18 +297,25 @@ __device__ __forceinline__ double species_km(const KParams &p, int lat) {
 // Raw pull of lattice lat: stored populations that stream into this node.
 // Every stored population is read once, so the loads are non-temporal and
 // leave the L2 to the node records that neighbouring nodes re-read.
-template <int D>
+// P: storage type of the populations (double, or float with double arithmetic).
+template <int D, typename P = double>
 __device__ __forceinline__ void pull_populations(const KParams &p, const Node &nd, const PullGeo<D> &g, int lat,
                                                  double *f) {
   constexpr int Q = LQ<D>::Q;
   const int N = p.N;
-  const double *base = p.pin + (size_t)lat * Q * N;
+  const P *base = static_cast<const P *>(p.pin) + (size_t)lat * Q * N;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     int dir;
     const int src = pull_addr<D>(p, nd, g, i, dir);
-    f[i] = __builtin_nontemporal_load(base + (size_t)dir * N + src);   // read once: keep L2 for records
+    f[i] = (double)__builtin_nontemporal_load(base + (size_t)dir * N + src);   // read once: keep L2 for records
   }
+}
+
+// Stores one population in storage type P (float: rounded to nearest).
+template <typename P>
+__device__ __forceinline__ void store_pop(void *out, size_t idx, double v) {
+  __builtin_nontemporal_store((P)v, static_cast<P *>(out) + idx);
 }
 
 // Inlet directions of an inlet node take the inlet equilibrium.
@@ -326,11 +333,11 @@ __device__ __forceinline__ void inlet_replace(const KParams &p, const Node &nd, 
 // Pulls lattice lat into f (post-stream populations of this node).  With SRC,
 // species lattices also take the reaction population of the previous step at
 // the source node and direction.
-template <int D, int M, bool SRC = true>
+template <int D, int M, bool SRC = true, typename P = double>
 __device__ __forceinline__ void pull_lattice(const KParams &p, const Node &nd, const PullGeo<D> &g,
                                              int lat, double phi, const double *vb, bool inlet_node,
                                              double *f) {
-  pull_populations<D>(p, nd, g, lat, f);
+  pull_populations<D, P>(p, nd, g, lat, f);
   if (SRC && lat < M && p.src_prev)
     add_source_populations<D>(p, nd, g, p.rec_prev + (size_t)(kRecSrc + lat) * p.N, species_km<M>(p, lat), f);
   if (inlet_node) inlet_replace<D, M>(p, nd, lat, phi, vb, f);

@@ -34,6 +34,8 @@ struct KParams {
   int chem;                 // a chemistry source is computed this step
   int need_v;               // node velocities are needed by the next step
   int src_prev;             // species pulls add the reaction populations of the previous step
+  int fp32;                 // populations stored as float (arithmetic stays double)
+  int pad1;
   const int8_t *colflag;    // packed 1-D columns: bit0 = left end, bit1 = right end; NULL = grid
   double theta_ref, inv_T_ref, nu, prandtl;
   double mmin_over_m[LBM_MMAX];   // m_min / m_a
@@ -42,9 +44,9 @@ struct KParams {
   double imD[LBM_MMAX * LBM_MMAX];  // inv_m[b] / Dref[a][b]
   double cv[LBM_MMAX], uf[LBM_MMAX];   // lattice units (per kelvin, absolute)
   InletState inlet[2];            // x = 0 and x = nx - 1
-  // populations [lattice][direction][node]
-  const double *pin;
-  double *pout;
+  // populations [lattice][direction][node], double or float (fp32)
+  const void *pin;
+  void *pout;
   // static per-node fields
   const double *phi;        // porosity
   const double *kfac;       // (phi/tort) (d0 / 3 dx) sqrt(8/pi); D^k_a = kfac sqrt(R_a T)
@@ -89,13 +91,13 @@ struct ChemParams {
 };
 
 struct InitParams {
-  int N, M, energy, pad;
+  int N, M, energy, fp32;
   double theta_ref, inv_T_ref;
   double mmin_over_m[LBM_MMAX];
   double inv_m[LBM_MMAX];
   double cv[LBM_MMAX], uf[LBM_MMAX];
   const double *X0, *Plat, *T0, *phi;
-  double *pop;
+  void *pop;                // double or float (fp32)
 };
 
 // Macroscopic output set of the moments kernel: rows
@@ -122,7 +124,7 @@ hipError_t launch_species(int dim, const KParams &p, hipStream_t s);
 hipError_t launch_mixture(int dim, const KParams &p, hipStream_t s);
 hipError_t launch_chem(const ChemParams &cp, hipStream_t s);
 hipError_t launch_moments(int dim, const KParams &p, double *out, hipStream_t s);
-hipError_t launch_diag(int dim, int L, int Mmom, const KParams &p, const double *pop, double *partials,
+hipError_t launch_diag(int dim, int L, int Mmom, const KParams &p, const void *pop, double *partials,
                        int nblocks, hipStream_t s);
 int chem_supported(int M, int K);
 

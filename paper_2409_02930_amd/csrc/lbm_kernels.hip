@@ -39,7 +39,7 @@ struct SpeciesState {
   double sumg;
 };
 
-template <int D, int M, bool ENERGY>
+template <int D, int M, bool ENERGY, typename PT>
 __device__ __forceinline__ void species_front(const KParams &p, const Node &nd, double phi,
                                               SpeciesState<D, M> &S) {
   constexpr int Q = LQ<D>::Q;
@@ -57,7 +57,7 @@ __device__ __forceinline__ void species_front(const KParams &p, const Node &nd, 
   for (int d = 0; d < D; ++d) jf[d] = 0.0;
   {
     double fm[Q];
-    pull_lattice<D, M>(p, nd, geo, M, phi, vb, inlet_node, fm);
+    pull_lattice<D, M, true, PT>(p, nd, geo, M, phi, vb, inlet_node, fm);
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
       sf += fm[i];
@@ -75,7 +75,7 @@ __device__ __forceinline__ void species_front(const KParams &p, const Node &nd, 
   S.sumg = 0.0;
   if (ENERGY) {
     double g[Q];
-    pull_lattice<D, M>(p, nd, geo, M + 1, phi, vb, inlet_node, g);
+    pull_lattice<D, M, true, PT>(p, nd, geo, M + 1, phi, vb, inlet_node, g);
     double sg = 0.0;
 #pragma unroll
     for (int i = 0; i < Q; ++i) sg += g[i];
@@ -83,7 +83,7 @@ __device__ __forceinline__ void species_front(const KParams &p, const Node &nd, 
   }
   // ---- species lattices
 #pragma unroll
-  for (int a = 0; a < M; ++a) pull_lattice<D, M>(p, nd, geo, a, phi, vb, inlet_node, S.f[a]);
+  for (int a = 0; a < M; ++a) pull_lattice<D, M, true, PT>(p, nd, geo, a, phi, vb, inlet_node, S.f[a]);
   // ---- species moments (eqs density1, momentum1)
 #pragma unroll
   for (int a = 0; a < M; ++a) {
@@ -452,7 +452,7 @@ __device__ __forceinline__ void species_momenta(const SpeciesShared<D, M, ENERGY
   }
 }
 
-template <int D, int M, bool ENERGY>
+template <int D, int M, bool ENERGY, typename PT>
 __global__ __launch_bounds__(64 * (M + 1 + (ENERGY ? 1 : 0))) void k_species(const KParams p) {
   constexpr int Q = LQ<D>::Q;
   __shared__ SpeciesShared<D, M, ENERGY> sh;
@@ -503,7 +503,7 @@ __global__ __launch_bounds__(64 * (M + 1 + (ENERGY ? 1 : 0))) void k_species(con
   Stage<D, M, ENERGY> st;
   if (rows) load_stage<D, M, ENERGY>(p, nd, w, lane, st);
   double f[Q];
-  if (valid) pull_populations<D>(p, nd, geo, lat, f);
+  if (valid) pull_populations<D, PT>(p, nd, geo, lat, f);
   if (p.src_prev) {
     if (rows) store_stage<D, M, ENERGY>(w, lane, st, sh);
     __syncthreads();
@@ -598,7 +598,7 @@ __global__ __launch_bounds__(64 * (M + 1 + (ENERGY ? 1 : 0))) void k_species(con
     }
     __syncthreads();
     if (valid) {
-      double *out = p.pout + (size_t)(a * Q) * N + n;
+      const size_t o = (size_t)(a * Q) * N + n;
 #pragma unroll
       for (int i = 0; i < Q; ++i) {
         double F = 0.0;                            // iab[a] == 0: the own term drops out
@@ -612,7 +612,7 @@ __global__ __launch_bounds__(64 * (M + 1 + (ENERGY ? 1 : 0))) void k_species(con
         const double fk = pra * pk;
         const double Fi = Ya * F + itk_a * (fst - fk);
         const double f0 = f[i];
-        __builtin_nontemporal_store(f0 + 2.0 * beta * (feq - f0) + (beta - 1.0) * Fi, out + (size_t)i * N);
+        store_pop<PT>(p.pout, o + (size_t)i * N, f0 + 2.0 * beta * (feq - f0) + (beta - 1.0) * Fi);
       }
     }
   } else if (w == M) {
@@ -682,7 +682,7 @@ __global__ __launch_bounds__(64 * (M + 1 + (ENERGY ? 1 : 0))) void k_species(con
 // ---------------------------------------------------------------------------
 // k_mixture: momentum lattice with the extended equilibrium, energy lattice
 // ---------------------------------------------------------------------------
-template <int D, int M, bool ENERGY>
+template <int D, int M, bool ENERGY, typename PT>
 __global__ __launch_bounds__(256) void k_mixture(const KParams p) {
   constexpr int Q = LQ<D>::Q;
   Node nd;
@@ -697,7 +697,7 @@ __global__ __launch_bounds__(256) void k_mixture(const KParams p) {
   const PullGeo<D> geo = pull_geo<D>(p, nd);
 
   double f[Q];
-  pull_lattice<D, M>(p, nd, geo, M, phi, vb, inlet_node, f);
+  pull_lattice<D, M, true, PT>(p, nd, geo, M, phi, vb, inlet_node, f);
   double sf = 0.0, jf[D];
 #pragma unroll
   for (int d = 0; d < D; ++d) jf[d] = 0.0;
@@ -745,7 +745,7 @@ __global__ __launch_bounds__(256) void k_mixture(const KParams p) {
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     const double fex = phirho * psi_dir<D>(i, xi, Pex);
-    __builtin_nontemporal_store(f[i] + omega * (fex - f[i]) + ratio * fex, p.pout + (size_t)(M * Q + i) * N + n);
+    store_pop<PT>(p.pout, (size_t)(M * Q + i) * N + n, f[i] + omega * (fex - f[i]) + ratio * fex);
   }
 
   if (ENERGY) {
@@ -797,7 +797,7 @@ __global__ __launch_bounds__(256) void k_mixture(const KParams p) {
     double g[Q], q[D];
 #pragma unroll
     for (int d = 0; d < D; ++d) q[d] = 0.0;
-    pull_lattice<D, M>(p, nd, geo, M + 1, phi, vb, inlet_node, g);
+    pull_lattice<D, M, true, PT>(p, nd, geo, M + 1, phi, vb, inlet_node, g);
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
 #pragma unroll
@@ -829,7 +829,7 @@ __global__ __launch_bounds__(256) void k_mixture(const KParams p) {
         for (int d = 0; d < D; ++d) cq += cdir(i, d) * Qv[d];
         out += 0.5 * cq;
       }
-      __builtin_nontemporal_store(out, p.pout + (size_t)((M + 1) * Q + i) * N + n);
+      store_pop<PT>(p.pout, (size_t)((M + 1) * Q + i) * N + n, out);
     }
   }
 }
@@ -837,7 +837,7 @@ __global__ __launch_bounds__(256) void k_mixture(const KParams p) {
 // ---------------------------------------------------------------------------
 // moments kernel: macroscopic fields at the current time level
 // ---------------------------------------------------------------------------
-template <int D, int M, bool ENERGY>
+template <int D, int M, bool ENERGY, typename PT>
 __global__ __launch_bounds__(256) void k_moments(const KParams p, double *out) {
   Node nd;
   if (!get_node(p, nd)) return;
@@ -845,7 +845,7 @@ __global__ __launch_bounds__(256) void k_moments(const KParams p, double *out) {
   const int n = nd.n;
   const double phi = p.phi[n];
   SpeciesState<D, M> S;
-  species_front<D, M, ENERGY>(p, nd, phi, S);
+  species_front<D, M, ENERGY, PT>(p, nd, phi, S);
   size_t r = 0;
   double rs = 0.0;
 #pragma unroll
@@ -868,7 +868,7 @@ __global__ __launch_bounds__(256) void k_moments(const KParams p, double *out) {
 // ---------------------------------------------------------------------------
 // initial equilibria at zero velocity (stored post-stream)
 // ---------------------------------------------------------------------------
-template <int D, int M>
+template <int D, int M, typename PT>
 __global__ __launch_bounds__(256) void k_init(const InitParams ip) {
   constexpr int Q = LQ<D>::Q;
   const int n = blockIdx.x * blockDim.x + threadIdx.x;
@@ -893,16 +893,17 @@ __global__ __launch_bounds__(256) void k_init(const InitParams ip) {
     U += Y * (ip.uf[a] + ip.cv[a] * T);
   }
   const double zero[3] = {0.0, 0.0, 0.0};
+  PT *pop = static_cast<PT *>(ip.pop);
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
 #pragma unroll
     for (int a = 0; a < M; ++a) {
-      double P[3] = {RaT[a], RaT[a], RaT[a]};
-      ip.pop[(size_t)(a * Q + i) * N + n] = phi * rho_a[a] * psi_dir<D>(i, zero, P);
+      const double Pa[3] = {RaT[a], RaT[a], RaT[a]};
+      pop[(size_t)(a * Q + i) * N + n] = (PT)(phi * rho_a[a] * psi_dir<D>(i, zero, Pa));
     }
-    double P[3] = {RT, RT, RT};
-    ip.pop[(size_t)(M * Q + i) * N + n] = phi * rho * psi_dir<D>(i, zero, P);
-    if (ip.energy) ip.pop[(size_t)((M + 1) * Q + i) * N + n] = geq_dir<D>(i, phi * rho, U, RT, zero);
+    const double Pm[3] = {RT, RT, RT};
+    pop[(size_t)(M * Q + i) * N + n] = (PT)(phi * rho * psi_dir<D>(i, zero, Pm));
+    if (ip.energy) pop[(size_t)((M + 1) * Q + i) * N + n] = (PT)geq_dir<D>(i, phi * rho, U, RT, zero);
   }
 }
 
@@ -1188,8 +1189,8 @@ __device__ __forceinline__ double block_sum(double v, double *sh) {
 
 // Totals of the stored state.  Species populations include the reaction
 // population the last step added after its collision (p.src_prev).
-template <int D>
-__global__ __launch_bounds__(256) void k_diag(int L, int Mmom, const KParams p, const double *pop,
+template <int D, typename PT>
+__global__ __launch_bounds__(256) void k_diag(int L, int Mmom, const KParams p, const PT *pop,
                                               double *partials) {
   __shared__ double sh[256];
   constexpr int Q = LQ<D>::Q;
@@ -1205,7 +1206,7 @@ __global__ __launch_bounds__(256) void k_diag(int L, int Mmom, const KParams p, 
       const double km = src ? p.theta_ref * p.mmin_over_m[l] : 0.0;
       const double *sa = p.rec_prev + (size_t)(kRecSrc + l) * N;
       for (int i = 0; i < Q; ++i) {
-        double v = pop[(size_t)(l * Q + i) * N + n];
+        double v = (double)pop[(size_t)(l * Q + i) * N + n];
         if (src) v += source_population<D>(load_src<D>(p.rec_prev, sa, p.T_prev, (size_t)N, n), km, p.inv_T_ref, i);
         if (!isfinite(v)) bad += 1.0;
         s += v;
@@ -1220,7 +1221,7 @@ __global__ __launch_bounds__(256) void k_diag(int L, int Mmom, const KParams p, 
     if (n < N) {
       for (int i = 0; i < Q; ++i) {
         const int c = ((d == 0 ? i : (d == 1 ? i / 3 : i / 9)) % 3) - 1;
-        s += c * pop[(size_t)(Mmom * Q + i) * N + n];
+        s += c * (double)pop[(size_t)(Mmom * Q + i) * N + n];
       }
     }
     const double r = block_sum(s, sh);
@@ -1243,34 +1244,49 @@ unsigned padded_blocks(int N, int bs) {
   return (nb + 7u) & ~7u;
 }
 
-template <int D, int M>
-hipError_t species_dispatch_e(const KParams &p, hipStream_t s) {
+template <int D, int M, typename PT>
+hipError_t species_dispatch_p(const KParams &p, hipStream_t s) {
   const unsigned nb = padded_blocks(p.N, 64);
   if (p.energy)
-    hipLaunchKernelGGL((k_species<D, M, true>), dim3(nb), dim3(64 * (M + 2)), 0, s, p);
+    hipLaunchKernelGGL((k_species<D, M, true, PT>), dim3(nb), dim3(64 * (M + 2)), 0, s, p);
   else
-    hipLaunchKernelGGL((k_species<D, M, false>), dim3(nb), dim3(64 * (M + 1)), 0, s, p);
+    hipLaunchKernelGGL((k_species<D, M, false, PT>), dim3(nb), dim3(64 * (M + 1)), 0, s, p);
+  return hipGetLastError();
+}
+
+template <int D, int M>
+hipError_t species_dispatch_e(const KParams &p, hipStream_t s) {
+  return p.fp32 ? species_dispatch_p<D, M, float>(p, s) : species_dispatch_p<D, M, double>(p, s);
+}
+
+template <int D, int M, typename PT>
+hipError_t mixture_dispatch_p(const KParams &p, hipStream_t s) {
+  const unsigned nb = padded_blocks(p.N, 256);
+  if (p.energy)
+    hipLaunchKernelGGL((k_mixture<D, M, true, PT>), dim3(nb), dim3(256), 0, s, p);
+  else
+    hipLaunchKernelGGL((k_mixture<D, M, false, PT>), dim3(nb), dim3(256), 0, s, p);
   return hipGetLastError();
 }
 
 template <int D, int M>
 hipError_t mixture_dispatch_e(const KParams &p, hipStream_t s) {
+  return p.fp32 ? mixture_dispatch_p<D, M, float>(p, s) : mixture_dispatch_p<D, M, double>(p, s);
+}
+
+template <int D, int M, typename PT>
+hipError_t moments_dispatch_p(const KParams &p, double *out, hipStream_t s) {
   const unsigned nb = padded_blocks(p.N, 256);
   if (p.energy)
-    hipLaunchKernelGGL((k_mixture<D, M, true>), dim3(nb), dim3(256), 0, s, p);
+    hipLaunchKernelGGL((k_moments<D, M, true, PT>), dim3(nb), dim3(256), 0, s, p, out);
   else
-    hipLaunchKernelGGL((k_mixture<D, M, false>), dim3(nb), dim3(256), 0, s, p);
+    hipLaunchKernelGGL((k_moments<D, M, false, PT>), dim3(nb), dim3(256), 0, s, p, out);
   return hipGetLastError();
 }
 
 template <int D, int M>
 hipError_t moments_dispatch_e(const KParams &p, double *out, hipStream_t s) {
-  const unsigned nb = padded_blocks(p.N, 256);
-  if (p.energy)
-    hipLaunchKernelGGL((k_moments<D, M, true>), dim3(nb), dim3(256), 0, s, p, out);
-  else
-    hipLaunchKernelGGL((k_moments<D, M, false>), dim3(nb), dim3(256), 0, s, p, out);
-  return hipGetLastError();
+  return p.fp32 ? moments_dispatch_p<D, M, float>(p, out, s) : moments_dispatch_p<D, M, double>(p, out, s);
 }
 
 template <int D>
@@ -1306,17 +1322,22 @@ hipError_t moments_dispatch(const KParams &p, double *out, hipStream_t s) {
   return hipErrorInvalidValue;
 }
 
-template <int D>
-hipError_t init_dispatch(const InitParams &ip, hipStream_t s) {
+template <int D, typename PT>
+hipError_t init_dispatch_p(const InitParams &ip, hipStream_t s) {
   const unsigned nb = (unsigned)((ip.N + 255) / 256);
   switch (ip.M) {
-    case 2: hipLaunchKernelGGL((k_init<D, 2>), dim3(nb), dim3(256), 0, s, ip); break;
-    case 3: hipLaunchKernelGGL((k_init<D, 3>), dim3(nb), dim3(256), 0, s, ip); break;
-    case 4: hipLaunchKernelGGL((k_init<D, 4>), dim3(nb), dim3(256), 0, s, ip); break;
-    case 5: hipLaunchKernelGGL((k_init<D, 5>), dim3(nb), dim3(256), 0, s, ip); break;
+    case 2: hipLaunchKernelGGL((k_init<D, 2, PT>), dim3(nb), dim3(256), 0, s, ip); break;
+    case 3: hipLaunchKernelGGL((k_init<D, 3, PT>), dim3(nb), dim3(256), 0, s, ip); break;
+    case 4: hipLaunchKernelGGL((k_init<D, 4, PT>), dim3(nb), dim3(256), 0, s, ip); break;
+    case 5: hipLaunchKernelGGL((k_init<D, 5, PT>), dim3(nb), dim3(256), 0, s, ip); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+template <int D>
+hipError_t init_dispatch(const InitParams &ip, hipStream_t s) {
+  return ip.fp32 ? init_dispatch_p<D, float>(ip, s) : init_dispatch_p<D, double>(ip, s);
 }
 
 }  // namespace
@@ -1386,12 +1407,20 @@ hipError_t launch_chem(const ChemParams &cp, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_diag(int dim, int L, int Mmom, const KParams &p, const double *pop, double *partials,
-                       int nblocks, hipStream_t s) {
+template <typename PT>
+hipError_t diag_dispatch(int dim, int L, int Mmom, const KParams &p, const void *pop, double *partials,
+                         int nblocks, hipStream_t s) {
+  const PT *q = static_cast<const PT *>(pop);
   switch (dim) {
-    case 1: hipLaunchKernelGGL(k_diag<1>, dim3(nblocks), dim3(256), 0, s, L, Mmom, p, pop, partials); break;
-    case 2: hipLaunchKernelGGL(k_diag<2>, dim3(nblocks), dim3(256), 0, s, L, Mmom, p, pop, partials); break;
-    default: hipLaunchKernelGGL(k_diag<3>, dim3(nblocks), dim3(256), 0, s, L, Mmom, p, pop, partials); break;
+    case 1: hipLaunchKernelGGL((k_diag<1, PT>), dim3(nblocks), dim3(256), 0, s, L, Mmom, p, q, partials); break;
+    case 2: hipLaunchKernelGGL((k_diag<2, PT>), dim3(nblocks), dim3(256), 0, s, L, Mmom, p, q, partials); break;
+    default: hipLaunchKernelGGL((k_diag<3, PT>), dim3(nblocks), dim3(256), 0, s, L, Mmom, p, q, partials); break;
   }
   return hipGetLastError();
+}
+
+hipError_t launch_diag(int dim, int L, int Mmom, const KParams &p, const void *pop, double *partials,
+                       int nblocks, hipStream_t s) {
+  return p.fp32 ? diag_dispatch<float>(dim, L, Mmom, p, pop, partials, nblocks, s)
+                : diag_dispatch<double>(dim, L, Mmom, p, pop, partials, nblocks, s);
 }

@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "_lib", "liblbm.so")
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EHIP, LBM_ESTATE, LBM_EUNSTABLE = 0, -1, -2, -3, -4, -5
 BC_PERIODIC, BC_BOUNCEBACK, BC_INLET, BC_OUTFLOW = 0, 1, 2, 3
 CHEM_SPECIALIZED, CHEM_GENERIC = 0, 1
+FP64, FP32 = 0, 1             # population storage; arithmetic is FP64 either way
 
 MOM_RHO_SPECIES = 1 << 0
 MOM_VELOCITY = 1 << 1
@@ -38,7 +39,7 @@ class lbm_config(C.Structure):
     _fields_ = [
         ("dim", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
         ("n_species", C.c_int32), ("energy_on", C.c_int32), ("bc_lo_x", C.c_int32),
-        ("bc_hi_x", C.c_int32), ("reserved", C.c_int32),
+        ("bc_hi_x", C.c_int32), ("precision", C.c_int32),
         ("dx_m", C.c_double), ("T_ref_K", C.c_double), ("P_ref_Pa", C.c_double),
         ("theta_ref", C.c_double), ("nu_lat", C.c_double), ("prandtl", C.c_double),
         ("molar_mass", _dp), ("D_ref_lat", _dp), ("cv", _dp), ("u_form", _dp),
@@ -130,7 +131,7 @@ class Lattice:
                  T_ref=1073.0, P_ref=101325.0, theta_ref=1.0 / 3.0, nu_lat=0.05, prandtl=0.7,
                  energy_on=False, cv=None, u_form=None, bc_lo=BC_PERIODIC, bc_hi=BC_PERIODIC,
                  inlet_lo_X=None, inlet_hi_X=None, inlet_P=101325.0, inlet_T=1073.0,
-                 stream=None, col_len=None):
+                 stream=None, col_len=None, precision=FP64):
         self._keep = []
         m = _arr(molar_mass)
         M = int(m.shape[0])
@@ -140,6 +141,7 @@ class Lattice:
         cfg.n_species = M
         cfg.energy_on = 1 if energy_on else 0
         cfg.bc_lo_x, cfg.bc_hi_x = bc_lo, bc_hi
+        cfg.precision = int(precision)
         cfg.dx_m, cfg.T_ref_K, cfg.P_ref_Pa, cfg.theta_ref = dx, T_ref, P_ref, theta_ref
         cfg.nu_lat, cfg.prandtl = nu_lat, prandtl
         arrays = dict(molar_mass=m, D_ref_lat=Dm, cv=_arr(cv), u_form=_arr(u_form),
@@ -306,13 +308,13 @@ class Lattice:
         self._check(_lib.lbm_load(self.ctx, buf, len(blob)))
 
 
-def lattice_from_workload(w, stream=None, col_len=None) -> Lattice:
+def lattice_from_workload(w, stream=None, col_len=None, precision=FP64) -> Lattice:
     """Builds a Lattice from a workload description (attribute names as in workloads.synth)."""
     lat = Lattice(w.lattice, w.nx, w.ny, w.nz, w.molar_mass, w.D_ref_lat, w.X0, w.T0, w.P0,
                   dx=w.dx, T_ref=w.T_ref, P_ref=w.P_ref, theta_ref=w.theta_ref, nu_lat=w.nu_lat,
                   prandtl=w.prandtl, energy_on=w.energy_on, cv=w.cv, u_form=w.u_form,
                   bc_lo=w.bc_lo, bc_hi=w.bc_hi, inlet_lo_X=w.inlet_lo_X, inlet_hi_X=w.inlet_hi_X,
-                  inlet_P=w.inlet_P, inlet_T=w.inlet_T, stream=stream, col_len=col_len)
+                  inlet_P=w.inlet_P, inlet_T=w.inlet_T, stream=stream, col_len=col_len, precision=precision)
     lat.set_porous_field(w.phi, w.tort, w.pore_radius if w.pore_radius is not None else float("inf"))
     if w.faradaic_rate is not None:
         lat.set_faradaic_source(w.faradaic_rate, *w.faradaic_species)
