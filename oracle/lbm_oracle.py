@@ -419,6 +419,20 @@ class Oracle:
             src[:, pr] += r * self.m[pr] / self.rho_unit
         return src.T.copy(), th.T.copy()
 
+    def surface_energy(self, theta, T):
+        """Internal energy of the adsorbed phase per unit volume, lattice units
+        (eq temperatureCell, adsorbed part): a_s rho^(s) sum_k Y_k U_k(T) with
+        rho^(s) Y_k = Gamma theta_k m_k and U_k = u_form_k + cv_k T.  Zero
+        without adsorbed-phase thermo."""
+        mech = self.mech
+        if mech is None or mech.surf_cv is None:
+            return np.zeros(self.N)
+        m_k = np.asarray(mech.surf_mass, dtype=np.float64)
+        Uk = (np.asarray(mech.surf_u_form, dtype=np.float64)[:, None]
+              + np.asarray(mech.surf_cv, dtype=np.float64)[:, None] * np.asarray(T)[None, :])   # J/kg
+        dens = mech.a_s * mech.gamma * m_k[:, None] * theta                                    # kg/m^3
+        return (dens * Uk).sum(axis=0) / (self.rho_unit * self.c2)
+
     # ----- one time step ---------------------------------------------------
     def step(self, n: int = 1):
         for _ in range(n):
@@ -511,6 +525,15 @@ class Oracle:
             for i in range(Q):
                 if int(np.abs(c[i]).sum()) == 1:
                     new_g[i] = new_g[i] + 0.5 * sum(c[i, d] * Qv[d] for d in range(D))
+            if self.mech is not None or w.faradaic_rate is not None:
+                # eqs temperatureCell, InternalEnergyCell_PC, g0mom_source, g_source (R27): the
+                # unified internal energy (fluid + adsorbed phase, one T) is kept through the
+                # chemistry, so the fluid's phi rho^pc U^pc = phi rho U + (E_s before - E_s after);
+                # g^eq,source is g^eq with (rho^pc, U^pc), pre-collision v and RT.
+                phirho_pc = phi * rho + src.sum(axis=0)
+                dEs = self.surface_energy(self.theta, T) - self.surface_energy(theta_new, T)
+                U_pc = (phi * rho * Umix + dEs) / phirho_pc
+                new_g = new_g + (self.g_equilibrium(phirho_pc, U_pc, RT, v) - geq)
         else:
             new_g = None
         # S11 streaming + boundary conditions

@@ -443,3 +443,37 @@ def test_thermal_decay_matches_thermal_diffusivity(x1):
     k = 2 * math.pi / nx
     alpha = w.nu_lat / w.prandtl
     assert abs(rate / (alpha * k * k) - 1.0) < 0.03
+
+
+def test_energy_density_unit_against_si():
+    """The lattice energy density unit is rho_unit c^2 (Section 5.2 unit system,
+    R16): the energy lattice's initial zeroth moment at rest, times rho_unit c^2,
+    equals the SI internal energy density phi sum_a c_a m_a (u_form_a + cv_a T)
+    with c_a = X_a P / (R_U T) of the ideal-gas inputs."""
+    w = synth.config3_energy(nx=6, ny=4, nz=3)
+    o = lo.Oracle(w)
+    T = np.asarray(w.T0)
+    c_a = np.asarray(w.X0) * np.asarray(w.P0)[None, :] / (lo.R_U * T[None, :])          # mol/m^3
+    m = np.asarray(w.molar_mass)
+    U_si = (c_a * m[:, None] * (np.asarray(w.u_form)[:, None] + np.asarray(w.cv)[:, None] * T[None, :])).sum(axis=0)
+    got = o.g.sum(axis=0) * o.rho_unit * o.c2
+    assert np.allclose(got, np.asarray(w.phi) * U_si, rtol=1e-13, atol=0.0)
+
+
+def test_unified_internal_energy_kept_through_chemistry():
+    """Eqs temperatureCell, InternalEnergyCell_PC, g0mom_source and g_source:
+    without electrical sources the unified internal energy (fluid + adsorbed
+    phase at one T) is unchanged by the chemistry, so over one step from rest
+    (v = 0, periodic, the collision and the stream keep sum g) the fluid's
+    energy total changes by minus the adsorbed phase's change, both at the
+    step's temperature.  A dropped or sign-flipped source term fails."""
+    w = synth.config3_energy(nx=6, ny=4, nz=3)
+    o = lo.Oracle(w)
+    T1 = o.macro()["T"]
+    es0 = o.surface_energy(o.theta, T1).sum()
+    g0 = o.g.sum()
+    o.step(1)
+    des = o.surface_energy(o.theta, T1).sum() - es0
+    dg = o.g.sum() - g0
+    assert abs(des) > 1e-6 * abs(g0)                       # the adsorbed phase really took energy
+    assert abs(dg + des) <= 1e-9 * abs(des), (dg, des)

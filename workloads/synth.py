@@ -51,6 +51,10 @@ class Mechanism:
     theta0: np.ndarray        # (K,) initial coverages
     n_sub: int = 4
     n_newton: int = 6
+    # adsorbed-phase thermo for the energy lattice, U_k = u_form_k + cv_k T (J/kg);
+    # None: no internal energy in the adsorbed phase
+    surf_cv: Optional[np.ndarray] = None        # (K,) J/(kg K)
+    surf_u_form: Optional[np.ndarray] = None    # (K,) J/kg
 
     @property
     def R(self) -> int:
@@ -271,6 +275,24 @@ def config3(nx: int = 256, ny: int = 128, nz: int = 128, steps: int = 2000, seed
                     molar_mass=m_kg, D_ref_lat=synthetic_D_ref(m), X0=X0,
                     P0=_uniform(N, P_ATM), T0=T, phi=phi, tort=phi ** -0.5,
                     pore_radius=1e-6, steps=steps, T_ref=1073.0, mech=mech)
+
+
+def config3_energy(nx: int = 10, ny: int = 6, nz: int = 4, seed: int = 3) -> Workload:
+    """C3 physics with the energy lattice on (a unit-test case, not a benchmark):
+    gas cv_a = (5/2) R_U / m_a, u_form 0; adsorbates with the same molar heat
+    capacity (cv_k = (5/2) R_U / m_k) and a formation energy of -20 kJ/mol for
+    the composites, so adsorption moves internal energy between the phases."""
+    R_U = 8.314462618
+    w = config3(nx=nx, ny=ny, nz=nz, seed=seed)
+    m = np.asarray(w.molar_mass)
+    sm = np.asarray(w.mech.surf_mass)
+    with np.errstate(divide="ignore"):
+        scv = np.where(sm > 0, 2.5 * R_U / np.where(sm > 0, sm, 1.0), 0.0)
+    suf = np.zeros_like(sm)
+    suf[6:] = -2.0e4 / sm[6:]
+    mech = replace(w.mech, surf_cv=scv, surf_u_form=suf)
+    return replace(w, name="c3_energy_reactive", energy_on=True, cv=2.5 * R_U / m, u_form=np.zeros(len(m)),
+                   mech=mech)
 
 
 def config4_columns(seed: int = 4, n_cols: int = 64, lmin: int = 200, lmax: int = 2000):
