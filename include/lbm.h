@@ -112,8 +112,15 @@ typedef struct {
   const double *A_b, *Ea_b;
   double gamma;            /* site density Gamma, mol/m^2 (eq surfaceMoleFractions)        */
   double a_s;              /* specific surface area a^(s), 1/m (eq totalFluidReactionRate) */
-  const double *surf_mass; /* [K] kg/mol (mass bookkeeping only)                           */
+  const double *surf_mass; /* [K] kg/mol (mass bookkeeping; adsorbed-phase energy)         */
   const double *theta0;    /* [K] initial coverages, applied to every node                 */
+  const double *surf_cv;   /* [K] J/(kg K) or NULL: adsorbed-phase internal energy         */
+  const double *surf_u_form;/* [K] J/kg or NULL: U_k = u_form_k + cv_k T (eq temperatureCell).
+                              With the energy lattice on, the chemistry keeps the unified
+                              internal energy (fluid + adsorbed phase at one T, eq
+                              InternalEnergyCell_PC) and the energy collision takes
+                              g^eq,source - g^eq (eqs g0mom_source, g_source); surf_cv NULL
+                              means no adsorbed-phase energy (surf_mass required otherwise) */
 } lbm_mechanism;
 
 /* Creates a context for a rectangular grid.  X0 [M][N] mole fractions, P0 [N]

@@ -48,6 +48,9 @@ struct lbm_ctx {
   double *T[2] = {nullptr, nullptr};
   double *srcsum = nullptr;
   double *theta = nullptr;
+  double *rEs = nullptr;                  // [N] adsorbed-phase energy before the chemistry
+  int esrc = 0;                           // adsorbed-phase thermo given (energy lattice)
+  double es_u[LBM_KMAX] = {}, es_c[LBM_KMAX] = {};
   double *faradaic = nullptr;
   double *macro = nullptr;
   double *partials = nullptr;
@@ -183,6 +186,12 @@ KParams base_params(const lbm_ctx *c) {
   p.rrho = c->rrho;
   p.rY = c->rY;
   p.rqd = c->rqd;
+  p.K = c->has_mech ? c->K : 0;
+  p.esrc = c->esrc;
+  p.theta = c->theta;
+  p.rEs = c->rEs;
+  memcpy(p.es_u, c->es_u, sizeof(p.es_u));
+  memcpy(p.es_c, c->es_c, sizeof(p.es_c));
   return p;
 }
 
@@ -471,6 +480,7 @@ int enqueue_step(lbm_ctx *c, int record_slot) {
   if (ev) HIPCHK(c, hipEventRecord(ev[0], c->stream));
   HIPCHK(c, launch_species(c->dim, p, c->stream));
   if (ev) HIPCHK(c, hipEventRecord(ev[1], c->stream));
+  if (p.esrc) HIPCHK(c, launch_surface_energy(p, c->stream));   // before the coverages change
   if (chem) {
     ChemParams cp = c->chem;
     cp.N = c->N;
@@ -640,6 +650,7 @@ int lbm_set_mechanism(lbm_ctx *c, const lbm_mechanism *mech) {
   if (!mech) {
     c->has_mech = 0;
     c->K = 0;
+    c->esrc = 0;
     return LBM_OK;
   }
   const int M = c->M, K = mech->n_surface, R = mech->n_reactions, S = M + K;
@@ -702,6 +713,27 @@ int lbm_set_mechanism(lbm_ctx *c, const lbm_mechanism *mech) {
   for (int s = 0; s < K; ++s)
     for (int n = 0; n < c->N; ++n) th[(size_t)s * c->N + n] = mech->theta0[s];
   HIPCHK(c, hipMemcpy(c->theta, th.data(), sizeof(double) * th.size(), hipMemcpyHostToDevice));
+  // adsorbed-phase internal energy per unit volume, lattice units (eq temperatureCell):
+  // a_s Gamma theta_k m_k (u_form_k + cv_k T) / (rho_unit c^2)
+  c->esrc = 0;
+  memset(c->es_u, 0, sizeof(c->es_u));
+  memset(c->es_c, 0, sizeof(c->es_c));
+  if (c->energy && mech->surf_cv) {
+    if (!mech->surf_mass) return fail(c, LBM_EINVAL, "adsorbed-phase thermo needs surf_mass");
+    for (int k = 0; k < K; ++k) {
+      const double w = mech->a_s * mech->gamma * mech->surf_mass[k] / (c->rho_unit * c->c2);
+      if (!std::isfinite(w) || !std::isfinite(mech->surf_cv[k]) ||
+          (mech->surf_u_form && !std::isfinite(mech->surf_u_form[k])))
+        return fail(c, LBM_EINVAL, "adsorbed-phase thermo must be finite");
+      c->es_c[k] = w * mech->surf_cv[k];
+      c->es_u[k] = mech->surf_u_form ? w * mech->surf_u_form[k] : 0.0;
+    }
+    if (!c->rEs) {
+      const int rc2 = dalloc(c, &c->rEs, c->N);
+      if (rc2) return rc2;
+    }
+    c->esrc = 1;
+  }
   c->K = K;
   c->has_mech = 1;
   return LBM_OK;
@@ -1129,7 +1161,7 @@ void lbm_destroy(lbm_ctx *c) {
   else (void)hipDeviceSynchronize();
   if (c->timing) lbm_set_timing(c, 0);
   double *bufs[] = {c->pop[0], c->pop[1], c->phi, c->kfac, c->Tfield, c->X0, c->Plat, c->rA, c->rRT, c->rFk,
-                    c->rrho, c->rY, c->rqd, c->rec[0], c->rec[1], c->T[0], c->T[1], c->srcsum, c->theta, c->faradaic, c->macro, c->partials};
+                    c->rrho, c->rY, c->rqd, c->rec[0], c->rec[1], c->T[0], c->T[1], c->srcsum, c->theta, c->rEs, c->faradaic, c->macro, c->partials};
   for (double *b : bufs) dfree(b);
   dfree(c->colflag);
   dfree(c->chem_tab);

@@ -65,6 +65,12 @@ struct KParams {
   const double *T_prev;     // [N] temperature of the previous step (energy) or Tfield
   double *T_cur;            // energy only
   const double *srcsum_cur; // [N] sum_a source of this step (mixture mass source)
+  // adsorbed-phase internal energy (energy lattice with a mechanism that has
+  // surface thermo): E_s = sum_k theta_k (es_u[k] + es_c[k] T), lattice units
+  int K, esrc;
+  const double *theta;      // [K][N] coverages (after this step's chemistry in k_mixture)
+  double *rEs;              // [N] E_s before this step's chemistry
+  double es_u[LBM_KMAX], es_c[LBM_KMAX];
 };
 
 // Mechanism tables, kept in device memory (indexed by the run-time reaction).
@@ -123,6 +129,7 @@ hipError_t launch_init(int dim, const InitParams &ip, hipStream_t s);
 hipError_t launch_species(int dim, const KParams &p, hipStream_t s);
 hipError_t launch_mixture(int dim, const KParams &p, hipStream_t s);
 hipError_t launch_chem(const ChemParams &cp, hipStream_t s);
+hipError_t launch_surface_energy(const KParams &p, hipStream_t s);
 hipError_t launch_moments(int dim, const KParams &p, double *out, hipStream_t s);
 hipError_t launch_diag(int dim, int L, int Mmom, const KParams &p, const void *pop, double *partials,
                        int nblocks, hipStream_t s);

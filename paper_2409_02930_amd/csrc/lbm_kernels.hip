@@ -819,10 +819,26 @@ __global__ __launch_bounds__(256) void k_mixture(const KParams p) {
       Qv[a] = (omega - omega1) * (q[a] - qeq - corr) + omega1 * rho * qd +
               0.5 * (2.0 - omega1) * P * phi * (3.0 * four[a]) - 0.5 * (omega - omega1) * v[a] * G[a];
     }
+    // chemistry (eqs temperatureCell, InternalEnergyCell_PC, g0mom_source,
+    // g_source): the unified internal energy of fluid and adsorbed phase at
+    // this T is kept, phi rho^pc U^pc = phi rho U + E_s(before) - E_s(after);
+    // g^eq,source is g^eq with (rho^pc, U^pc) at the pre-collision v and RT
+    double phirho_pc = phirho, U_pc = U;
+    if (p.chem) {
+      phirho_pc = phirho + p.srcsum_cur[n];
+      double dEs = 0.0;
+      if (p.esrc) {
+        double es = 0.0;
+        for (int k = 0; k < p.K; ++k) es += p.theta[(size_t)k * N + n] * (p.es_u[k] + p.es_c[k] * T);
+        dEs = p.rEs[n] - es;
+      }
+      U_pc = (phirho * U + dEs) / phirho_pc;
+    }
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
       const double ge = geq_dir<D>(i, phirho, U, RT, v);
       double out = g[i] + omega * (ge - g[i]);
+      if (p.chem) out += geq_dir<D>(i, phirho_pc, U_pc, RT, v) - ge;   // eq g_source
       if (cnorm2<D>(i) == 1) {
         double cq = 0.0;
 #pragma unroll
@@ -1187,6 +1203,17 @@ __device__ __forceinline__ double block_sum(double v, double *sh) {
   return r;
 }
 
+// Internal energy of the adsorbed phase before this step's chemistry, at this
+// step's temperature (eq temperatureCell, adsorbed part).
+__global__ __launch_bounds__(256) void k_surface_energy(const KParams p) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= p.N) return;
+  const double T = p.T_cur[n];
+  double es = 0.0;
+  for (int k = 0; k < p.K; ++k) es += p.theta[(size_t)k * p.N + n] * (p.es_u[k] + p.es_c[k] * T);
+  p.rEs[n] = es;
+}
+
 // Totals of the stored state.  Species populations include the reaction
 // population the last step added after its collision (p.src_prev).
 template <int D, typename PT>
@@ -1380,6 +1407,11 @@ hipError_t launch_moments(int dim, const KParams &p, double *out, hipStream_t s)
 
 int chem_supported(int M, int K) {
   return (M == 2 && K == 2) || (M == 5 && K == 10) || (M == 3 && K == 4);
+}
+
+hipError_t launch_surface_energy(const KParams &p, hipStream_t s) {
+  hipLaunchKernelGGL(k_surface_energy, dim3((p.N + 255) / 256), dim3(256), 0, s, p);
+  return hipGetLastError();
 }
 
 hipError_t launch_chem(const ChemParams &cp, hipStream_t s) {

@@ -113,6 +113,15 @@ def test_d3q27_row_blocks_with_chemistry(lbm, shape):
     _run(lbm, w, 6)
 
 
+@pytest.mark.parametrize("kernel", ["specialized", "generic"])
+def test_d3q27_energy_with_chemistry(lbm, kernel):
+    """Energy lattice with the surface mechanism and adsorbed-phase thermo: the
+    chemistry's energy source (unified internal energy kept, g^eq,source)."""
+    w = synth.config3_energy(nx=10, ny=6, nz=4)
+    kind = lbm.CHEM_SPECIALIZED if kernel == "specialized" else lbm.CHEM_GENERIC
+    _run(lbm, w, 8, chem_kernel=kind)
+
+
 def test_specialized_chemistry_matches_generic_full_newton(lbm):
     """Specialised vs generic kernel on a stiffer mechanism setting (more
     sub-steps and Newton iterations), both through lbm_step: every field
