@@ -122,6 +122,25 @@ def test_d3q27_energy_with_chemistry(lbm, kernel):
     _run(lbm, w, 8, chem_kernel=kind)
 
 
+def _uniform_phi(w, phi):
+    return replace(w, phi=np.full(w.N, phi), tort=np.full(w.N, phi ** -0.5))
+
+
+DEGENERATE = {
+    "d2q9_single_node": lambda: synth.config1(nx=1, ny=1),
+    "d3q27_single_node_chemistry": lambda: _uniform_phi(synth.config3(nx=1, ny=1, nz=1), 0.45),
+    "d3q27_3x1x2_chemistry": lambda: _uniform_phi(synth.config3(nx=3, ny=1, nz=2), 0.4),
+    "d1q3_two_node_column": lambda: synth.config4_column(2, 0.4, 1.0),
+}
+
+
+@pytest.mark.parametrize("case", list(DEGENERATE))
+def test_degenerate_grids(lbm, case):
+    """One node (every direction streams back onto it), a grid thinner than the
+    stencil in y, a two-node column with an inlet and a wall at its ends."""
+    _run(lbm, DEGENERATE[case](), 5)
+
+
 def test_specialized_chemistry_matches_generic_full_newton(lbm):
     """Specialised vs generic kernel on a stiffer mechanism setting (more
     sub-steps and Newton iterations), both through lbm_step: every field
