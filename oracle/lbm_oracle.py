@@ -390,26 +390,33 @@ class Oracle:
 
         wrow = np.concatenate([np.repeat(phi[:, None], M, axis=1),
                                np.full((self.N, K), gam)], axis=1)                       # (N, S)
-        srow = np.concatenate([np.full(M, a_s), np.ones(K)])                              # a_s for gas rows
+        # volume factor of reaction r in the gas balances (eq totalFluidReactionRate):
+        # a_s for a surface reaction (rate per unit surface), phi for a homogeneous
+        # gas-phase reaction (rate per unit gas volume; eq dtrhoa balances phi rho_a)
+        hom = (np.zeros(mech.R, dtype=bool) if mech.homogeneous is None
+               else np.asarray(mech.homogeneous, dtype=bool))
+        vol = np.where(hom[None, :], phi[:, None], a_s)                                # (N, R)
+        gas_st = stoich[:, :M]                                                           # (R, M)
+        surf_st = stoich[:, M:]                                                          # (R, K)
         for _ in range(mech.n_sub):
             y0 = np.concatenate([c, th], axis=1)
             y = y0.copy()
             for _ in range(mech.n_newton):
                 C = conc(y[:, :M], y[:, M:])
                 q = rates(C)                                                             # (N, R)
-                prod = q @ stoich                                                        # (N, S)
-                F = wrow * (y - y0) - h * srow[None, :] * prod
+                prod = np.concatenate([(vol * q) @ gas_st, q @ surf_st], axis=1)         # (N, S)
+                F = wrow * (y - y0) - h * prod
                 dq = drates(C) * scale[None, None, :]                                    # d q / d y
                 J = np.zeros((self.N, S, S))
                 idx = np.arange(S)
                 J[:, idx, idx] = wrow
-                J -= h * srow[None, :, None] * np.einsum("rs,nrt->nst", stoich, dq)
+                J[:, :M, :] -= h * np.einsum("rs,nr,nrt->nst", gas_st, vol, dq)
+                J[:, M:, :] -= h * np.einsum("rs,nrt->nst", surf_st, dq)
                 y = y + np.linalg.solve(J, -F[:, :, None])[:, :, 0]
             C = conc(y[:, :M], y[:, M:])
-            dxi = h * rates(C)                                                           # extents, mol/m^2
-            dn = dxi @ stoich                                                            # (N, S)
-            th = th + dn[:, M:] / gam
-            dgas = a_s * dn[:, :M]                                                       # mol / m^3 total
+            dxi = h * rates(C)                                                           # extents
+            th = th + (dxi @ surf_st) / gam
+            dgas = (vol * dxi) @ gas_st                                                  # mol / m^3 total
             c = c + dgas / phi[:, None]
             src += dgas * self.m[None, :] / self.rho_unit
         if self.w.faradaic_rate is not None:

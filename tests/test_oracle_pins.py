@@ -477,3 +477,36 @@ def test_unified_internal_energy_kept_through_chemistry():
     dg = o.g.sum() - g0
     assert abs(des) > 1e-6 * abs(g0)                       # the adsorbed phase really took energy
     assert abs(dg + des) <= 1e-9 * abs(des), (dg, des)
+
+
+def test_homogeneous_reaction_reaches_mass_action_equilibrium():
+    """Homogeneous 2A <=> B (eqs sumRhoDot, totalFluidReactionRate): the
+    implicit chemistry's fixed point is the mass-action equilibrium
+    c_B / c_A^2 = kf / kb, and the mixture mass is unchanged (m_B = 2 m_A)."""
+    w = synth.homogeneous_dimerisation()
+    o = lo.Oracle(w)
+    rho0 = o.macro()["rho_a"].sum(axis=0)
+    o.step(1000)
+    mac = o.macro()
+    cA = mac["rho_a"][0] * o.rho_unit / o.m[0]
+    cB = mac["rho_a"][1] * o.rho_unit / o.m[1]
+    ratio = w.mech.A_f[0] / w.mech.A_b[0]
+    assert np.allclose(cB / cA ** 2, ratio, rtol=1e-10, atol=0.0)
+    assert np.allclose(mac["rho_a"].sum(axis=0), rho0, rtol=1e-12, atol=0.0)
+
+
+def test_homogeneous_reaction_rate_is_per_gas_volume():
+    """One step with slow kinetics: dc_A = -2 (kf c_A^2 - kb c_B) dt, the gas
+    concentration changes at the mass-action rate itself (eq 185: phi rho_a
+    balances a source per unit total volume (eq dtrhoa) = phi times the per-gas-volume
+    rate), independent of the porosity and of the surface area a_s."""
+    for phi in (0.3, 0.8):
+        w = synth.homogeneous_dimerisation(phi=phi, kf=2.0e2, kb=5.0e3)
+        o = lo.Oracle(w)
+        mac = o.macro()
+        cA = mac["rho_a"][0] * o.rho_unit / o.m[0]
+        cB = mac["rho_a"][1] * o.rho_unit / o.m[1]
+        expect = -2.0 * (w.mech.A_f[0] * cA ** 2 - w.mech.A_b[0] * cB) * o.dt
+        o.step(1)
+        cA1 = o.macro()["rho_a"][0] * o.rho_unit / o.m[0]
+        assert np.allclose(cA1 - cA, expect, rtol=1e-5, atol=0.0), (cA1 - cA, expect)
