@@ -121,6 +121,11 @@ typedef struct {
                               InternalEnergyCell_PC) and the energy collision takes
                               g^eq,source - g^eq (eqs g0mom_source, g_source); surf_cv NULL
                               means no adsorbed-phase energy (surf_mass required otherwise) */
+  const int32_t *homogeneous;/* [R] or NULL (all surface): 1 marks a homogeneous gas-phase
+                              reaction (eqs sumRhoDot, totalFluidReactionRate): gas species
+                              only, zero net mass; its mass-action rate is per unit gas
+                              volume (mol m^-3 s^-1 with C the gas concentrations), so it
+                              enters the gas balances with phi instead of a_s            */
 } lbm_mechanism;
 
 /* Creates a context for a rectangular grid.  X0 [M][N] mole fractions, P0 [N]

@@ -166,17 +166,21 @@ struct Gen {
       o("      {  // reaction %d", r);
       o("        const double kf = sk[%d][lane], kb = sk[%d][lane];", 2 * r, 2 * r + 1);
       o("        (void)kf; (void)kb;");
-      o("        const double q = %s;", rate(r).c_str());
+      if (sp.hom[r])   // homogeneous: gas rows weighted by phi, not a_s
+        o("        const double q = hom_w * (%s);", rate(r).c_str());
+      else
+        o("        const double q = %s;", rate(r).c_str());
       for (int s = 0; s < S; ++s)
         if (st[r][s]) o("        P[%d]%s;", s, times(st[r][s], "q").c_str());
       for (int t = 0; t < S; ++t) {
         if (!in[r][t]) continue;
         const std::string d = drate(r, t);
         if (d.empty()) continue;
+        const char *hw = sp.hom[r] ? "hom_w * " : "";
         if (t < M)
-          o("        { const double d = %s;", d.c_str());
+          o("        { const double d = %s(%s);", hw, d.c_str());
         else
-          o("        { const double d = gam * (%s);", d.c_str());
+          o("        { const double d = %sgam * (%s);", hw, d.c_str());
         for (int s = 0; s < S; ++s)
           if (st[r][s]) o("          J[%d][%d]%s;", s, t, times(st[r][s], "d").c_str());
         o("        }");
@@ -331,6 +335,8 @@ struct Gen {
     for (int k = 0; k < K; ++k) o("  y0(%d) = theta[(size_t)%d * N + n];", M + k, k);
     o("  const double h = dt / %d.0;", sp.n_sub);
     o("  const double cg = h * a_s / phi, cs = h / gam;");
+    o("  const double hom_w = phi / a_s;   // homogeneous reactions: phi q instead of a_s q");
+    o("  (void)hom_w;");
     o("#pragma unroll 1");
     o("  for (int sub = 0; sub < %d; ++sub) {", sp.n_sub);
     o("    double y[%d];", S);
@@ -356,7 +362,7 @@ struct Gen {
       o("    {");
       o("      const double kf = sk[%d][lane], kb = sk[%d][lane];", 2 * r, 2 * r + 1);
       o("      (void)kf; (void)kb;");
-      o("      const double dxi = h * (%s);", rate(r).c_str());
+      o("      const double dxi = %sh * (%s);", sp.hom[r] ? "hom_w * " : "", rate(r).c_str());
       for (int s = 0; s < S; ++s)
         if (st[r][s]) o("      dn[%d]%s;", s, times(st[r][s], "dxi").c_str());
       o("    }");
@@ -425,7 +431,7 @@ void chem_choose_order(ChemSpec &sp, int ns, const double *T, const double *phi,
         for (int s = 0; s < S; ++s) {
           const int st = sp.nu_b[r][s] - sp.nu_f[r][s];
           if (!st) continue;
-          const double coef = s < M ? h * a_s / phi[j] : h / gam;
+          const double coef = s < M ? (sp.hom[r] ? h : h * a_s / phi[j]) : h / gam;
           A[s * S + t] -= coef * st * d;
           pat[s][t] = true;
         }

@@ -415,6 +415,7 @@ int specialize_chemistry(lbm_ctx *c) {
     sp.Ea_f[r] = c->chem_host.Ea_f[r];
     sp.A_b[r] = c->chem_host.A_b[r];
     sp.Ea_b[r] = c->chem_host.Ea_b[r];
+    sp.hom[r] = c->chem_host.hom[r];
   }
   for (int a = 0; a < M; ++a) sp.m[a] = c->m[a];
   sp.R_U = kRU;
@@ -676,6 +677,21 @@ int lbm_set_mechanism(lbm_ctx *c, const lbm_mechanism *mech) {
       }
     }
     if (site_f != site_b) return fail(c, LBM_EINVAL, "reaction %d is not site-balanced", r);
+    const int hom = mech->homogeneous ? mech->homogeneous[r] : 0;
+    if (hom != 0 && hom != 1) return fail(c, LBM_EINVAL, "homogeneous flags must be 0 or 1");
+    if (hom) {                        // gas species only, zero net mass (eq sumRhoDot)
+      double dm = 0.0, mm = 0.0;
+      for (int s = 0; s < S; ++s) {
+        const int ef = mech->nu_f[r * S + s], eb = mech->nu_b[r * S + s];
+        if (s >= M && (ef || eb)) return fail(c, LBM_EINVAL, "homogeneous reaction %d has surface species", r);
+        if (s < M) {
+          dm += (eb - ef) * c->m[s];
+          mm += (eb + ef) * c->m[s];
+        }
+      }
+      if (fabs(dm) > 1e-12 * mm) return fail(c, LBM_EINVAL, "homogeneous reaction %d changes the mass", r);
+    }
+    tab.hom[r] = (int8_t)hom;
     if (!std::isfinite(mech->A_f[r]) || !std::isfinite(mech->A_b[r]) || !std::isfinite(mech->Ea_f[r]) ||
         !std::isfinite(mech->Ea_b[r]) || mech->A_f[r] < 0 || mech->A_b[r] < 0)
       return fail(c, LBM_EINVAL, "reaction %d: pre-factors must be finite and >= 0, energies finite", r);

@@ -78,6 +78,7 @@ struct ChemTables {
   double A_f[LBM_RMAX], Ea_f[LBM_RMAX], A_b[LBM_RMAX], Ea_b[LBM_RMAX];
   alignas(16) int8_t nu_f[LBM_RMAX][16];
   alignas(16) int8_t nu_b[LBM_RMAX][16];
+  int8_t hom[LBM_RMAX];          // 1: homogeneous gas-phase reaction (weight phi, not a_s)
 };
 
 struct ChemParams {
@@ -122,6 +123,7 @@ struct ChemSpec {
   double m[LBM_MMAX];                            // gas molar masses, kg/mol
   double R_U;
   int perm[16];                                  // elimination order of the S = M + K unknowns
+  int hom[LBM_RMAX];                             // homogeneous gas-phase reactions
 };
 
 // launchers (lbm_kernels.hip)

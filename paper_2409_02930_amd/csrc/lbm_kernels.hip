@@ -1054,14 +1054,17 @@ void k_chem(const ChemParams cp) {
       const double hg = h * cp.a_s / phi, hs = h / gam;   // h s / W for gas and surface rows
       for (int r = 0; r < cp.R; ++r) {
         const NuRow NF = load_nu(tb->nu_f[r]), NB = load_nu(tb->nu_b[r]);
+        // a homogeneous reaction's gas rows take phi q (per total volume) where a
+        // surface reaction's take a_s q: scale by phi / a_s, gas rows only exist for it
+        const double wq = tb->hom[r] ? phi / cp.a_s : 1.0;
         double dq[S];
-        const double q = mass_action<S>(NF, NB, s_k[2 * r][lane], s_k[2 * r + 1][lane], C, dq);
+        const double q = wq * mass_action<S>(NF, NB, s_k[2 * r][lane], s_k[2 * r + 1][lane], C, dq);
         // chain rule to the unknowns: dC_a/dy_a = 1, dC_s/dtheta_s = gamma, dC_V/dtheta_s = -gamma
         double dqu[U];
 #pragma unroll
-        for (int a = 0; a < M; ++a) dqu[a] = dq[a];
+        for (int a = 0; a < M; ++a) dqu[a] = wq * dq[a];
 #pragma unroll
-        for (int k = 1; k < K; ++k) dqu[M + k - 1] = gam * (dq[M + k] - dq[M]);
+        for (int k = 1; k < K; ++k) dqu[M + k - 1] = wq * gam * (dq[M + k] - dq[M]);
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           const int s = (u < M) ? u : u + 1;
@@ -1132,7 +1135,8 @@ void k_chem(const ChemParams cp) {
     for (int s = 0; s < S; ++s) dn[s] = 0.0;
     for (int r = 0; r < cp.R; ++r) {
       const NuRow NF = load_nu(tb->nu_f[r]), NB = load_nu(tb->nu_b[r]);
-      const double dxi = h * mass_action<S>(NF, NB, s_k[2 * r][lane], s_k[2 * r + 1][lane], C, nullptr);
+      const double wq = tb->hom[r] ? phi / cp.a_s : 1.0;
+      const double dxi = wq * h * mass_action<S>(NF, NB, s_k[2 * r][lane], s_k[2 * r + 1][lane], C, nullptr);
 #pragma unroll
       for (int s = 0; s < S; ++s) {
         const int st = nu_of(NB, s) - nu_of(NF, s);

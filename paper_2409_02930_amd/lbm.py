@@ -54,6 +54,7 @@ class lbm_mechanism(C.Structure):
         ("n_newton", C.c_int32), ("nu_f", _ip), ("nu_b", _ip), ("A_f", _dp), ("Ea_f", _dp),
         ("A_b", _dp), ("Ea_b", _dp), ("gamma", C.c_double), ("a_s", C.c_double),
         ("surf_mass", _dp), ("theta0", _dp), ("surf_cv", _dp), ("surf_u_form", _dp),
+        ("homogeneous", _ip),
     ]
 
 
@@ -193,7 +194,8 @@ class Lattice:
 
     def set_mechanism(self, mech):
         """mech: object with K, nu_f, nu_b, A_f, Ea_f, A_b, Ea_b, gamma, a_s, surf_mass, theta0,
-        n_sub, n_newton and optionally surf_cv, surf_u_form (None removes the mechanism)."""
+        n_sub, n_newton and optionally surf_cv, surf_u_form, homogeneous (None removes the
+        mechanism)."""
         if mech is None:
             self._check(_lib.lbm_set_mechanism(self.ctx, None))
             self.K = 0
@@ -202,13 +204,15 @@ class Lattice:
                     A_f=_arr(mech.A_f), Ea_f=_arr(mech.Ea_f), A_b=_arr(mech.A_b), Ea_b=_arr(mech.Ea_b),
                     surf_mass=_arr(mech.surf_mass), theta0=_arr(mech.theta0),
                     surf_cv=_arr(getattr(mech, "surf_cv", None)),
-                    surf_u_form=_arr(getattr(mech, "surf_u_form", None)))
+                    surf_u_form=_arr(getattr(mech, "surf_u_form", None)),
+                    homogeneous=_arr(getattr(mech, "homogeneous", None), np.int32))
         st = lbm_mechanism()
         st.n_surface = int(mech.K)
         st.n_reactions = int(np.asarray(mech.nu_f).shape[0])
         st.n_sub, st.n_newton = int(mech.n_sub), int(mech.n_newton)
         st.nu_f = _ptr(keep["nu_f"], C.c_int32)
         st.nu_b = _ptr(keep["nu_b"], C.c_int32)
+        st.homogeneous = _ptr(keep["homogeneous"], C.c_int32)
         for k in ("A_f", "Ea_f", "A_b", "Ea_b", "surf_mass", "theta0", "surf_cv", "surf_u_form"):
             setattr(st, k, _ptr(keep[k]))
         st.gamma, st.a_s = float(mech.gamma), float(mech.a_s)

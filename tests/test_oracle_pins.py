@@ -497,8 +497,8 @@ def test_homogeneous_reaction_reaches_mass_action_equilibrium():
 
 def test_homogeneous_reaction_rate_is_per_gas_volume():
     """One step with slow kinetics: dc_A = -2 (kf c_A^2 - kb c_B) dt, the gas
-    concentration changes at the mass-action rate itself (eq 185: phi rho_a
-    balances a source per unit total volume (eq dtrhoa) = phi times the per-gas-volume
+    concentration changes at the mass-action rate itself (eq dtrhoa: phi rho_a
+    balances a source per unit total volume = phi times the per-gas-volume
     rate), independent of the porosity and of the surface area a_s."""
     for phi in (0.3, 0.8):
         w = synth.homogeneous_dimerisation(phi=phi, kf=2.0e2, kb=5.0e3)

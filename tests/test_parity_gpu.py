@@ -141,6 +141,21 @@ def test_degenerate_grids(lbm, case):
     _run(lbm, DEGENERATE[case](), 5)
 
 
+HOMOGENEOUS = {
+    "d1q3_dimerisation": lambda: synth.homogeneous_dimerisation(nx=8),
+    "d2q9_dimerisation_and_adsorption": lambda: synth.homogeneous_dimerisation(nx=6, ny=4, with_surface=True),
+}
+
+
+@pytest.mark.parametrize("kernel", ["specialized", "generic"])
+@pytest.mark.parametrize("case", list(HOMOGENEOUS))
+def test_homogeneous_gas_reactions(lbm, case, kernel):
+    """Homogeneous gas-phase reaction 2A <=> B alone and next to a surface
+    reaction (eqs sumRhoDot, totalFluidReactionRate)."""
+    kind = lbm.CHEM_SPECIALIZED if kernel == "specialized" else lbm.CHEM_GENERIC
+    _run(lbm, HOMOGENEOUS[case](), 20, chem_kernel=kind)
+
+
 def test_specialized_chemistry_matches_generic_full_newton(lbm):
     """Specialised vs generic kernel on a stiffer mechanism setting (more
     sub-steps and Newton iterations), both through lbm_step: every field

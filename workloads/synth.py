@@ -299,22 +299,31 @@ def config3_energy(nx: int = 10, ny: int = 6, nz: int = 4, seed: int = 3) -> Wor
 
 
 def homogeneous_dimerisation(nx: int = 8, ny: int = 1, phi: float = 0.4, kf: float = 2.0e6,
-                             kb: float = 5.0e7, x_a: float = 0.9) -> Workload:
+                             kb: float = 5.0e7, x_a: float = 0.9, with_surface: bool = False) -> Workload:
     """Binary gas 2A <=> B (m_B = 2 m_A: zero net mass) as a homogeneous gas-phase
     reaction with temperature-independent rate constants (kf in m^3/(mol s), kb in
     1/s), uniform state, isothermal 1073 K, D1Q3 (ny = 1) or D2Q9, periodic.  The
     mechanism carries an inert two-species surface (vacancy only) because the
-    chemistry solve always has coverages."""
+    chemistry solve always has coverages.  with_surface adds the surface reaction
+    A + V <=> A(s) next to the homogeneous one."""
     m = np.array([14.0, 28.0])
     lattice = 1 if ny == 1 else 2
     N = nx * ny
     X0 = np.stack([_uniform(N, x_a), _uniform(N, 1.0 - x_a)])
-    nu_f = np.array([[2, 0, 0, 0]], dtype=np.int32)
-    nu_b = np.array([[0, 1, 0, 0]], dtype=np.int32)
-    mech = Mechanism(K=2, nu_f=nu_f, nu_b=nu_b, A_f=np.array([kf]), Ea_f=np.zeros(1),
-                     A_b=np.array([kb]), Ea_b=np.zeros(1), gamma=2.6e-5, a_s=1.0e7,
-                     surf_mass=np.array([0.0, 0.014]), theta0=np.array([1.0, 0.0]), n_sub=1, n_newton=3,
-                     homogeneous=np.array([1], dtype=np.int32))
+    nu_f = [[2, 0, 0, 0]]
+    nu_b = [[0, 1, 0, 0]]
+    A_f, A_b, hom = [kf], [kb], [1]
+    if with_surface:                      # A + V <=> A(s), mol/(m^2 s) per (mol/m^3) (mol/m^2)
+        nu_f.append([1, 0, 1, 0])
+        nu_b.append([0, 0, 0, 1])
+        A_f.append(2.0e4)
+        A_b.append(1.0e5)
+        hom.append(0)
+    R = len(A_f)
+    mech = Mechanism(K=2, nu_f=np.array(nu_f, dtype=np.int32), nu_b=np.array(nu_b, dtype=np.int32),
+                     A_f=np.array(A_f), Ea_f=np.zeros(R), A_b=np.array(A_b), Ea_b=np.zeros(R),
+                     gamma=2.6e-5, a_s=1.0e7, surf_mass=np.array([0.0, 0.014]), theta0=np.array([1.0, 0.0]),
+                     n_sub=1, n_newton=3, homogeneous=np.array(hom, dtype=np.int32))
     return Workload(name="homogeneous_dimerisation", lattice=lattice, nx=nx, ny=ny, nz=1,
                     molar_mass=m * 1e-3, D_ref_lat=synthetic_D_ref(m), X0=X0,
                     P0=_uniform(N, P_ATM), T0=_uniform(N, 1073.0), phi=_uniform(N, phi),
