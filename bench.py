@@ -97,6 +97,8 @@ def make_workload(name):
         return synth.config3()
     if name == "c3_nochem":
         return synth.config3(with_mech=False)
+    if name == "c3_energy":       # C3 with the energy lattice and adsorbed-phase thermo
+        return synth.config3_energy(nx=256, ny=128, nz=128)
     if name == "c2":
         return synth.config2(kn_index=3)
     if name == "c5":
