@@ -359,16 +359,18 @@ class Oracle:
         nu_f = mech.nu_f.astype(np.float64)
         nu_b = mech.nu_b.astype(np.float64)
         stoich = (mech.nu_b - mech.nu_f).astype(np.float64)                            # (R, S)
-        gam, a_s = mech.gamma, mech.a_s
+        gam_k, a_k = self.surface_weights()                                              # (K,) per species
+        ph = (np.zeros(K, dtype=int) if mech.surface_phase is None
+              else np.asarray(mech.surface_phase, dtype=int))
         phi = self.phi
         h = self.dt / mech.n_sub
         c = (mac["rho_a"] * self.rho_unit / self.m[:, None]).T.copy()                    # (N, M) mol/m^3
         th = self.theta.T.copy()                                                         # (N, K)
         src = np.zeros((self.N, M))
-        scale = np.concatenate([np.ones(M), np.full(K, gam)])                           # dC/dy
+        scale = np.concatenate([np.ones(M), gam_k])                                     # dC/dy
 
         def conc(cg, ts):
-            return np.concatenate([cg, gam * ts], axis=1)                                # (N, S)
+            return np.concatenate([cg, gam_k[None, :] * ts], axis=1)                     # (N, S)
 
         def rates(C):
             fwd = kf.T * np.prod(C[:, None, :] ** nu_f[None], axis=2)
@@ -389,15 +391,23 @@ class Oracle:
             return dq
 
         wrow = np.concatenate([np.repeat(phi[:, None], M, axis=1),
-                               np.full((self.N, K), gam)], axis=1)                       # (N, S)
+                               np.repeat(gam_k[None, :], self.N, axis=0)], axis=1)       # (N, S)
         # volume factor of reaction r in the gas balances (eq totalFluidReactionRate):
         # a_s for a surface reaction (rate per unit surface), phi for a homogeneous
         # gas-phase reaction (rate per unit gas volume; eq dtrhoa balances phi rho_a)
         hom = (np.zeros(mech.R, dtype=bool) if mech.homogeneous is None
                else np.asarray(mech.homogeneous, dtype=bool))
-        vol = np.where(hom[None, :], phi[:, None], a_s)                                # (N, R)
+        edge = (np.zeros(mech.R, dtype=bool) if mech.edge is None
+                else np.asarray(mech.edge, dtype=bool))
+        # phase of a surface reaction: the phase of its surface species (one phase each)
+        sp_in = (mech.nu_f[:, M:] != 0) | (mech.nu_b[:, M:] != 0)                       # (R, K)
+        r_phase = np.array([ph[sp_in[r]][0] if sp_in[r].any() else 0 for r in range(mech.R)])
+        a_r = np.where(r_phase == 0, mech.a_s, mech.a_s2)
+        vol = np.where(hom[None, :], phi[:, None], a_r[None, :])                        # (N, R)
         gas_st = stoich[:, :M]                                                           # (R, M)
-        surf_st = stoich[:, M:]                                                          # (R, K)
+        # eq totalSurfaceReactionRate: a coverage takes its surface's reactions per unit
+        # area and the edge reactions scaled by l_TPB / a^(s) of its own surface
+        surf_st = stoich[:, M:] * np.where(edge[:, None], mech.l_tpb / a_k[None, :], 1.0)   # (R, K)
         for _ in range(mech.n_sub):
             y0 = np.concatenate([c, th], axis=1)
             y = y0.copy()
@@ -415,7 +425,7 @@ class Oracle:
                 y = y + np.linalg.solve(J, -F[:, :, None])[:, :, 0]
             C = conc(y[:, :M], y[:, M:])
             dxi = h * rates(C)                                                           # extents
-            th = th + (dxi @ surf_st) / gam
+            th = th + (dxi @ surf_st) / gam_k[None, :]
             dgas = (vol * dxi) @ gas_st                                                  # mol / m^3 total
             c = c + dgas / phi[:, None]
             src += dgas * self.m[None, :] / self.rho_unit
@@ -437,8 +447,18 @@ class Oracle:
         m_k = np.asarray(mech.surf_mass, dtype=np.float64)
         Uk = (np.asarray(mech.surf_u_form, dtype=np.float64)[:, None]
               + np.asarray(mech.surf_cv, dtype=np.float64)[:, None] * np.asarray(T)[None, :])   # J/kg
-        dens = mech.a_s * mech.gamma * m_k[:, None] * theta                                    # kg/m^3
+        gam_k, a_k = self.surface_weights()
+        dens = (a_k * gam_k * m_k)[:, None] * theta                                            # kg/m^3
         return (dens * Uk).sum(axis=0) / (self.rho_unit * self.c2)
+
+    def surface_weights(self):
+        """Site density Gamma and specific area a^(s) of each surface species' phase."""
+        mech = self.mech
+        ph = (np.zeros(mech.K, dtype=int) if mech.surface_phase is None
+              else np.asarray(mech.surface_phase, dtype=int))
+        gam_k = np.where(ph == 0, mech.gamma, mech.gamma2)
+        a_k = np.where(ph == 0, mech.a_s, mech.a_s2)
+        return gam_k, a_k
 
     # ----- one time step ---------------------------------------------------
     def step(self, n: int = 1):

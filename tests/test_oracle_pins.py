@@ -510,3 +510,55 @@ def test_homogeneous_reaction_rate_is_per_gas_volume():
         o.step(1)
         cA1 = o.macro()["rho_a"][0] * o.rho_unit / o.m[0]
         assert np.allclose(cA1 - cA, expect, rtol=1e-5, atol=0.0), (cA1 - cA, expect)
+
+
+def test_two_phase_edge_reaction_equilibrium_and_balances():
+    """Two surface phases joined by a TPB edge reaction A1 + V2 <=> A2 + V1 (eqs
+    totalSurfaceReactionRate, totalSurfaceReactionRateTPB_electrode/_electrolyte):
+    the implicit update's fixed point is the mass-action equilibrium
+    theta_A2 theta_V1 / (theta_A1 theta_V2) = kf / kb, each phase keeps its sites,
+    and the adsorbate moles per volume a1 G1 theta_A1 + a2 G2 theta_A2 are kept."""
+    w = synth.two_phase_tpb(nx=3, ny=3, with_gas=False)
+    o = lo.Oracle(w)
+    m = w.mech
+    held0 = m.a_s * m.gamma * o.theta[1] + m.a_s2 * m.gamma2 * o.theta[3]
+    o.step(400)
+    th = o.theta
+    assert np.allclose(th[0] + th[1], 1.0, rtol=0, atol=1e-13)
+    assert np.allclose(th[2] + th[3], 1.0, rtol=0, atol=1e-13)
+    assert np.allclose(m.a_s * m.gamma * th[1] + m.a_s2 * m.gamma2 * th[3], held0, rtol=1e-12, atol=0)
+    assert np.allclose(th[3] * th[0] / (th[1] * th[2]), m.A_f[0] / m.A_b[0], rtol=1e-9, atol=0)
+
+
+def test_two_phase_edge_rate_scaled_by_tpb_length_over_area():
+    """One step with slow kinetics: each phase's coverage changes at the edge rate
+    times l_TPB / (a^(s) Gamma) of its own surface (eq totalSurfaceReactionRate)."""
+    w = synth.two_phase_tpb(nx=2, ny=2, with_gas=False, kf=3.0e1, kb=1.0e1)
+    o = lo.Oracle(w)
+    m = w.mech
+    th = o.theta
+    C = np.array([m.gamma * th[0], m.gamma * th[1], m.gamma2 * th[2], m.gamma2 * th[3]])
+    q = m.A_f[0] * C[1] * C[2] - m.A_b[0] * C[3] * C[0]                  # per unit edge length
+    o.step(1)
+    d1 = o.theta[1] - th[1]
+    d2 = o.theta[3] - th[3]
+    assert np.allclose(d1, -m.l_tpb / (m.a_s * m.gamma) * q * o.dt, rtol=1e-5, atol=0)
+    assert np.allclose(d2, m.l_tpb / (m.a_s2 * m.gamma2) * q * o.dt, rtol=1e-5, atol=0)
+
+
+def test_two_phase_chemistry_conserves_sites_and_mass():
+    """With gas adsorption on phase 1, the edge transfer and desorption from phase 2:
+    sites per phase and gas + both adsorbed phases' mass are conserved per node."""
+    w = synth.two_phase_tpb(nx=3, ny=2, with_gas=True)
+    o = lo.Oracle(w)
+    mac = o.macro()
+    src, th = o.chemistry(mac)
+    m = w.mech
+    assert np.all(np.abs(th[0] + th[1] - 1.0) < 1e-13) and np.all(np.abs(th[2] + th[3] - 1.0) < 1e-13)
+    gas = (src * o.rho_unit).sum(0)
+    a_k = np.array([m.a_s, m.a_s, m.a_s2, m.a_s2])
+    g_k = np.array([m.gamma, m.gamma, m.gamma2, m.gamma2])
+    surf = ((a_k * g_k * m.surf_mass)[:, None] * (th - o.theta)).sum(0)
+    scale = (o.phi * mac["rho_a"].sum(0)) * o.rho_unit
+    assert np.all(np.abs(gas + surf) / scale < 1e-13)
+    assert np.any(np.abs(gas) / scale > 1e-8)

@@ -58,6 +58,15 @@ class Mechanism:
     # (R,) 1 for a homogeneous gas-phase reaction (gas species only, zero net mass,
     # q per unit gas volume), 0 for a surface reaction; None: all surface
     homogeneous: Optional[np.ndarray] = None
+    # second surface phase (e.g. electrolyte next to electrode): surface_phase (K,) 0/1 assigns
+    # each surface species (each phase has its own vacancy); gamma2, a_s2 are that phase's site
+    # density and specific area; edge (R,) marks triple-phase-boundary reactions among adsorbed
+    # species of both phases, rate per unit edge length, l_tpb edge length per unit volume (1/m^2)
+    surface_phase: Optional[np.ndarray] = None
+    gamma2: float = 0.0
+    a_s2: float = 0.0
+    edge: Optional[np.ndarray] = None
+    l_tpb: float = 0.0
 
     @property
     def R(self) -> int:
@@ -328,6 +337,42 @@ def homogeneous_dimerisation(nx: int = 8, ny: int = 1, phi: float = 0.4, kf: flo
                     molar_mass=m * 1e-3, D_ref_lat=synthetic_D_ref(m), X0=X0,
                     P0=_uniform(N, P_ATM), T0=_uniform(N, 1073.0), phi=_uniform(N, phi),
                     tort=_uniform(N, phi ** -0.5), pore_radius=1e-6, steps=100, T_ref=1073.0, mech=mech)
+
+
+def two_phase_tpb(nx: int = 6, ny: int = 4, phi: float = 0.4, theta_a1: float = 0.5,
+                  with_gas: bool = True, kf: float = 3.0e7, kb: float = 1.0e7) -> Workload:
+    """Two surface phases with a triple-phase-boundary edge reaction, 3 inert-ish gas
+    species (2, 18, 28 g/mol), isothermal 1073 K, D2Q9 periodic, uniform state.
+    Surface species: V1, A1 (phase 1: Gamma 2.6e-5, a_s 1e7), V2, A2 (phase 2:
+    Gamma 1.3e-5, a_s 5e6); edge reaction A1 + V2 <=> A2 + V1 (kf, kb in
+    m^2 mol^-1 s^-1 per unit edge length, l_tpb 2e12 m^-2).  with_gas adds the
+    adsorption G1 + V1 <=> A1 on phase 1 and the desorption A2 <=> G1 + V2 on
+    phase 2 (A carries the mass of G1, 18 g/mol)."""
+    m = np.array([2.0, 18.0, 28.0])
+    N = nx * ny
+    X0 = np.stack([_uniform(N, 0.3), _uniform(N, 0.3), _uniform(N, 0.4)])
+    M = 3
+    # columns: G0 G1 G2 | V1 A1 V2 A2
+    nu_f = [[0, 0, 0, 0, 1, 1, 0]]
+    nu_b = [[0, 0, 0, 1, 0, 0, 1]]
+    A_f, A_b, edge = [kf], [kb], [1]
+    if with_gas:
+        nu_f += [[0, 1, 0, 1, 0, 0, 0], [0, 0, 0, 0, 0, 0, 1]]
+        nu_b += [[0, 0, 0, 0, 1, 0, 0], [0, 1, 0, 0, 0, 1, 0]]
+        A_f += [2.0e4, 3.0e6]
+        A_b += [1.0e5, 4.0e4]
+        edge += [0, 0]
+    R = len(A_f)
+    mech = Mechanism(K=4, nu_f=np.array(nu_f, dtype=np.int32), nu_b=np.array(nu_b, dtype=np.int32),
+                     A_f=np.array(A_f), Ea_f=np.zeros(R), A_b=np.array(A_b), Ea_b=np.zeros(R),
+                     gamma=2.6e-5, a_s=1.0e7, surf_mass=np.array([0.0, 0.018, 0.0, 0.018]),
+                     theta0=np.array([1.0 - theta_a1, theta_a1, 1.0, 0.0]), n_sub=1, n_newton=3,
+                     surface_phase=np.array([0, 0, 1, 1], dtype=np.int32), gamma2=1.3e-5, a_s2=5.0e6,
+                     edge=np.array(edge, dtype=np.int32), l_tpb=2.0e12)
+    return Workload(name="two_phase_tpb", lattice=2, nx=nx, ny=ny, nz=1, molar_mass=m * 1e-3,
+                    D_ref_lat=synthetic_D_ref(m), X0=X0, P0=_uniform(N, P_ATM), T0=_uniform(N, 1073.0),
+                    phi=_uniform(N, phi), tort=_uniform(N, phi ** -0.5), pore_radius=1e-6, steps=100,
+                    T_ref=1073.0, mech=mech)
 
 
 def config4_columns(seed: int = 4, n_cols: int = 64, lmin: int = 200, lmax: int = 2000):
