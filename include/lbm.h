@@ -126,6 +126,19 @@ typedef struct {
                               only, zero net mass; its mass-action rate is per unit gas
                               volume (mol m^-3 s^-1 with C the gas concentrations), so it
                               enters the gas balances with phi instead of a_s            */
+  /* Second surface phase and triple-phase-boundary (TPB) edge (eqs totalSurfaceReactionRate,
+   * totalSurfaceReactionRateTPB_electrode/_electrolyte).  surface_phase [K] (NULL: all 0)
+   * assigns each surface species to phase 0 (gamma, a_s) or phase 1 (gamma2, a_s2); each
+   * phase has its own vacancy and theta0 sums to 1 per phase.  A surface reaction's surface
+   * species lie on one phase and balance its sites.  edge [R] (NULL: none) marks TPB
+   * reactions among adsorbed species of both phases (no gas species, sites balanced per
+   * phase) with a mass-action rate per unit edge length; l_tpb is the edge length per unit
+   * volume (1/m^2), so a coverage of phase k takes l_tpb / a^(s)_k times the edge rate. */
+  const int32_t *surface_phase;
+  double gamma2;           /* site density of phase 1, mol/m^2                             */
+  double a_s2;             /* specific surface area of phase 1, 1/m                        */
+  const int32_t *edge;
+  double l_tpb;            /* TPB length per unit volume, 1/m^2                            */
 } lbm_mechanism;
 
 /* Creates a context for a rectangular grid.  X0 [M][N] mole fractions, P0 [N]

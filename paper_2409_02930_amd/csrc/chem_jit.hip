@@ -142,6 +142,25 @@ struct Gen {
     return "(" + f + ") - (" + b + ")";
   }
 
+  // Weight of reaction r in the balance of species s, relative to the row
+  // coefficient (h / phi for gas rows, h / Gamma_s for coverage rows):
+  // gas rows take a^(s) of the reaction's surface (phi for a homogeneous
+  // reaction), coverage rows 1 (l_TPB / a^(s)_s for a TPB edge reaction).
+  std::string weight(int r, int s) const {
+    if (s < M) return sp.kind[r] == 1 ? std::string("phi") : lit(sp.w_r[r]);
+    if (sp.kind[r] == 2) return lit(sp.l_tpb / sp.a_k[s - M]);
+    return "";
+  }
+
+  // "x" scaled by c * weight(r, s) as an accumulation statement tail.
+  std::string acc(int r, int s, int c, const std::string &x) const {
+    std::string w = weight(r, s);
+    std::string e = w.empty() ? x : w + " * " + x;
+    if (c == 1) return " += " + e;
+    if (c == -1) return " -= " + e;
+    return " += " + std::to_string(c) + ".0 * " + e;
+  }
+
   static std::string times(int c, const char *x) {
     if (c == 1) return std::string(" += ") + x;
     if (c == -1) return std::string(" -= ") + x;
@@ -150,7 +169,7 @@ struct Gen {
 
   void concentrations(Out &o) const {
     for (int a = 0; a < M; ++a) o("      C[%d] = y[%d];", a, a);
-    for (int s = M; s < S; ++s) o("      C[%d] = gam * y[%d];", s, s);
+    for (int s = M; s < S; ++s) o("      C[%d] = %s * y[%d];", s, lit(sp.gam_k[s - M]).c_str(), s);
   }
 
   // J <- I - coef_s G, b <- -(y - y0) + coef_s P at the iterate y.
@@ -166,29 +185,26 @@ struct Gen {
       o("      {  // reaction %d", r);
       o("        const double kf = sk[%d][lane], kb = sk[%d][lane];", 2 * r, 2 * r + 1);
       o("        (void)kf; (void)kb;");
-      if (sp.hom[r])   // homogeneous: gas rows weighted by phi, not a_s
-        o("        const double q = hom_w * (%s);", rate(r).c_str());
-      else
-        o("        const double q = %s;", rate(r).c_str());
+      o("        const double q = %s;", rate(r).c_str());
       for (int s = 0; s < S; ++s)
-        if (st[r][s]) o("        P[%d]%s;", s, times(st[r][s], "q").c_str());
+        if (st[r][s]) o("        P[%d]%s;", s, acc(r, s, st[r][s], "q").c_str());
       for (int t = 0; t < S; ++t) {
         if (!in[r][t]) continue;
         const std::string d = drate(r, t);
         if (d.empty()) continue;
-        const char *hw = sp.hom[r] ? "hom_w * " : "";
         if (t < M)
-          o("        { const double d = %s(%s);", hw, d.c_str());
+          o("        { const double d = %s;", d.c_str());
         else
-          o("        { const double d = %sgam * (%s);", hw, d.c_str());
+          o("        { const double d = %s * (%s);", lit(sp.gam_k[t - M]).c_str(), d.c_str());
         for (int s = 0; s < S; ++s)
-          if (st[r][s]) o("          J[%d][%d]%s;", s, t, times(st[r][s], "d").c_str());
+          if (st[r][s]) o("          J[%d][%d]%s;", s, t, acc(r, s, st[r][s], "d").c_str());
         o("        }");
       }
       o("      }");
     }
     for (int s = 0; s < S; ++s) {
-      const char *cf = s < M ? "cg" : "cs";
+      const std::string cfs = s < M ? std::string("cg") : "cs" + std::to_string(s);
+      const char *cf = cfs.c_str();
       for (int t = 0; t < S; ++t) {
         if (!pat[s][t]) continue;
         if (s == t)
@@ -334,9 +350,9 @@ struct Gen {
     }
     for (int k = 0; k < K; ++k) o("  y0(%d) = theta[(size_t)%d * N + n];", M + k, k);
     o("  const double h = dt / %d.0;", sp.n_sub);
-    o("  const double cg = h * a_s / phi, cs = h / gam;");
-    o("  const double hom_w = phi / a_s;   // homogeneous reactions: phi q instead of a_s q");
-    o("  (void)hom_w;");
+    o("  const double cg = h / phi;   // gas rows (phi c); coverage rows (Gamma theta):");
+    for (int s = M; s < S; ++s) o("  const double cs%d = h / %s;", s, lit(sp.gam_k[s - M]).c_str());
+    o("  (void)gam; (void)a_s;");
     o("#pragma unroll 1");
     o("  for (int sub = 0; sub < %d; ++sub) {", sp.n_sub);
     o("    double y[%d];", S);
@@ -362,14 +378,14 @@ struct Gen {
       o("    {");
       o("      const double kf = sk[%d][lane], kb = sk[%d][lane];", 2 * r, 2 * r + 1);
       o("      (void)kf; (void)kb;");
-      o("      const double dxi = %sh * (%s);", sp.hom[r] ? "hom_w * " : "", rate(r).c_str());
+      o("      const double dxi = h * (%s);", rate(r).c_str());
       for (int s = 0; s < S; ++s)
-        if (st[r][s]) o("      dn[%d]%s;", s, times(st[r][s], "dxi").c_str());
+        if (st[r][s]) o("      dn[%d]%s;", s, acc(r, s, st[r][s], "dxi").c_str());
       o("    }");
     }
-    for (int k = 0; k < K; ++k) o("    y0(%d) += dn[%d] / gam;", M + k, M + k);
+    for (int k = 0; k < K; ++k) o("    y0(%d) += dn[%d] / %s;", M + k, M + k, lit(sp.gam_k[k]).c_str());
     for (int a = 0; a < M; ++a) {
-      o("    { const double dgas = a_s * dn[%d];", a);
+      o("    { const double dgas = dn[%d];   // mol per m^3 of REV", a);
       o("      y0(%d) += dgas / phi;", a);
       o("      src[%d] += dgas * %s / rho_unit; }", a, lit(sp.m[a]).c_str());
     }
@@ -427,11 +443,12 @@ void chem_choose_order(ChemSpec &sp, int ns, const double *T, const double *phi,
           for (int i = 0; i < ef; ++i) df *= c[u];
           for (int i = 0; i < eb; ++i) db *= c[u];
         }
-        const double d = (df - db) * (t < M ? 1.0 : gam);
+        const double d = (df - db) * (t < M ? 1.0 : sp.gam_k[t - M]);
         for (int s = 0; s < S; ++s) {
           const int st = sp.nu_b[r][s] - sp.nu_f[r][s];
           if (!st) continue;
-          const double coef = s < M ? (sp.hom[r] ? h : h * a_s / phi[j]) : h / gam;
+          const double coef = s < M ? (sp.kind[r] == 1 ? h : h * sp.w_r[r] / phi[j])
+                                    : h / sp.gam_k[s - M] * (sp.kind[r] == 2 ? sp.l_tpb / sp.a_k[s - M] : 1.0);
           A[s * S + t] -= coef * st * d;
           pat[s][t] = true;
         }

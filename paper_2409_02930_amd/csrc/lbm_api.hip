@@ -415,9 +415,15 @@ int specialize_chemistry(lbm_ctx *c) {
     sp.Ea_f[r] = c->chem_host.Ea_f[r];
     sp.A_b[r] = c->chem_host.A_b[r];
     sp.Ea_b[r] = c->chem_host.Ea_b[r];
-    sp.hom[r] = c->chem_host.hom[r];
+    sp.kind[r] = c->chem_host.kind[r];
+    sp.w_r[r] = c->chem_host.w_r[r];
   }
   for (int a = 0; a < M; ++a) sp.m[a] = c->m[a];
+  for (int k = 0; k < K; ++k) {
+    sp.gam_k[k] = c->chem_host.gam_k[k];
+    sp.a_k[k] = c->chem_host.a_k[k];
+  }
+  sp.l_tpb = c->chem_host.l_tpb;
   sp.R_U = kRU;
   if (c->have_perm) {
     memcpy(sp.perm, c->chem_perm, sizeof(sp.perm));
@@ -455,7 +461,7 @@ int sample_order(lbm_ctx *c, ChemSpec &sp) {
     }
     for (int k = 0; k < K; ++k) {
       HIPCHK(c, hipMemcpy(&x, c->theta + (size_t)k * N + n, sizeof(double), hipMemcpyDeviceToHost));
-      C[(size_t)j * S + M + k] = cp.gamma * x;
+      C[(size_t)j * S + M + k] = sp.gam_k[k] * x;
     }
   }
   chem_choose_order(sp, ns, T.data(), phi.data(), C.data(), c->dt / cp.n_sub, cp.a_s, cp.gamma);
@@ -664,21 +670,44 @@ int lbm_set_mechanism(lbm_ctx *c, const lbm_mechanism *mech) {
   const int fuel = c->chem.fuel, product = c->chem.product;
   ChemTables tab;
   memset(&tab, 0, sizeof(tab));
+  // surface phases: site density and specific area per surface species
+  int phase[LBM_KMAX];
+  bool two = false;
+  for (int k = 0; k < K; ++k) {
+    phase[k] = mech->surface_phase ? mech->surface_phase[k] : 0;
+    if (phase[k] != 0 && phase[k] != 1) return fail(c, LBM_EINVAL, "surface_phase must be 0 or 1");
+    two = two || phase[k] == 1;
+  }
+  if (two && (!(mech->gamma2 > 0) || !(mech->a_s2 > 0)))
+    return fail(c, LBM_EINVAL, "a second surface phase needs gamma2 and a_s2 > 0");
+  for (int k = 0; k < K; ++k) {
+    tab.gam_k[k] = phase[k] ? mech->gamma2 : mech->gamma;
+    tab.a_k[k] = phase[k] ? mech->a_s2 : mech->a_s;
+  }
+  tab.l_tpb = mech->l_tpb;
   for (int r = 0; r < R; ++r) {
-    int site_f = 0, site_b = 0;
+    int site[2][2] = {{0, 0}, {0, 0}};           // [phase][forward, backward]
+    bool gas = false, ph_in[2] = {false, false};
     for (int s = 0; s < S; ++s) {
       const int ef = mech->nu_f[r * S + s], eb = mech->nu_b[r * S + s];
       if (ef < 0 || ef > 3 || eb < 0 || eb > 3) return fail(c, LBM_EINVAL, "stoichiometric coefficients must be 0..3");
       tab.nu_f[r][s] = (int8_t)ef;
       tab.nu_b[r][s] = (int8_t)eb;
       if (s >= M) {
-        site_f += ef;
-        site_b += eb;
+        site[phase[s - M]][0] += ef;
+        site[phase[s - M]][1] += eb;
+        if (ef || eb) ph_in[phase[s - M]] = true;
+      } else if (ef || eb) {
+        gas = true;
       }
     }
-    if (site_f != site_b) return fail(c, LBM_EINVAL, "reaction %d is not site-balanced", r);
+    if (site[0][0] != site[0][1] || site[1][0] != site[1][1])
+      return fail(c, LBM_EINVAL, "reaction %d is not site-balanced on every phase", r);
     const int hom = mech->homogeneous ? mech->homogeneous[r] : 0;
+    const int edge = mech->edge ? mech->edge[r] : 0;
     if (hom != 0 && hom != 1) return fail(c, LBM_EINVAL, "homogeneous flags must be 0 or 1");
+    if (edge != 0 && edge != 1) return fail(c, LBM_EINVAL, "edge flags must be 0 or 1");
+    if (hom && edge) return fail(c, LBM_EINVAL, "reaction %d cannot be homogeneous and an edge reaction", r);
     if (hom) {                        // gas species only, zero net mass (eq sumRhoDot)
       double dm = 0.0, mm = 0.0;
       for (int s = 0; s < S; ++s) {
@@ -691,7 +720,14 @@ int lbm_set_mechanism(lbm_ctx *c, const lbm_mechanism *mech) {
       }
       if (fabs(dm) > 1e-12 * mm) return fail(c, LBM_EINVAL, "homogeneous reaction %d changes the mass", r);
     }
-    tab.hom[r] = (int8_t)hom;
+    if (edge) {                       // adsorbed species only, rate per unit TPB length
+      if (gas) return fail(c, LBM_EINVAL, "edge reaction %d has gas species", r);
+      if (!(mech->l_tpb > 0)) return fail(c, LBM_EINVAL, "edge reactions need l_tpb > 0");
+    }
+    if (!hom && !edge && ph_in[0] && ph_in[1])
+      return fail(c, LBM_EINVAL, "surface reaction %d spans two phases (mark it as an edge reaction)", r);
+    tab.kind[r] = (int8_t)(hom ? 1 : (edge ? 2 : 0));
+    tab.w_r[r] = ph_in[1] && !ph_in[0] ? mech->a_s2 : mech->a_s;
     if (!std::isfinite(mech->A_f[r]) || !std::isfinite(mech->A_b[r]) || !std::isfinite(mech->Ea_f[r]) ||
         !std::isfinite(mech->Ea_b[r]) || mech->A_f[r] < 0 || mech->A_b[r] < 0)
       return fail(c, LBM_EINVAL, "reaction %d: pre-factors must be finite and >= 0, energies finite", r);
@@ -718,9 +754,10 @@ int lbm_set_mechanism(lbm_ctx *c, const lbm_mechanism *mech) {
   cp.a_s = mech->a_s;
   cp.fuel = fuel;
   cp.product = product;
-  double st = 0.0;
-  for (int s = 0; s < K; ++s) st += mech->theta0[s];
-  if (fabs(st - 1.0) > 1e-9) return fail(c, LBM_EINVAL, "theta0 must sum to 1");
+  double st[2] = {0.0, 0.0};
+  for (int s = 0; s < K; ++s) st[phase[s]] += mech->theta0[s];
+  if (fabs(st[0] - 1.0) > 1e-9 || (two && fabs(st[1] - 1.0) > 1e-9))
+    return fail(c, LBM_EINVAL, "theta0 must sum to 1 on every surface phase");
   dfree(c->theta);
   c->theta = nullptr;
   int rc = dalloc(c, &c->theta, (size_t)K * c->N);
@@ -737,7 +774,7 @@ int lbm_set_mechanism(lbm_ctx *c, const lbm_mechanism *mech) {
   if (c->energy && mech->surf_cv) {
     if (!mech->surf_mass) return fail(c, LBM_EINVAL, "adsorbed-phase thermo needs surf_mass");
     for (int k = 0; k < K; ++k) {
-      const double w = mech->a_s * mech->gamma * mech->surf_mass[k] / (c->rho_unit * c->c2);
+      const double w = tab.a_k[k] * tab.gam_k[k] * mech->surf_mass[k] / (c->rho_unit * c->c2);
       if (!std::isfinite(w) || !std::isfinite(mech->surf_cv[k]) ||
           (mech->surf_u_form && !std::isfinite(mech->surf_u_form[k])))
         return fail(c, LBM_EINVAL, "adsorbed-phase thermo must be finite");

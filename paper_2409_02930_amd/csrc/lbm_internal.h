@@ -78,7 +78,12 @@ struct ChemTables {
   double A_f[LBM_RMAX], Ea_f[LBM_RMAX], A_b[LBM_RMAX], Ea_b[LBM_RMAX];
   alignas(16) int8_t nu_f[LBM_RMAX][16];
   alignas(16) int8_t nu_b[LBM_RMAX][16];
-  int8_t hom[LBM_RMAX];          // 1: homogeneous gas-phase reaction (weight phi, not a_s)
+  // gas-row weight of reaction r: w_r (a^(s) of its surface phase) or phi for a homogeneous one;
+  // coverage-row weight of surface species k: 1, or l_TPB / a_k for an edge reaction
+  double w_r[LBM_RMAX];
+  double gam_k[LBM_KMAX], a_k[LBM_KMAX];   // site density and area of species k's phase
+  double l_tpb;
+  int8_t kind[LBM_RMAX];         // 0 surface, 1 homogeneous gas-phase, 2 TPB edge
 };
 
 struct ChemParams {
@@ -123,7 +128,10 @@ struct ChemSpec {
   double m[LBM_MMAX];                            // gas molar masses, kg/mol
   double R_U;
   int perm[16];                                  // elimination order of the S = M + K unknowns
-  int hom[LBM_RMAX];                             // homogeneous gas-phase reactions
+  int kind[LBM_RMAX];                            // 0 surface, 1 homogeneous, 2 TPB edge
+  double w_r[LBM_RMAX];                          // gas-row weight of a surface reaction (a^(s))
+  double gam_k[16], a_k[16];                     // per surface species: site density, area
+  double l_tpb;
 };
 
 // launchers (lbm_kernels.hip)

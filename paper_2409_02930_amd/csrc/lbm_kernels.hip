@@ -997,8 +997,7 @@ __device__ __forceinline__ double mass_action(const NuRow &NF, const NuRow &NB, 
 template <int M, int K>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1)))
 void k_chem(const ChemParams cp) {
-  constexpr int S = M + K;      // all species (gas, vacancy, adsorbates)
-  constexpr int U = S - 1;      // Newton unknowns
+  constexpr int S = M + K;      // unknowns: gas concentrations and every coverage (vacancies too)
   __shared__ double s_k[2 * LBM_RMAX][64];    // kf, kb of every reaction at this lane's node
   const int lane = threadIdx.x;
   const int n = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1006,7 +1005,6 @@ void k_chem(const ChemParams cp) {
   const int N = cp.N;
   const double T = cp.T[n];
   const double phi = cp.phi[n];
-  const double gam = cp.gamma;
   const double h = cp.dt / cp.n_sub;
   const double inv_RT = 1.0 / (cp.R_U * T);
   const ChemTables *__restrict__ tb = cp.tab;
@@ -1014,84 +1012,74 @@ void k_chem(const ChemParams cp) {
     s_k[2 * r][lane] = tb->A_f[r] * exp(-tb->Ea_f[r] * inv_RT);
     s_k[2 * r + 1][lane] = tb->A_b[r] * exp(-tb->Ea_b[r] * inv_RT);
   }
-  double c0[M], th0[K];
+  double gk[K];                 // site density of each coverage's surface phase
 #pragma unroll
-  for (int a = 0; a < M; ++a) c0[a] = cp.rrho[(size_t)a * N + n] * cp.rho_unit / cp.m[a];
+  for (int k = 0; k < K; ++k) gk[k] = tb->gam_k[k];
+  double y0[S];
 #pragma unroll
-  for (int k = 0; k < K; ++k) th0[k] = cp.theta[(size_t)k * N + n];
+  for (int a = 0; a < M; ++a) y0[a] = cp.rrho[(size_t)a * N + n] * cp.rho_unit / cp.m[a];
+#pragma unroll
+  for (int k = 0; k < K; ++k) y0[M + k] = cp.theta[(size_t)k * N + n];
   double src[M];
 #pragma unroll
   for (int a = 0; a < M; ++a) src[a] = 0.0;
 
   for (int sub = 0; sub < cp.n_sub; ++sub) {
-    double y[U];
+    double y[S];
 #pragma unroll
-    for (int a = 0; a < M; ++a) y[a] = c0[a];
-#pragma unroll
-    for (int k = 1; k < K; ++k) y[M + k - 1] = th0[k];
+    for (int u = 0; u < S; ++u) y[u] = y0[u];
     for (int it = 0; it < cp.n_newton; ++it) {
-      // concentrations of every species at the iterate
       double C[S];
 #pragma unroll
       for (int a = 0; a < M; ++a) C[a] = y[a];
-      double sth = 0.0;
 #pragma unroll
-      for (int k = 1; k < K; ++k) {
-        C[M + k] = gam * y[M + k - 1];
-        sth += y[M + k - 1];
+      for (int k = 0; k < K; ++k) C[M + k] = gk[k] * y[M + k];
+      // Newton system divided row-wise by the phase weight (phi, Gamma_k):
+      //   J = I - (h / W) sum_r wt_rs st_rs dq_r/dy,  b = -(y - y0) + (h / W) sum_r wt_rs st_rs q_r
+      double J[S][S], b[S];
+#pragma unroll
+      for (int u = 0; u < S; ++u) {
+        b[u] = -(y[u] - y0[u]);
+#pragma unroll
+        for (int v = 0; v < S; ++v) J[u][v] = (u == v) ? 1.0 : 0.0;
       }
-      C[M] = gam * (1.0 - sth);
-      // Newton system divided row-wise by W (rows equilibrated):
-      //   J = I - h W^-1 s S dq/dy,  b = -((y - y0) - h W^-1 s S q)
-      double J[U][U], b[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const double yy0 = (u < M) ? c0[u] : th0[u - M + 1];
-        b[u] = -(y[u] - yy0);
-#pragma unroll
-        for (int v = 0; v < U; ++v) J[u][v] = (u == v) ? 1.0 : 0.0;
-      }
-      const double hg = h * cp.a_s / phi, hs = h / gam;   // h s / W for gas and surface rows
       for (int r = 0; r < cp.R; ++r) {
         const NuRow NF = load_nu(tb->nu_f[r]), NB = load_nu(tb->nu_b[r]);
-        // a homogeneous reaction's gas rows take phi q (per total volume) where a
-        // surface reaction's take a_s q: scale by phi / a_s, gas rows only exist for it
-        const double wq = tb->hom[r] ? phi / cp.a_s : 1.0;
+        const int kind = tb->kind[r];
+        // gas rows: a^(s) of the reaction's surface, phi for a homogeneous reaction;
+        // coverage rows: 1, l_TPB / a^(s)_k for a TPB edge reaction
+        const double wg = (kind == 1 ? phi : tb->w_r[r]) * h / phi;
         double dq[S];
-        const double q = wq * mass_action<S>(NF, NB, s_k[2 * r][lane], s_k[2 * r + 1][lane], C, dq);
-        // chain rule to the unknowns: dC_a/dy_a = 1, dC_s/dtheta_s = gamma, dC_V/dtheta_s = -gamma
-        double dqu[U];
+        const double q = mass_action<S>(NF, NB, s_k[2 * r][lane], s_k[2 * r + 1][lane], C, dq);
 #pragma unroll
-        for (int a = 0; a < M; ++a) dqu[a] = wq * dq[a];
+        for (int k = 0; k < K; ++k) dq[M + k] *= gk[k];   // dC_k / dtheta_k = Gamma_k
 #pragma unroll
-        for (int k = 1; k < K; ++k) dqu[M + k - 1] = wq * gam * (dq[M + k] - dq[M]);
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const int s = (u < M) ? u : u + 1;
-          const int st = nu_of(NB, s) - nu_of(NF, s);
+        for (int u = 0; u < S; ++u) {
+          const int st = nu_of(NB, u) - nu_of(NF, u);
           if (st) {
-            const double coef = ((u < M) ? hg : hs) * st;
+            const double coef = st * ((u < M) ? wg
+                                              : h / gk[u - M] * (kind == 2 ? tb->l_tpb / tb->a_k[u - M] : 1.0));
             b[u] += coef * q;
 #pragma unroll
-            for (int v = 0; v < U; ++v) J[u][v] -= coef * dqu[v];
+            for (int v = 0; v < S; ++v) J[u][v] -= coef * dq[v];
           }
         }
       }
       // LU with partial pivoting on the equilibrated rows (first maximum on ties)
 #pragma unroll
-      for (int k = 0; k < U; ++k) {
+      for (int k = 0; k < S; ++k) {
         int piv = k;
         double amax = fabs(J[k][k]);
 #pragma unroll
-        for (int r = k + 1; r < U; ++r) {
+        for (int r = k + 1; r < S; ++r) {
           const double av = fabs(J[r][k]);
           if (av > amax) { amax = av; piv = r; }
         }
 #pragma unroll
-        for (int r = k + 1; r < U; ++r) {
+        for (int r = k + 1; r < S; ++r) {
           const bool sw = (piv == r);
 #pragma unroll
-          for (int c = k; c < U; ++c) {
+          for (int c = k; c < S; ++c) {
             const double tk = J[k][c];
             J[k][c] = sw ? J[r][c] : tk;
             J[r][c] = sw ? tk : J[r][c];
@@ -1102,54 +1090,50 @@ void k_chem(const ChemParams cp) {
         }
         const double inv = 1.0 / J[k][k];
 #pragma unroll
-        for (int r = k + 1; r < U; ++r) {
+        for (int r = k + 1; r < S; ++r) {
           const double l = J[r][k] * inv;
 #pragma unroll
-          for (int c = k + 1; c < U; ++c) J[r][c] -= l * J[k][c];
+          for (int c = k + 1; c < S; ++c) J[r][c] -= l * J[k][c];
           b[r] -= l * b[k];
         }
       }
 #pragma unroll
-      for (int k = U - 1; k >= 0; --k) {
+      for (int k = S - 1; k >= 0; --k) {
         double sacc = b[k];
 #pragma unroll
-        for (int c = k + 1; c < U; ++c) sacc -= J[k][c] * b[c];
+        for (int c = k + 1; c < S; ++c) sacc -= J[k][c] * b[c];
         b[k] = sacc / J[k][k];
       }
 #pragma unroll
-      for (int u = 0; u < U; ++u) y[u] += b[u];
+      for (int u = 0; u < S; ++u) y[u] += b[u];
     }
-    // extents at the implicit state, conservative update of both phases
+    // extents at the implicit state, conservative update of every phase
     double C[S];
 #pragma unroll
     for (int a = 0; a < M; ++a) C[a] = y[a];
-    double sth = 0.0;
 #pragma unroll
-    for (int k = 1; k < K; ++k) {
-      C[M + k] = gam * y[M + k - 1];
-      sth += y[M + k - 1];
-    }
-    C[M] = gam * (1.0 - sth);
-    double dn[S];
+    for (int k = 0; k < K; ++k) C[M + k] = gk[k] * y[M + k];
+    double dn[S];                 // gas: mol per m^3 of REV; coverages: mol per m^2 of their surface
 #pragma unroll
-    for (int s = 0; s < S; ++s) dn[s] = 0.0;
+    for (int u = 0; u < S; ++u) dn[u] = 0.0;
     for (int r = 0; r < cp.R; ++r) {
       const NuRow NF = load_nu(tb->nu_f[r]), NB = load_nu(tb->nu_b[r]);
-      const double wq = tb->hom[r] ? phi / cp.a_s : 1.0;
-      const double dxi = wq * h * mass_action<S>(NF, NB, s_k[2 * r][lane], s_k[2 * r + 1][lane], C, nullptr);
+      const int kind = tb->kind[r];
+      const double dxi = h * mass_action<S>(NF, NB, s_k[2 * r][lane], s_k[2 * r + 1][lane], C, nullptr);
+      const double wgas = kind == 1 ? phi : tb->w_r[r];
 #pragma unroll
-      for (int s = 0; s < S; ++s) {
-        const int st = nu_of(NB, s) - nu_of(NF, s);
-        if (st) dn[s] += st * dxi;
+      for (int u = 0; u < S; ++u) {
+        const int st = nu_of(NB, u) - nu_of(NF, u);
+        if (st)
+          dn[u] += st * dxi * ((u < M) ? wgas : (kind == 2 ? tb->l_tpb / tb->a_k[u - M] : 1.0));
       }
     }
 #pragma unroll
-    for (int k = 0; k < K; ++k) th0[k] += dn[M + k] / gam;
+    for (int k = 0; k < K; ++k) y0[M + k] += dn[M + k] / gk[k];
 #pragma unroll
     for (int a = 0; a < M; ++a) {
-      const double dgas = cp.a_s * dn[a];
-      c0[a] += dgas / phi;
-      src[a] += dgas * cp.m[a] / cp.rho_unit;
+      y0[a] += dn[a] / phi;
+      src[a] += dn[a] * cp.m[a] / cp.rho_unit;
     }
   }
   if (cp.faradaic) {
@@ -1168,7 +1152,7 @@ void k_chem(const ChemParams cp) {
   }
   cp.srcsum[n] = ssum;
 #pragma unroll
-  for (int k = 0; k < K; ++k) cp.theta[(size_t)k * N + n] = th0[k];
+  for (int k = 0; k < K; ++k) cp.theta[(size_t)k * N + n] = y0[M + k];
 }
 
 // Faradaic source only (no mechanism installed).

@@ -54,7 +54,8 @@ class lbm_mechanism(C.Structure):
         ("n_newton", C.c_int32), ("nu_f", _ip), ("nu_b", _ip), ("A_f", _dp), ("Ea_f", _dp),
         ("A_b", _dp), ("Ea_b", _dp), ("gamma", C.c_double), ("a_s", C.c_double),
         ("surf_mass", _dp), ("theta0", _dp), ("surf_cv", _dp), ("surf_u_form", _dp),
-        ("homogeneous", _ip),
+        ("homogeneous", _ip), ("surface_phase", _ip), ("gamma2", C.c_double), ("a_s2", C.c_double),
+        ("edge", _ip), ("l_tpb", C.c_double),
     ]
 
 
@@ -194,8 +195,8 @@ class Lattice:
 
     def set_mechanism(self, mech):
         """mech: object with K, nu_f, nu_b, A_f, Ea_f, A_b, Ea_b, gamma, a_s, surf_mass, theta0,
-        n_sub, n_newton and optionally surf_cv, surf_u_form, homogeneous (None removes the
-        mechanism)."""
+        n_sub, n_newton and optionally surf_cv, surf_u_form, homogeneous, surface_phase,
+        gamma2, a_s2, edge, l_tpb (None removes the mechanism)."""
         if mech is None:
             self._check(_lib.lbm_set_mechanism(self.ctx, None))
             self.K = 0
@@ -205,7 +206,9 @@ class Lattice:
                     surf_mass=_arr(mech.surf_mass), theta0=_arr(mech.theta0),
                     surf_cv=_arr(getattr(mech, "surf_cv", None)),
                     surf_u_form=_arr(getattr(mech, "surf_u_form", None)),
-                    homogeneous=_arr(getattr(mech, "homogeneous", None), np.int32))
+                    homogeneous=_arr(getattr(mech, "homogeneous", None), np.int32),
+                    surface_phase=_arr(getattr(mech, "surface_phase", None), np.int32),
+                    edge=_arr(getattr(mech, "edge", None), np.int32))
         st = lbm_mechanism()
         st.n_surface = int(mech.K)
         st.n_reactions = int(np.asarray(mech.nu_f).shape[0])
@@ -213,6 +216,11 @@ class Lattice:
         st.nu_f = _ptr(keep["nu_f"], C.c_int32)
         st.nu_b = _ptr(keep["nu_b"], C.c_int32)
         st.homogeneous = _ptr(keep["homogeneous"], C.c_int32)
+        st.surface_phase = _ptr(keep["surface_phase"], C.c_int32)
+        st.edge = _ptr(keep["edge"], C.c_int32)
+        st.gamma2 = float(getattr(mech, "gamma2", 0.0) or 0.0)
+        st.a_s2 = float(getattr(mech, "a_s2", 0.0) or 0.0)
+        st.l_tpb = float(getattr(mech, "l_tpb", 0.0) or 0.0)
         for k in ("A_f", "Ea_f", "A_b", "Ea_b", "surf_mass", "theta0", "surf_cv", "surf_u_form"):
             setattr(st, k, _ptr(keep[k]))
         st.gamma, st.a_s = float(mech.gamma), float(mech.a_s)

@@ -156,6 +156,22 @@ def test_homogeneous_gas_reactions(lbm, case, kernel):
     _run(lbm, HOMOGENEOUS[case](), 20, chem_kernel=kind)
 
 
+TWO_PHASE = {
+    "edge_transfer_only": lambda: synth.two_phase_tpb(nx=5, ny=3, with_gas=False),
+    "adsorption_edge_desorption": lambda: synth.two_phase_tpb(nx=6, ny=4, with_gas=True),
+}
+
+
+@pytest.mark.parametrize("kernel", ["specialized", "generic"])
+@pytest.mark.parametrize("case", list(TWO_PHASE))
+def test_two_surface_phases_with_tpb_edge(lbm, case, kernel):
+    """Electrode and electrolyte surfaces with their own site densities and areas,
+    joined by a TPB edge reaction (eqs totalSurfaceReactionRateTPB_electrode and
+    _electrolyte)."""
+    kind = lbm.CHEM_SPECIALIZED if kernel == "specialized" else lbm.CHEM_GENERIC
+    _run(lbm, TWO_PHASE[case](), 20, chem_kernel=kind)
+
+
 def test_specialized_chemistry_matches_generic_full_newton(lbm):
     """Specialised vs generic kernel on a stiffer mechanism setting (more
     sub-steps and Newton iterations), both through lbm_step: every field
