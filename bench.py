@@ -72,11 +72,11 @@ def kernel_bytes_per_node(w, kernel, pop_bytes=8):
         rd += (M + D) if chem else 0                  # previous step's source and velocity (source populations)
         wr = D + 1 + (D if w.pore_radius and np.isfinite(w.pore_radius) else 0)
         wr += (M + D) if chem else 0                  # chemistry input densities, node velocity
-        wr += (1 + M + D) if E else 0
+        wr += (1 + M + 2 + D) if E else 0
         return pop_bytes * pops + 8 * (rd + wr)
     if kernel == "mixture":
         pops = 2 * (1 + E) * Q
-        rd = 1 + D + 1 + D + (1 if chem else 0) + ((M + D + 1) if E else 0)
+        rd = 1 + D + 1 + D + (1 if chem else 0) + ((M + 2 + D + 1) if E else 0)
         return pop_bytes * pops + 8 * rd
     if kernel == "chem":
         return 8 * (M + 2 + K + K + M + 1)          # rho_a, T, phi, theta in/out, source, sum

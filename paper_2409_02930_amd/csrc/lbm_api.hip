@@ -359,7 +359,7 @@ int common_init(const lbm_config *cfg, int N, const double *X0, const double *P0
       (rc = dalloc(c, &c->srcsum, N)))
     return rc;
   if (c->energy) {
-    if ((rc = dalloc(c, &c->rY, (size_t)c->M * N)) || (rc = dalloc(c, &c->rqd, (size_t)D * N)) ||
+    if ((rc = dalloc(c, &c->rY, (size_t)(c->M + 2) * N)) || (rc = dalloc(c, &c->rqd, (size_t)D * N)) ||
         (rc = dalloc(c, &c->T[0], N)) || (rc = dalloc(c, &c->T[1], N)))
       return rc;
   }

@@ -56,7 +56,8 @@ struct KParams {
   double *rRT;              // [N] mixture R T
   double *rFk;              // [D][N] Knudsen force
   double *rrho;             // [M][N] species densities (chemistry input)
-  double *rY;               // [M][N] mass fractions (energy lattice)
+  double *rY;               // [M+2][N] mass fractions (energy lattice), then sum_a uf_a Y_a and
+                            //   sum_a (cv_a + R_a / T) Y_a, so sum_a H_a(T) Y_a = row M + T row M+1
   double *rqd;              // [D][N] sum_a H_a Y_a (u_a - u_bar) (energy lattice)
   // ping-pong node records between consecutive steps, kRec planes of N doubles:
   //   planes 0..2 v = u/phi, planes 3..7 species source rho_dot_a dt (lattice units)

@@ -668,8 +668,15 @@ __global__ __launch_bounds__(64 * (M + 1 + (ENERGY ? 1 : 0))) void k_species(con
           }
           p.rqd[(size_t)d * N + n] = sacc;
         }
+        double yu = 0.0, yc = 0.0;
 #pragma unroll
-        for (int a = 0; a < M; ++a) p.rY[(size_t)a * N + n] = s.Y[a];
+        for (int a = 0; a < M; ++a) {
+          p.rY[(size_t)a * N + n] = s.Y[a];
+          yu += p.uf[a] * s.Y[a];
+          yc += (p.cv[a] + p.theta_ref * p.mmin_over_m[a] * p.inv_T_ref) * s.Y[a];
+        }
+        p.rY[(size_t)M * N + n] = yu;           // H_a(T) = uf_a + (cv_a + R_a/T) T: the stencil of
+        p.rY[(size_t)(M + 1) * N + n] = yc;     // sum_a H_a(T_x) Y_a needs two fields, not M
       }
     }
     __syncthreads();
@@ -785,9 +792,7 @@ __global__ __launch_bounds__(256) void k_mixture(const KParams p) {
     for (int i = 0; i < Q; ++i) {
       if (cnorm2<D>(i) == 0) continue;
       const int m = nb_node<D>(p, nd, i);
-      double hy = 0.0;
-#pragma unroll
-      for (int a = 0; a < M; ++a) hy += Ha[a] * p.rY[(size_t)a * N + m];
+      const double hy = p.rY[(size_t)M * N + m] + T * p.rY[(size_t)(M + 1) * N + m];   // sum_a H_a(T) Y_a(m)
 #pragma unroll
       for (int d = 0; d < D; ++d) {
         const int c = cdir(i, d);
