@@ -55,6 +55,17 @@ Readings adopted where the paper is silent, garbled or self-inconsistent
       barycentric velocity, and a nearly pure species is almost collisionless).
   R26 Faradaic source: fuel consumed / product produced at a prescribed
       volumetric molar rate (explicit).
+  R30 charge transfer (Section 4.1, eq volumetricCurrent; the rate law is not
+      printed): a TPB edge reaction that releases z electrons into the
+      electrode has k_f exp(beta z F dPhi / (R_U T)) and
+      k_b exp(-(1 - beta) z F dPhi / (R_U T)), dPhi = Phi_electrode -
+      Phi_electrolyte, beta the symmetry factor (mass action with a
+      Butler-Volmer potential factor).  I^(v) = F l_TPB sum_r z_r xi_r / dt with
+      the step's extents.  Charge transport (eqs areaCurrentDensity,
+      electrolytePotential) integrates along x with the rectangle rule over the
+      cells 0..x of each (y, z) line, Phi_electrolyte = 0 before cell 0; a
+      step's rates take the potentials integrated from the previous step's
+      currents (dPhi = Phi_electrode before the first step).
 """
 from __future__ import annotations
 
@@ -63,6 +74,7 @@ import math
 import numpy as np
 
 R_U = 8.314462618       # J/(mol K)
+F_C = 96485.33212       # C/mol
 
 # x-axis boundary kinds (y and z are periodic)
 BC_PERIODIC = 0
@@ -195,6 +207,15 @@ class Oracle:
             self.cv_lat = np.asarray(w.cv, dtype=np.float64) / self.c2
             self.uf_lat = np.asarray(w.u_form, dtype=np.float64) / self.c2
         self.T_field = np.asarray(w.T0, dtype=np.float64).copy()
+        # electrode coupling (Section 4.2, R30): Phi_electrode (V) and the electrolyte
+        # resistivity Omega(x) (Ohm m); dphi is the potential difference the rates see
+        self.electrode = getattr(w, "electrode", None)
+        self.i_v = np.zeros(self.N)
+        self.i_a = np.zeros(self.N)
+        self.phi_el = np.zeros(self.N)
+        self.dphi = np.zeros(self.N)
+        if self.electrode is not None:
+            self.dphi[:] = float(self.electrode["phi_ed"])
         self.step_count = 0
         self._init_state()
 
@@ -356,6 +377,15 @@ class Oracle:
         T = mac["T"]
         kf = mech.A_f[:, None] * np.exp(-mech.Ea_f[:, None] / (R_U * T[None, :]))      # (R, N)
         kb = mech.A_b[:, None] * np.exp(-mech.Ea_b[:, None] / (R_U * T[None, :]))
+        zc = getattr(mech, "charge_z", None)
+        if zc is not None:
+            # R30: potential factors of the charge-transfer reactions
+            zc = np.asarray(zc, dtype=np.float64)
+            bct = np.asarray(mech.beta_ct, dtype=np.float64)
+            fpot = F_C * self.dphi / (R_U * T)                                           # (N,)
+            kf = kf * np.exp((bct * zc)[:, None] * fpot[None, :])
+            kb = kb * np.exp(-((1.0 - bct) * zc)[:, None] * fpot[None, :])
+        iv = np.zeros(self.N)
         nu_f = mech.nu_f.astype(np.float64)
         nu_b = mech.nu_b.astype(np.float64)
         stoich = (mech.nu_b - mech.nu_f).astype(np.float64)                            # (R, S)
@@ -425,6 +455,8 @@ class Oracle:
                 y = y + np.linalg.solve(J, -F[:, :, None])[:, :, 0]
             C = conc(y[:, :M], y[:, M:])
             dxi = h * rates(C)                                                           # extents
+            if zc is not None:
+                iv += F_C * mech.l_tpb * (dxi @ zc) / self.dt                            # eq volumetricCurrent
             th = th + (dxi @ surf_st) / gam_k[None, :]
             dgas = (vol * dxi) @ gas_st                                                  # mol / m^3 total
             c = c + dgas / phi[:, None]
@@ -434,7 +466,18 @@ class Oracle:
             r = np.asarray(self.w.faradaic_rate, dtype=np.float64) * self.dt             # mol/m^3 per step
             src[:, fu] -= r * self.m[fu] / self.rho_unit
             src[:, pr] += r * self.m[pr] / self.rho_unit
+        self._iv = iv
         return src.T.copy(), th.T.copy()
+
+    def charge_transport(self, iv):
+        """eqs areaCurrentDensity and electrolytePotential along x (R30): the area current
+        density I^(a) and the electrolyte potential of every node from the volumetric
+        current I^(v) (A/m^3), dx in metres, Omega(x) in Ohm m."""
+        dx = self.w.dx
+        om = np.asarray(self.electrode["omega"], dtype=np.float64)                      # (nx,)
+        ia = np.cumsum(self.to_grid(iv) * dx, axis=-1)                                   # A/m^2
+        pel = np.cumsum(ia * om * dx, axis=-1)                                           # V
+        return self.from_grid(ia), self.from_grid(pel)
 
     def surface_energy(self, theta, T):
         """Internal energy of the adsorbed phase per unit volume, lattice units
@@ -569,6 +612,10 @@ class Oracle:
         if self.energy:
             self.g = self.stream(new_g, ("energy",), mac)
         self.theta = theta_new
+        if self.electrode is not None:
+            self.i_v = self._iv if self.mech is not None else np.zeros(self.N)
+            self.i_a, self.phi_el = self.charge_transport(self.i_v)
+            self.dphi = float(self.electrode["phi_ed"]) - self.phi_el
         self.step_count += 1
 
     # ----- S11 ---------------------------------------------------------------

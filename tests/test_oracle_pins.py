@@ -562,3 +562,80 @@ def test_two_phase_chemistry_conserves_sites_and_mass():
     scale = (o.phi * mac["rho_a"].sum(0)) * o.rho_unit
     assert np.all(np.abs(gas + surf) / scale < 1e-13)
     assert np.any(np.abs(gas) / scale > 1e-8)
+
+
+# --------------------------------------------------------------------------
+# Charge transfer and charge transport (Sections 4.1-4.2, R30)
+# --------------------------------------------------------------------------
+
+def _charge_slab(theta0, z=1, beta=0.5, kf=3.0e1, kb=1.0e1, nx=3, ny=2, phi_ed=0.0, omega=0.0):
+    w = synth.electrode_slab(nx=nx, ny=ny, phi_ed=phi_ed, omega=omega, beta=beta, with_gas=False,
+                             kf=kf, kb=kb)
+    w.mech.theta0 = np.asarray(theta0, dtype=np.float64)
+    w.mech.charge_z = np.array([z], dtype=np.int32)
+    return w
+
+
+def test_charge_transfer_rests_at_the_nernst_potential():
+    """The net charge-transfer rate vanishes where the electrode potential balances the
+    mass-action quotient: dPhi_eq = (R_U T / (z F)) ln(kb C_A2 C_V1 / (kf C_A1 C_V2)); there
+    the step produces no current and leaves the coverages unchanged, while 20 mV above it
+    the oxidation runs (positive current)."""
+    th0 = [0.4, 0.6, 0.7, 0.3]
+    w = _charge_slab(th0, z=2, beta=0.3)
+    m = w.mech
+    C = np.array([m.gamma * th0[0], m.gamma * th0[1], m.gamma2 * th0[2], m.gamma2 * th0[3]])
+    T = w.T0[0]
+    eq = lo.R_U * T / (2 * lo.F_C) * math.log(m.A_b[0] * C[3] * C[0] / (m.A_f[0] * C[1] * C[2]))
+    w.electrode["phi_ed"] = eq
+    o = lo.Oracle(w)
+    o.step(1)
+    w2 = _charge_slab(th0, z=2, beta=0.3, phi_ed=eq + 0.02)
+    o2 = lo.Oracle(w2)
+    o2.step(1)
+    assert np.all(o2.i_v > 1e6)
+    assert np.all(np.abs(o.i_v) < 1e-9 * o2.i_v)
+    assert np.allclose(o.theta, np.asarray(th0)[:, None], rtol=0, atol=1e-15)
+
+
+def test_charge_transfer_tafel_slope_is_beta_z_f_over_rt():
+    """Far from equilibrium (no product on the surface, slow kinetics) the oxidation current
+    grows as exp(beta z F dPhi / (R_U T)): raising the potential by 10 mV multiplies it by
+    exp(beta z F 0.01 / (R_U T)), with beta = 0.3, z = 2 (not 1 - beta, not z = 1)."""
+    th0 = [0.4, 0.6, 1.0, 0.0]
+    cur = []
+    for ph in (0.05, 0.06):
+        o = lo.Oracle(_charge_slab(th0, z=2, beta=0.3, phi_ed=ph))
+        o.step(1)
+        cur.append(o.i_v.copy())
+    T = 1073.0
+    ratio = math.exp(0.3 * 2 * lo.F_C * 0.01 / (lo.R_U * T))
+    assert np.allclose(cur[1] / cur[0], ratio, rtol=1e-6, atol=0)
+
+
+def test_charge_balance_current_equals_transferred_adsorbate():
+    """eq volumetricCurrent against the coverage bookkeeping: the charge one step releases per
+    unit volume, I^(v) dt, is z F times the moles of A2 formed on the electrolyte surface,
+    a2 Gamma2 (theta_A2' - theta_A2), with z = 2."""
+    th0 = [0.4, 0.6, 0.9, 0.1]
+    w = _charge_slab(th0, z=2, beta=0.5, kf=3.0e5, kb=1.0e5, phi_ed=0.03)
+    o = lo.Oracle(w)
+    m = w.mech
+    o.step(1)
+    moles = m.a_s2 * m.gamma2 * (o.theta[3] - th0[3])
+    assert np.all(moles > 0)
+    assert np.allclose(o.i_v * o.dt, 2 * lo.F_C * moles, rtol=1e-9, atol=0)
+
+
+def test_charge_transport_closed_form_for_uniform_current():
+    """eqs areaCurrentDensity, electrolytePotential with a uniform volumetric current I and
+    resistivity Omega, integrated from x = 0 cell by cell: I^(a)(x_i) = (i + 1) I dx and
+    Phi(x_i) = Omega I dx^2 (i + 1)(i + 2) / 2 on every (y) line."""
+    w = synth.electrode_slab(nx=7, ny=3, omega=0.25)
+    o = lo.Oracle(w)
+    I = 3.0e9
+    ia, pel = o.charge_transport(np.full(o.N, I))
+    i = np.tile(np.arange(w.nx), w.ny).astype(np.float64)
+    dx = w.dx
+    assert np.allclose(ia, (i + 1) * I * dx, rtol=1e-13, atol=0)
+    assert np.allclose(pel, 0.25 * I * dx * dx * (i + 1) * (i + 2) / 2, rtol=1e-13, atol=0)

@@ -67,6 +67,10 @@ class Mechanism:
     a_s2: float = 0.0
     edge: Optional[np.ndarray] = None
     l_tpb: float = 0.0
+    # charge transfer (Section 4.1): charge_z (R,) electrons released into the electrode by the
+    # forward direction of a TPB edge reaction (0: none), beta_ct (R,) symmetry factors
+    charge_z: Optional[np.ndarray] = None
+    beta_ct: Optional[np.ndarray] = None
 
     @property
     def R(self) -> int:
@@ -108,6 +112,9 @@ class Workload:
     mech: Optional[Mechanism] = None
     faradaic_rate: Optional[np.ndarray] = None   # (N,) mol/(m^3 s) of fuel consumed
     faradaic_species: tuple = (0, 1)             # (fuel, product)
+    # electrode coupling (Section 4.2): {"phi_ed": electrode potential V, "omega": (nx,)
+    # electrolyte resistivity Ohm m}; None: no charge transport
+    electrode: Optional[dict] = None
     meta: dict = field(default_factory=dict)
 
     @property
@@ -373,6 +380,27 @@ def two_phase_tpb(nx: int = 6, ny: int = 4, phi: float = 0.4, theta_a1: float = 
                     D_ref_lat=synthetic_D_ref(m), X0=X0, P0=_uniform(N, P_ATM), T0=_uniform(N, 1073.0),
                     phi=_uniform(N, phi), tort=_uniform(N, phi ** -0.5), pore_radius=1e-6, steps=100,
                     T_ref=1073.0, mech=mech)
+
+
+def electrode_slab(nx: int = 12, ny: int = 2, phi_ed: float = 0.05, omega: float = 5.0e-3,
+                   beta: float = 0.5, with_gas: bool = True, kf: float = 3.0e3,
+                   kb: float = 1.0e3) -> Workload:
+    """The two-phase TPB mechanism of two_phase_tpb with its edge reaction as a
+    charge transfer (A1 + V2 <=> A2 + V1 + e-, one electron into the electrode,
+    symmetry factor beta), on a D2Q9 slab periodic in y and bounce-back at both
+    x ends; electrode potential phi_ed (V) and a uniform electrolyte resistivity
+    omega (Ohm m) along x."""
+    w = two_phase_tpb(nx=nx, ny=ny, with_gas=with_gas, kf=kf, kb=kb)
+    R = w.mech.R
+    z = np.zeros(R, dtype=np.int32)
+    z[0] = 1
+    w.mech.charge_z = z
+    w.mech.beta_ct = np.full(R, beta)
+    w.bc_lo = BC_BOUNCEBACK
+    w.bc_hi = BC_BOUNCEBACK
+    w.electrode = {"phi_ed": float(phi_ed), "omega": np.full(nx, float(omega))}
+    w.name = "electrode_slab"
+    return w
 
 
 def config4_columns(seed: int = 4, n_cols: int = 64, lmin: int = 200, lmax: int = 2000):
