@@ -139,6 +139,17 @@ typedef struct {
   double a_s2;             /* specific surface area of phase 1, 1/m                        */
   const int32_t *edge;
   double l_tpb;            /* TPB length per unit volume, 1/m^2                            */
+  /* Charge transfer at the TPB (Section 4.1, eq volumetricCurrent).  charge_z [R] (NULL: none)
+   * is the number of electrons the forward direction of an edge reaction releases into the
+   * electrode (-4..4; only edge reactions may carry charge); beta_ct [R] (required with
+   * charge_z) the symmetry factor in [0, 1].  With dPhi = Phi_electrode - Phi_electrolyte at
+   * the node, the mass-action constants become k_f exp(beta z F dPhi / (R_U T)) and
+   * k_b exp(-(1 - beta) z F dPhi / (R_U T)) (dPhi = 0 without lbm_set_electrode), and the
+   * step's volumetric current I^(v) = F l_TPB sum_r z_r xi_r / dt (A/m^3, extents xi_r per
+   * unit TPB length over the step) is kept for lbm_get_charge.  Mechanisms with charge
+   * transfer run the generic chemistry kernel.                                             */
+  const int32_t *charge_z;
+  const double *beta_ct;
 } lbm_mechanism;
 
 /* Creates a context for a rectangular grid.  X0 [M][N] mole fractions, P0 [N]
@@ -186,6 +197,25 @@ int lbm_set_chem_kernel(lbm_ctx *ctx, int32_t kind);
  * species `fuel` and produces species `product` (explicit, added to the
  * chemistry source; NULL removes it).  Only valid before the first lbm_step. */
 int lbm_set_faradaic_source(lbm_ctx *ctx, const double *rate, int32_t fuel, int32_t product);
+
+/* Electrode coupling and 1-D charge transport along x (Section 4.2, eqs areaCurrentDensity,
+ * electrolytePotential).  phi_electrode: potential of the electrode phase, V (spatially
+ * constant, eq electrodePotential); omega: host [nx] electrolyte resistivity in Ohm m,
+ * copied; NULL switches the coupling off.  Regular grids only (LBM_EINVAL for packed
+ * columns).  After each step's chemistry the library integrates, on every (y, z) line from
+ * x = 0 cell by cell (rectangle rule, Phi_electrolyte = 0 before the first cell),
+ * I^(a)(x) = sum I^(v) dx and Phi_electrolyte(x) = sum I^(a) Omega dx; the next step's
+ * charge-transfer rates see dPhi = phi_electrode - Phi_electrolyte(x) (dPhi = phi_electrode
+ * before the first integration).  May be called between steps (e.g. to sweep the
+ * potential); it drops a captured step graph.  The electrode state is not part of
+ * snapshots (lbm_save returns LBM_ESTATE while the coupling is on).                       */
+int lbm_set_electrode(lbm_ctx *ctx, double phi_electrode, const double *omega);
+
+/* Copies to host [N] arrays (each may be NULL) the last step's volumetric current I^(v)
+ * (A/m^3), area current density I^(a) (A/m^2) and electrolyte potential (V); synchronizes
+ * the stream.  Arrays the installed model does not produce are zero.  LBM_ESTATE without a
+ * charge-transfer mechanism or an electrode.                                               */
+int lbm_get_charge(lbm_ctx *ctx, double *iv, double *ia, double *phi_el);
 
 /* Advances n_steps time steps, asynchronously on the configured stream. */
 int lbm_step(lbm_ctx *ctx, int64_t n_steps);

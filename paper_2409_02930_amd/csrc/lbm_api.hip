@@ -16,6 +16,7 @@
 namespace {
 
 constexpr double kRU = 8.314462618;      // J/(mol K)
+constexpr double kFC = 96485.33212;      // C/mol
 constexpr int kTimingRing = 64;          // steps of per-kernel events kept
 
 struct Buf {
@@ -62,6 +63,10 @@ struct lbm_ctx {
   int knudsen = 0;
   double pore_radius = 0.0;
   int has_mech = 0, has_faradaic = 0;
+  int has_ct = 0;                       // the mechanism has charge-transfer reactions
+  int electrode = 0;                    // charge transport along x (lbm_set_electrode)
+  double phi_ed = 0.0;                  // electrode potential, V
+  double *iv = nullptr, *ia = nullptr, *pel = nullptr, *omega_x = nullptr;
   ChemParams chem;
   ChemTables *chem_tab = nullptr;
   ChemTables chem_host;                 // host copy of the installed mechanism
@@ -503,11 +508,26 @@ int enqueue_step(lbm_ctx *c, int record_slot) {
     cp.dt = c->dt;
     cp.rho_unit = c->rho_unit;
     cp.R_U = kRU;
+    cp.F_C = kFC;
+    cp.iv = c->has_ct ? c->iv : nullptr;
+    cp.pel = c->electrode ? c->pel : nullptr;
+    cp.phi_ed = c->phi_ed;
     for (int a = 0; a < c->M; ++a) cp.m[a] = c->m[a];
     if (c->chem_fn)
       HIPCHK(c, launch_chem_specialized(c->chem_fn, cp, c->stream));
     else
       HIPCHK(c, launch_chem(cp, c->stream));
+  }
+  if (c->electrode) {           // the next step's rates see the potentials of this step's currents
+    ChargeParams q;
+    q.nx = c->nx;
+    q.lines = c->ny * c->nz;
+    q.dx = c->dx;
+    q.iv = c->iv;
+    q.omega = c->omega_x;
+    q.ia = c->ia;
+    q.pel = c->pel;
+    HIPCHK(c, launch_charge(q, c->stream));
   }
   if (ev) HIPCHK(c, hipEventRecord(ev[2], c->stream));
   if (ev) HIPCHK(c, hipEventRecord(ev[3], c->stream));   // no separate source pass (added at the pull)
@@ -562,7 +582,7 @@ int capture_steps(lbm_ctx *c) {
 // chemistry kernel of the remaining run in place.
 bool graph_ready(const lbm_ctx *c) {
   if (!c->graph_steps || c->first_step || c->steps_done < 1) return false;
-  if (c->has_mech && c->chem_kernel == LBM_CHEM_SPECIALIZED && !c->chem_fn) return false;
+  if (c->has_mech && !c->has_ct && c->chem_kernel == LBM_CHEM_SPECIALIZED && !c->chem_fn) return false;
   return true;
 }
 
@@ -656,6 +676,7 @@ int lbm_set_mechanism(lbm_ctx *c, const lbm_mechanism *mech) {
   if (c->steps_done) return fail(c, LBM_ESTATE, "lbm_set_mechanism after the first step");
   if (!mech) {
     c->has_mech = 0;
+    c->has_ct = 0;
     c->K = 0;
     c->esrc = 0;
     return LBM_OK;
@@ -685,6 +706,7 @@ int lbm_set_mechanism(lbm_ctx *c, const lbm_mechanism *mech) {
     tab.a_k[k] = phase[k] ? mech->a_s2 : mech->a_s;
   }
   tab.l_tpb = mech->l_tpb;
+  bool has_ct = false;
   for (int r = 0; r < R; ++r) {
     int site[2][2] = {{0, 0}, {0, 0}};           // [phase][forward, backward]
     bool gas = false, ph_in[2] = {false, false};
@@ -726,6 +748,16 @@ int lbm_set_mechanism(lbm_ctx *c, const lbm_mechanism *mech) {
     }
     if (!hom && !edge && ph_in[0] && ph_in[1])
       return fail(c, LBM_EINVAL, "surface reaction %d spans two phases (mark it as an edge reaction)", r);
+    const int z = mech->charge_z ? mech->charge_z[r] : 0;
+    if (z) {                          // charge transfer at the TPB
+      if (!edge) return fail(c, LBM_EINVAL, "charge-transfer reaction %d must be a TPB edge reaction", r);
+      if (z < -4 || z > 4) return fail(c, LBM_EINVAL, "reaction %d: charge_z must lie in -4..4", r);
+      if (!mech->beta_ct || !(mech->beta_ct[r] >= 0.0 && mech->beta_ct[r] <= 1.0))
+        return fail(c, LBM_EINVAL, "reaction %d: symmetry factor beta_ct must lie in [0, 1]", r);
+      tab.beta_ct[r] = mech->beta_ct[r];
+      has_ct = true;
+    }
+    tab.charge_z[r] = (int8_t)z;
     tab.kind[r] = (int8_t)(hom ? 1 : (edge ? 2 : 0));
     tab.w_r[r] = ph_in[1] && !ph_in[0] ? mech->a_s2 : mech->a_s;
     if (!std::isfinite(mech->A_f[r]) || !std::isfinite(mech->A_b[r]) || !std::isfinite(mech->Ea_f[r]) ||
@@ -787,8 +819,65 @@ int lbm_set_mechanism(lbm_ctx *c, const lbm_mechanism *mech) {
     }
     c->esrc = 1;
   }
+  if (has_ct && !c->iv) {
+    const int rc3 = dalloc(c, &c->iv, c->N);
+    if (rc3) return rc3;
+    HIPCHK(c, hipMemset(c->iv, 0, sizeof(double) * c->N));
+  }
+  c->has_ct = has_ct ? 1 : 0;
   c->K = K;
   c->has_mech = 1;
+  return LBM_OK;
+}
+
+int lbm_set_electrode(lbm_ctx *c, double phi_electrode, const double *omega) {
+  if (!c) return LBM_EINVAL;
+  drop_graph(c);                // captured steps hold the electrode potential
+  if (!omega) {
+    c->electrode = 0;
+    return LBM_OK;
+  }
+  if (c->colflag) return fail(c, LBM_EINVAL, "charge transport needs a regular grid, not packed columns");
+  if (!std::isfinite(phi_electrode)) return fail(c, LBM_EINVAL, "electrode potential must be finite");
+  for (int x = 0; x < c->nx; ++x)
+    if (!std::isfinite(omega[x]) || omega[x] < 0.0)
+      return fail(c, LBM_EINVAL, "resistivity omega[%d] must be finite and >= 0", x);
+  if (!c->pel) {
+    double **bufs[] = {&c->ia, &c->pel};
+    for (double **b : bufs) {
+      const int rc = dalloc(c, b, c->N);
+      if (rc) return rc;
+      HIPCHK(c, hipMemset(*b, 0, sizeof(double) * c->N));
+    }
+    const int rc = dalloc(c, &c->omega_x, c->nx);
+    if (rc) return rc;
+  }
+  if (!c->iv) {
+    const int rc = dalloc(c, &c->iv, c->N);
+    if (rc) return rc;
+    HIPCHK(c, hipMemset(c->iv, 0, sizeof(double) * c->N));
+  }
+  HIPCHK(c, hipMemcpy(c->omega_x, omega, sizeof(double) * c->nx, hipMemcpyHostToDevice));
+  c->phi_ed = phi_electrode;
+  c->electrode = 1;
+  return LBM_OK;
+}
+
+int lbm_get_charge(lbm_ctx *c, double *iv, double *ia, double *phi_el) {
+  if (!c) return LBM_EINVAL;
+  if (!c->has_ct && !c->electrode)
+    return fail(c, LBM_ESTATE, "no charge-transfer mechanism and no electrode installed");
+  HIPCHK(c, c->stream ? hipStreamSynchronize(c->stream) : hipDeviceSynchronize());
+  const size_t bytes = sizeof(double) * c->N;
+  double *outs[] = {iv, ia, phi_el};
+  const double *srcs[] = {c->iv, c->ia, c->pel};
+  for (int k = 0; k < 3; ++k) {
+    if (!outs[k]) continue;
+    if (srcs[k])
+      HIPCHK(c, hipMemcpy(outs[k], srcs[k], bytes, hipMemcpyDeviceToHost));
+    else
+      memset(outs[k], 0, bytes);
+  }
   return LBM_OK;
 }
 
@@ -841,7 +930,8 @@ int lbm_step(lbm_ctx *c, int64_t n_steps) {
   const int64_t first_timed = n_steps > kTimingRing ? n_steps - kTimingRing : 0;
   int slot = 0;
   for (int64_t s = 0; s < n_steps;) {
-    if (c->has_mech && c->chem_kernel == LBM_CHEM_SPECIALIZED && !c->chem_fn && c->steps_done >= 1) {
+    if (c->has_mech && !c->has_ct && c->chem_kernel == LBM_CHEM_SPECIALIZED && !c->chem_fn &&
+        c->steps_done >= 1) {
       const int rc = specialize_chemistry(c);   // after the first step (generic kernel)
       if (rc) return rc;
     }
@@ -1131,6 +1221,7 @@ constexpr uint64_t kMagic = 0x324d424c5844ull;
 
 int lbm_save(lbm_ctx *c, void *buf, size_t *size) {
   if (!c || !size) return LBM_EINVAL;
+  if (c->electrode) return fail(c, LBM_ESTATE, "snapshots do not hold the electrode state");
   const size_t N = c->N, D = c->dim, M = c->M;
   const size_t npop = pop_words(c);
   const size_t nrec = (size_t)kRec * N + (c->energy ? N : 0) + (c->has_mech ? (size_t)c->K * N : 0);
@@ -1214,7 +1305,8 @@ void lbm_destroy(lbm_ctx *c) {
   else (void)hipDeviceSynchronize();
   if (c->timing) lbm_set_timing(c, 0);
   double *bufs[] = {c->pop[0], c->pop[1], c->phi, c->kfac, c->Tfield, c->X0, c->Plat, c->rA, c->rRT, c->rFk,
-                    c->rrho, c->rY, c->rqd, c->rec[0], c->rec[1], c->T[0], c->T[1], c->srcsum, c->theta, c->rEs, c->faradaic, c->macro, c->partials};
+                    c->rrho, c->rY, c->rqd, c->rec[0], c->rec[1], c->T[0], c->T[1], c->srcsum, c->theta, c->rEs, c->faradaic, c->macro, c->partials,
+                    c->iv, c->ia, c->pel, c->omega_x};
   for (double *b : bufs) dfree(b);
   dfree(c->colflag);
   dfree(c->chem_tab);

@@ -84,7 +84,9 @@ struct ChemTables {
   double w_r[LBM_RMAX];
   double gam_k[LBM_KMAX], a_k[LBM_KMAX];   // site density and area of species k's phase
   double l_tpb;
+  double beta_ct[LBM_RMAX];      // symmetry factor of a charge-transfer reaction
   int8_t kind[LBM_RMAX];         // 0 surface, 1 homogeneous gas-phase, 2 TPB edge
+  int8_t charge_z[LBM_RMAX];     // electrons the forward direction releases into the electrode
 };
 
 struct ChemParams {
@@ -101,6 +103,20 @@ struct ChemParams {
   double *theta;            // [K][N] in place
   double *rec;              // node records of this step: source written to plane kRecSrc + a
   double *srcsum;           // [N]
+  // charge transfer: dPhi = phi_ed - pel[n] (pel NULL: dPhi = 0); iv [N] receives the
+  // volumetric current (NULL: the mechanism has no charge-transfer reaction)
+  const double *pel;
+  double phi_ed, F_C;
+  double *iv;
+};
+
+// 1-D charge transport along x on every (y, z) line of a regular grid.
+struct ChargeParams {
+  int nx, lines;
+  double dx;                // m
+  const double *iv;         // [N] A/m^3
+  const double *omega;      // [nx] Ohm m
+  double *ia, *pel;         // [N] A/m^2, V
 };
 
 struct InitParams {
@@ -140,6 +156,7 @@ hipError_t launch_init(int dim, const InitParams &ip, hipStream_t s);
 hipError_t launch_species(int dim, const KParams &p, hipStream_t s);
 hipError_t launch_mixture(int dim, const KParams &p, hipStream_t s);
 hipError_t launch_chem(const ChemParams &cp, hipStream_t s);
+hipError_t launch_charge(const ChargeParams &q, hipStream_t s);
 hipError_t launch_surface_energy(const KParams &p, hipStream_t s);
 hipError_t launch_moments(int dim, const KParams &p, double *out, hipStream_t s);
 hipError_t launch_diag(int dim, int L, int Mmom, const KParams &p, const void *pop, double *partials,

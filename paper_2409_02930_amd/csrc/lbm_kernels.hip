@@ -1013,10 +1013,20 @@ void k_chem(const ChemParams cp) {
   const double h = cp.dt / cp.n_sub;
   const double inv_RT = 1.0 / (cp.R_U * T);
   const ChemTables *__restrict__ tb = cp.tab;
+  // charge transfer: z F dPhi / (R_U T) with dPhi = Phi_electrode - Phi_electrolyte
+  const double fpot = cp.pel ? cp.F_C * (cp.phi_ed - cp.pel[n]) * inv_RT : 0.0;
   for (int r = 0; r < cp.R; ++r) {
-    s_k[2 * r][lane] = tb->A_f[r] * exp(-tb->Ea_f[r] * inv_RT);
-    s_k[2 * r + 1][lane] = tb->A_b[r] * exp(-tb->Ea_b[r] * inv_RT);
+    double kf = tb->A_f[r] * exp(-tb->Ea_f[r] * inv_RT);
+    double kb = tb->A_b[r] * exp(-tb->Ea_b[r] * inv_RT);
+    const int z = tb->charge_z[r];
+    if (z) {                    // Butler-Volmer factors of the mass-action constants
+      kf *= exp(tb->beta_ct[r] * z * fpot);
+      kb *= exp(-(1.0 - tb->beta_ct[r]) * z * fpot);
+    }
+    s_k[2 * r][lane] = kf;
+    s_k[2 * r + 1][lane] = kb;
   }
+  double iv = 0.0;              // charge released per unit volume over the step / dt
   double gk[K];                 // site density of each coverage's surface phase
 #pragma unroll
   for (int k = 0; k < K; ++k) gk[k] = tb->gam_k[k];
@@ -1121,10 +1131,12 @@ void k_chem(const ChemParams cp) {
     double dn[S];                 // gas: mol per m^3 of REV; coverages: mol per m^2 of their surface
 #pragma unroll
     for (int u = 0; u < S; ++u) dn[u] = 0.0;
+    double ze = 0.0;              // sum_r z_r xi_r: electrons per unit TPB length
     for (int r = 0; r < cp.R; ++r) {
       const NuRow NF = load_nu(tb->nu_f[r]), NB = load_nu(tb->nu_b[r]);
       const int kind = tb->kind[r];
       const double dxi = h * mass_action<S>(NF, NB, s_k[2 * r][lane], s_k[2 * r + 1][lane], C, nullptr);
+      ze += tb->charge_z[r] * dxi;
       const double wgas = kind == 1 ? phi : tb->w_r[r];
 #pragma unroll
       for (int u = 0; u < S; ++u) {
@@ -1140,7 +1152,9 @@ void k_chem(const ChemParams cp) {
       y0[a] += dn[a] / phi;
       src[a] += dn[a] * cp.m[a] / cp.rho_unit;
     }
+    iv += cp.F_C * tb->l_tpb * ze / cp.dt;   // eq volumetricCurrent
   }
+  if (cp.iv) cp.iv[n] = iv;
   if (cp.faradaic) {
     const double r = cp.faradaic[n] * cp.dt;
 #pragma unroll
@@ -1404,6 +1418,26 @@ int chem_supported(int M, int K) {
 
 hipError_t launch_surface_energy(const KParams &p, hipStream_t s) {
   hipLaunchKernelGGL(k_surface_energy, dim3((p.N + 255) / 256), dim3(256), 0, s, p);
+  return hipGetLastError();
+}
+
+// eqs areaCurrentDensity and electrolytePotential: one lane per (y, z) line walks x,
+// I^(a) and Phi_electrolyte accumulated cell by cell from x = 0 (Phi = 0 before it).
+__global__ __launch_bounds__(256) void k_charge(const ChargeParams q) {
+  const int line = blockIdx.x * blockDim.x + threadIdx.x;
+  if (line >= q.lines) return;
+  const size_t base = (size_t)line * q.nx;
+  double ia = 0.0, pel = 0.0;
+  for (int x = 0; x < q.nx; ++x) {
+    ia += q.iv[base + x] * q.dx;
+    pel += ia * q.omega[x] * q.dx;
+    q.ia[base + x] = ia;
+    q.pel[base + x] = pel;
+  }
+}
+
+hipError_t launch_charge(const ChargeParams &q, hipStream_t s) {
+  hipLaunchKernelGGL(k_charge, dim3((q.lines + 255) / 256), dim3(256), 0, s, q);
   return hipGetLastError();
 }
 

@@ -55,7 +55,7 @@ class lbm_mechanism(C.Structure):
         ("A_b", _dp), ("Ea_b", _dp), ("gamma", C.c_double), ("a_s", C.c_double),
         ("surf_mass", _dp), ("theta0", _dp), ("surf_cv", _dp), ("surf_u_form", _dp),
         ("homogeneous", _ip), ("surface_phase", _ip), ("gamma2", C.c_double), ("a_s2", C.c_double),
-        ("edge", _ip), ("l_tpb", C.c_double),
+        ("edge", _ip), ("l_tpb", C.c_double), ("charge_z", _ip), ("beta_ct", _dp),
     ]
 
 
@@ -85,6 +85,8 @@ def _load():
         "lbm_set_mechanism": ([vp, C.POINTER(lbm_mechanism)], C.c_int),
         "lbm_set_faradaic_source": ([vp, _dp, C.c_int32, C.c_int32], C.c_int),
         "lbm_set_chem_kernel": ([vp, C.c_int32], C.c_int),
+        "lbm_set_electrode": ([vp, C.c_double, _dp], C.c_int),
+        "lbm_get_charge": ([vp, _dp, _dp, _dp], C.c_int),
         "lbm_step": ([vp, C.c_int64], C.c_int),
         "lbm_set_graph": ([vp, C.c_int32], C.c_int),
         "lbm_adjoint_outlet_flux": ([vp, C.c_int64, C.c_int32, _dp, vp, _dp, C.c_int32], C.c_int),
@@ -108,7 +110,7 @@ def _load():
 _lib = _load()
 
 EXPORTED = ["lbm_init", "lbm_init_columns", "lbm_set_porous_field", "lbm_set_mechanism",
-            "lbm_set_chem_kernel", "lbm_set_faradaic_source", "lbm_step", "lbm_set_graph", "lbm_adjoint_outlet_flux", "lbm_moments", "lbm_moment_rows",
+            "lbm_set_chem_kernel", "lbm_set_faradaic_source", "lbm_set_electrode", "lbm_get_charge", "lbm_step", "lbm_set_graph", "lbm_adjoint_outlet_flux", "lbm_moments", "lbm_moment_rows",
             "lbm_get_diagnostics", "lbm_set_timing", "lbm_get_timing", "lbm_save", "lbm_load",
             "lbm_last_error", "lbm_destroy"]
 
@@ -196,7 +198,7 @@ class Lattice:
     def set_mechanism(self, mech):
         """mech: object with K, nu_f, nu_b, A_f, Ea_f, A_b, Ea_b, gamma, a_s, surf_mass, theta0,
         n_sub, n_newton and optionally surf_cv, surf_u_form, homogeneous, surface_phase,
-        gamma2, a_s2, edge, l_tpb (None removes the mechanism)."""
+        gamma2, a_s2, edge, l_tpb, charge_z, beta_ct (None removes the mechanism)."""
         if mech is None:
             self._check(_lib.lbm_set_mechanism(self.ctx, None))
             self.K = 0
@@ -208,7 +210,9 @@ class Lattice:
                     surf_u_form=_arr(getattr(mech, "surf_u_form", None)),
                     homogeneous=_arr(getattr(mech, "homogeneous", None), np.int32),
                     surface_phase=_arr(getattr(mech, "surface_phase", None), np.int32),
-                    edge=_arr(getattr(mech, "edge", None), np.int32))
+                    edge=_arr(getattr(mech, "edge", None), np.int32),
+                    charge_z=_arr(getattr(mech, "charge_z", None), np.int32),
+                    beta_ct=_arr(getattr(mech, "beta_ct", None)))
         st = lbm_mechanism()
         st.n_surface = int(mech.K)
         st.n_reactions = int(np.asarray(mech.nu_f).shape[0])
@@ -218,6 +222,8 @@ class Lattice:
         st.homogeneous = _ptr(keep["homogeneous"], C.c_int32)
         st.surface_phase = _ptr(keep["surface_phase"], C.c_int32)
         st.edge = _ptr(keep["edge"], C.c_int32)
+        st.charge_z = _ptr(keep["charge_z"], C.c_int32)
+        st.beta_ct = _ptr(keep["beta_ct"])
         st.gamma2 = float(getattr(mech, "gamma2", 0.0) or 0.0)
         st.a_s2 = float(getattr(mech, "a_s2", 0.0) or 0.0)
         st.l_tpb = float(getattr(mech, "l_tpb", 0.0) or 0.0)
@@ -234,6 +240,18 @@ class Lattice:
     def set_faradaic_source(self, rate, fuel=0, product=1):
         rate = _arr(rate)
         self._check(_lib.lbm_set_faradaic_source(self.ctx, _ptr(rate), int(fuel), int(product)))
+
+    def set_electrode(self, phi_electrode, omega):
+        """Electrode potential (V) and electrolyte resistivity [nx] (Ohm m) of the 1-D charge
+        transport along x; omega None switches it off."""
+        om = _arr(omega)
+        self._check(_lib.lbm_set_electrode(self.ctx, float(phi_electrode), _ptr(om)))
+
+    def charge(self):
+        """(I^(v) A/m^3, I^(a) A/m^2, Phi_electrolyte V) of the last step, host float64 [N] each."""
+        out = [np.empty(self.N) for _ in range(3)]
+        self._check(_lib.lbm_get_charge(self.ctx, *(_ptr(o) for o in out)))
+        return tuple(out)
 
     # -- run -------------------------------------------------------------------
     def step(self, n=1):
@@ -334,6 +352,9 @@ def lattice_from_workload(w, stream=None, col_len=None, precision=FP64) -> Latti
         lat.set_faradaic_source(w.faradaic_rate, *w.faradaic_species)
     if w.mech is not None:
         lat.set_mechanism(w.mech)
+    el = getattr(w, "electrode", None)
+    if el is not None:
+        lat.set_electrode(el["phi_ed"], el["omega"])
     return lat
 
 

@@ -1,0 +1,153 @@
+"""Charge transfer at the TPB and 1-D charge transport (Sections 4.1-4.2): the HIP path
+against the FP64 oracle on the same seeded inputs, through the C ABI.
+
+Fields, coverages and the three charge outputs (volumetric current I^(v), area current
+density I^(a), electrolyte potential) are compared with the normwise relative error
+max |gpu - oracle| / max |oracle| <= 1e-11, the bar of the other parity tests: both sides
+are FP64 and differ by rounding order, FMA contraction and libm ulps only.
+"""
+import sys
+from dataclasses import replace
+
+import numpy as np
+import pytest
+
+from oracle.lbm_oracle import Oracle
+from workloads import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-11
+FLOOR = {"u": 1e-3, "j_a": 1e-2}
+KEYS = ("rho_a", "u", "T", "P", "j_a", "X", "rho", "theta")
+
+
+@pytest.fixture(scope="module")
+def lbm():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2409_02930_amd import lbm as _lbm
+    return _lbm
+
+
+def _log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _err(g, r, floor=0.0):
+    g = np.asarray(g, dtype=np.float64).reshape(-1)
+    r = np.asarray(r, dtype=np.float64).reshape(-1)
+    assert g.shape == r.shape
+    assert np.all(np.isfinite(g))
+    scale = max(float(np.max(np.abs(r))), floor)
+    return 0.0 if scale == 0 else float(np.max(np.abs(g - r)) / scale)
+
+
+def _check(lat, o):
+    got = lat.fields()
+    ref = o.moments()
+    errs = {k: _err(got[k], ref[k], FLOOR.get(k, 0.0)) for k in KEYS}
+    iv, ia, pel = lat.charge()
+    errs.update(iv=_err(iv, o.i_v), ia=_err(ia, o.i_a), pel=_err(pel, o.phi_el))
+    bad = {k: e for k, e in errs.items() if not e <= TOL}
+    assert not bad, f"normwise errors above {TOL}: {bad} (all: {errs})"
+    return errs
+
+
+CASES = {
+    "transfer_only_12x2": lambda: synth.electrode_slab(nx=12, ny=2, with_gas=False),
+    "adsorption_transfer_desorption_37x3": lambda: synth.electrode_slab(nx=37, ny=3, omega=1.0e-3),
+    "z2_beta03_anodic_24x1": lambda: _z2(synth.electrode_slab(nx=24, ny=1, beta=0.3, phi_ed=0.08,
+                                                              omega=2.0e-3)),
+}
+
+
+def _z2(w):
+    w.mech.charge_z = np.array([2, 0, 0], dtype=np.int32)
+    return w
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_charge_transfer_and_transport_match_oracle(lbm, case):
+    """Butler-Volmer charge transfer on the TPB edge, the volumetric current and its
+    integration along x into I^(a) and Phi_electrolyte, coupled back into the next
+    step's rates, over 30 steps."""
+    w = CASES[case]()
+    _log(f"case {case} N={w.N}")
+    lat = lbm.lattice_from_workload(w)
+    o = Oracle(w)
+    for chunk in (1, 9, 20):
+        lat.step(chunk)
+        o.step(chunk)
+        _check(lat, o)
+    assert np.max(np.abs(o.phi_el)) > 1e-3          # the coupling is exercised
+    lat.close()
+
+
+def test_potential_sweep_between_steps_and_graph_replay(lbm):
+    """The electrode potential changed between steps (a polarisation sweep) and the same run
+    replayed through the captured step graph: both match the oracle, which updates
+    dPhi = Phi_electrode - Phi_electrolyte at the new potential."""
+    import torch
+    stream = torch.cuda.Stream()
+    w = synth.electrode_slab(nx=16, ny=2, omega=2.0e-3)
+    om = w.electrode["omega"]
+    o = Oracle(w)
+    lats = [lbm.lattice_from_workload(w, stream=stream.cuda_stream) for _ in range(2)]
+    lats[1].set_graph(4)
+    for ph in (0.05, 0.02, 0.09):
+        _log(f"phi_ed {ph}")
+        o.electrode["phi_ed"] = ph
+        o.dphi = ph - o.phi_el
+        o.step(9)
+        for lat in lats:
+            lat.set_electrode(ph, om)
+            lat.step(9)
+            _check(lat, o)
+        plain, graph = lats[0].charge(), lats[1].charge()
+        for a, b in zip(plain, graph):                 # graph replay: bitwise the plain launches
+            assert np.array_equal(a, b)
+    for lat in lats:
+        lat.close()
+
+
+def test_charge_transfer_without_electrode_has_zero_potential(lbm):
+    """Charge-transfer reactions with no electrode installed: dPhi = 0 in the rates, the
+    current is still reported, I^(a) and the potential are zero."""
+    w = synth.electrode_slab(nx=10, ny=2)
+    w.electrode = None
+    o = Oracle(w)
+    lat = lbm.lattice_from_workload(w)
+    o.step(5)
+    lat.step(5)
+    got = lat.fields()
+    ref = o.moments()
+    for k in KEYS:
+        assert _err(got[k], ref[k], FLOOR.get(k, 0.0)) <= TOL, k
+    iv, ia, pel = lat.charge()
+    assert _err(iv, o._iv) <= TOL
+    assert np.all(ia == 0.0) and np.all(pel == 0.0)
+    lat.close()
+
+
+def test_charge_transfer_validation(lbm):
+    """Host validation: charge only on TPB edge reactions, beta_ct in [0, 1] and required,
+    no charge transport on packed columns, no snapshot while the electrode is on."""
+    w = synth.electrode_slab(nx=6, ny=2)
+    bad = [replace(w.mech, charge_z=np.array([0, 1, 0], dtype=np.int32)),     # a surface reaction
+           replace(w.mech, beta_ct=np.array([1.5, 0.5, 0.5])),
+           replace(w.mech, beta_ct=None)]
+    for m in bad:
+        lat = lbm.lattice_from_workload(replace(w, mech=None, electrode=None))
+        with pytest.raises(lbm.LBMError):
+            lat.set_mechanism(m)
+        lat.close()
+    lat = lbm.lattice_from_workload(w)
+    with pytest.raises(lbm.LBMError):
+        lat.save()
+    with pytest.raises(lbm.LBMError):
+        lat.set_electrode(0.1, np.full(w.nx, -1.0))
+    lat.set_electrode(0.0, None)                      # off again: snapshots allowed
+    lat.save()
+    lat.close()
