@@ -198,18 +198,20 @@ int lbm_set_chem_kernel(lbm_ctx *ctx, int32_t kind);
  * chemistry source; NULL removes it).  Only valid before the first lbm_step. */
 int lbm_set_faradaic_source(lbm_ctx *ctx, const double *rate, int32_t fuel, int32_t product);
 
-/* Electrode coupling and 1-D charge transport along x (Section 4.2, eqs areaCurrentDensity,
- * electrolytePotential).  phi_electrode: potential of the electrode phase, V (spatially
- * constant, eq electrodePotential); omega: host [nx] electrolyte resistivity in Ohm m,
- * copied; NULL switches the coupling off.  Regular grids only (LBM_EINVAL for packed
- * columns).  After each step's chemistry the library integrates, on every (y, z) line from
- * x = 0 cell by cell (rectangle rule, Phi_electrolyte = 0 before the first cell),
- * I^(a)(x) = sum I^(v) dx and Phi_electrolyte(x) = sum I^(a) Omega dx; the next step's
- * charge-transfer rates see dPhi = phi_electrode - Phi_electrolyte(x) (dPhi = phi_electrode
- * before the first integration).  May be called between steps (e.g. to sweep the
- * potential); it drops a captured step graph.  The electrode state is not part of
- * snapshots (lbm_save returns LBM_ESTATE while the coupling is on).                       */
-int lbm_set_electrode(lbm_ctx *ctx, double phi_electrode, const double *omega);
+/* Electrode coupling and 1-D charge transport along x (Section 4.2, eqs electrodePotential,
+ * areaCurrentDensity, electrolytePotential).  The x lines are the ny nz rows of a regular
+ * grid (line y + ny z) or the packed columns of lbm_init_columns (in column order).
+ * phi_electrode: host [n_lines] potential of the electrode phase of each line, V (constant
+ * along the line); omega: host [N] electrolyte resistivity at each node, Ohm m (>= 0); both
+ * copied.  phi_electrode NULL switches the coupling off.  After each step's chemistry the
+ * library integrates every line from its first node cell by cell (rectangle rule,
+ * Phi_electrolyte = 0 before the first cell): I^(a)(x) = sum I^(v) dx and
+ * Phi_electrolyte(x) = sum I^(a) Omega dx; the next step's charge-transfer rates see
+ * dPhi = phi_electrode - Phi_electrolyte(x) (dPhi = phi_electrode before the first
+ * integration).  May be called between steps (e.g. to sweep the potential: the
+ * electrolyte potential is kept); it drops a captured step graph.  The electrode state is
+ * not part of snapshots (lbm_save returns LBM_ESTATE while the coupling is on).            */
+int lbm_set_electrode(lbm_ctx *ctx, const double *phi_electrode, const double *omega);
 
 /* Copies to host [N] arrays (each may be NULL) the last step's volumetric current I^(v)
  * (A/m^3), area current density I^(a) (A/m^2) and electrolyte potential (V); synchronizes

@@ -65,8 +65,10 @@ struct lbm_ctx {
   int has_mech = 0, has_faradaic = 0;
   int has_ct = 0;                       // the mechanism has charge-transfer reactions
   int electrode = 0;                    // charge transport along x (lbm_set_electrode)
-  double phi_ed = 0.0;                  // electrode potential, V
-  double *iv = nullptr, *ia = nullptr, *pel = nullptr, *omega_x = nullptr;
+  int n_lines = 0;                      // x lines: ny nz rows of a grid, or the packed columns
+  std::vector<int> line_off;            // [n_lines + 1] first node of each line
+  int *d_line_off = nullptr;
+  double *iv = nullptr, *ia = nullptr, *pel = nullptr, *ped = nullptr, *omega_n = nullptr;
   ChemParams chem;
   ChemTables *chem_tab = nullptr;
   ChemTables chem_host;                 // host copy of the installed mechanism
@@ -511,7 +513,7 @@ int enqueue_step(lbm_ctx *c, int record_slot) {
     cp.F_C = kFC;
     cp.iv = c->has_ct ? c->iv : nullptr;
     cp.pel = c->electrode ? c->pel : nullptr;
-    cp.phi_ed = c->phi_ed;
+    cp.ped = c->electrode ? c->ped : nullptr;
     for (int a = 0; a < c->M; ++a) cp.m[a] = c->m[a];
     if (c->chem_fn)
       HIPCHK(c, launch_chem_specialized(c->chem_fn, cp, c->stream));
@@ -520,11 +522,11 @@ int enqueue_step(lbm_ctx *c, int record_slot) {
   }
   if (c->electrode) {           // the next step's rates see the potentials of this step's currents
     ChargeParams q;
-    q.nx = c->nx;
-    q.lines = c->ny * c->nz;
+    q.lines = c->n_lines;
+    q.off = c->d_line_off;
     q.dx = c->dx;
     q.iv = c->iv;
-    q.omega = c->omega_x;
+    q.omega = c->omega_n;
     q.ia = c->ia;
     q.pel = c->pel;
     HIPCHK(c, launch_charge(q, c->stream));
@@ -632,6 +634,8 @@ int lbm_init_columns(const lbm_config *cfg, int32_t n_cols, const int32_t *col_l
   c->nx = (int)N;
   c->ny = c->nz = 1;
   c->n_cols = n_cols;
+  c->line_off.assign(n_cols + 1, 0);
+  for (int k = 0; k < n_cols; ++k) c->line_off[k + 1] = c->line_off[k] + col_len[k];
   rc = common_init(cfg, (int)N, X0, P0, T0, c);
   if (rc) return rc;
   std::vector<int8_t> flag(N, 0);
@@ -830,35 +834,47 @@ int lbm_set_mechanism(lbm_ctx *c, const lbm_mechanism *mech) {
   return LBM_OK;
 }
 
-int lbm_set_electrode(lbm_ctx *c, double phi_electrode, const double *omega) {
+int lbm_set_electrode(lbm_ctx *c, const double *phi_electrode, const double *omega) {
   if (!c) return LBM_EINVAL;
-  drop_graph(c);                // captured steps hold the electrode potential
-  if (!omega) {
+  drop_graph(c);                // captured steps read the electrode arrays of their set-up
+  if (!phi_electrode) {
     c->electrode = 0;
     return LBM_OK;
   }
-  if (c->colflag) return fail(c, LBM_EINVAL, "charge transport needs a regular grid, not packed columns");
-  if (!std::isfinite(phi_electrode)) return fail(c, LBM_EINVAL, "electrode potential must be finite");
-  for (int x = 0; x < c->nx; ++x)
-    if (!std::isfinite(omega[x]) || omega[x] < 0.0)
-      return fail(c, LBM_EINVAL, "resistivity omega[%d] must be finite and >= 0", x);
+  if (!omega) return fail(c, LBM_EINVAL, "omega is required with an electrode potential");
+  if (c->line_off.empty()) {    // regular grid: the ny nz rows along x
+    const int L = c->ny * c->nz;
+    c->line_off.assign(L + 1, 0);
+    for (int l = 0; l < L; ++l) c->line_off[l + 1] = c->line_off[l] + c->nx;
+  }
+  const int L = (int)c->line_off.size() - 1;
+  for (int l = 0; l < L; ++l)
+    if (!std::isfinite(phi_electrode[l])) return fail(c, LBM_EINVAL, "electrode potential of line %d not finite", l);
+  for (int n = 0; n < c->N; ++n)
+    if (!std::isfinite(omega[n]) || omega[n] < 0.0)
+      return fail(c, LBM_EINVAL, "resistivity omega[%d] must be finite and >= 0", n);
   if (!c->pel) {
-    double **bufs[] = {&c->ia, &c->pel};
+    double **bufs[] = {&c->ia, &c->pel, &c->ped, &c->omega_n};
     for (double **b : bufs) {
       const int rc = dalloc(c, b, c->N);
       if (rc) return rc;
       HIPCHK(c, hipMemset(*b, 0, sizeof(double) * c->N));
     }
-    const int rc = dalloc(c, &c->omega_x, c->nx);
-    if (rc) return rc;
+    const hipError_t e = hipMalloc((void **)&c->d_line_off, sizeof(int) * (L + 1));
+    if (e != hipSuccess) return fail(c, LBM_ENOMEM, "hipMalloc line offsets");
+    HIPCHK(c, hipMemcpy(c->d_line_off, c->line_off.data(), sizeof(int) * (L + 1), hipMemcpyHostToDevice));
+    c->n_lines = L;
   }
   if (!c->iv) {
     const int rc = dalloc(c, &c->iv, c->N);
     if (rc) return rc;
     HIPCHK(c, hipMemset(c->iv, 0, sizeof(double) * c->N));
   }
-  HIPCHK(c, hipMemcpy(c->omega_x, omega, sizeof(double) * c->nx, hipMemcpyHostToDevice));
-  c->phi_ed = phi_electrode;
+  std::vector<double> ped(c->N);
+  for (int l = 0; l < L; ++l)
+    for (int n = c->line_off[l]; n < c->line_off[l + 1]; ++n) ped[n] = phi_electrode[l];
+  HIPCHK(c, hipMemcpy(c->ped, ped.data(), sizeof(double) * c->N, hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(c->omega_n, omega, sizeof(double) * c->N, hipMemcpyHostToDevice));
   c->electrode = 1;
   return LBM_OK;
 }
@@ -1306,9 +1322,10 @@ void lbm_destroy(lbm_ctx *c) {
   if (c->timing) lbm_set_timing(c, 0);
   double *bufs[] = {c->pop[0], c->pop[1], c->phi, c->kfac, c->Tfield, c->X0, c->Plat, c->rA, c->rRT, c->rFk,
                     c->rrho, c->rY, c->rqd, c->rec[0], c->rec[1], c->T[0], c->T[1], c->srcsum, c->theta, c->rEs, c->faradaic, c->macro, c->partials,
-                    c->iv, c->ia, c->pel, c->omega_x};
+                    c->iv, c->ia, c->pel, c->ped, c->omega_n};
   for (double *b : bufs) dfree(b);
   dfree(c->colflag);
+  dfree(c->d_line_off);
   dfree(c->chem_tab);
   delete c;
 }

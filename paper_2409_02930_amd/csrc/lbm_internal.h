@@ -103,19 +103,22 @@ struct ChemParams {
   double *theta;            // [K][N] in place
   double *rec;              // node records of this step: source written to plane kRecSrc + a
   double *srcsum;           // [N]
-  // charge transfer: dPhi = phi_ed - pel[n] (pel NULL: dPhi = 0); iv [N] receives the
-  // volumetric current (NULL: the mechanism has no charge-transfer reaction)
-  const double *pel;
-  double phi_ed, F_C;
+  // charge transfer: dPhi = ped[n] - pel[n] (electrode minus electrolyte potential; pel
+  // NULL: dPhi = 0); iv [N] receives the volumetric current (NULL: the mechanism has no
+  // charge-transfer reaction)
+  const double *ped, *pel;
+  double F_C;
   double *iv;
 };
 
-// 1-D charge transport along x on every (y, z) line of a regular grid.
+// 1-D charge transport along x: line l holds the nodes off[l] .. off[l + 1] - 1 in x order
+// (an x row of a regular grid or one packed column).
 struct ChargeParams {
-  int nx, lines;
+  int lines;
+  const int *off;           // [lines + 1]
   double dx;                // m
   const double *iv;         // [N] A/m^3
-  const double *omega;      // [nx] Ohm m
+  const double *omega;      // [N] Ohm m
   double *ia, *pel;         // [N] A/m^2, V
 };
 

@@ -1014,7 +1014,7 @@ void k_chem(const ChemParams cp) {
   const double inv_RT = 1.0 / (cp.R_U * T);
   const ChemTables *__restrict__ tb = cp.tab;
   // charge transfer: z F dPhi / (R_U T) with dPhi = Phi_electrode - Phi_electrolyte
-  const double fpot = cp.pel ? cp.F_C * (cp.phi_ed - cp.pel[n]) * inv_RT : 0.0;
+  const double fpot = cp.pel ? cp.F_C * (cp.ped[n] - cp.pel[n]) * inv_RT : 0.0;
   for (int r = 0; r < cp.R; ++r) {
     double kf = tb->A_f[r] * exp(-tb->Ea_f[r] * inv_RT);
     double kb = tb->A_b[r] * exp(-tb->Ea_b[r] * inv_RT);
@@ -1421,18 +1421,19 @@ hipError_t launch_surface_energy(const KParams &p, hipStream_t s) {
   return hipGetLastError();
 }
 
-// eqs areaCurrentDensity and electrolytePotential: one lane per (y, z) line walks x,
-// I^(a) and Phi_electrolyte accumulated cell by cell from x = 0 (Phi = 0 before it).
+// eqs areaCurrentDensity and electrolytePotential: one lane per line walks x, I^(a)
+// and Phi_electrolyte accumulated cell by cell from the line's first node (Phi = 0
+// before it).
 __global__ __launch_bounds__(256) void k_charge(const ChargeParams q) {
   const int line = blockIdx.x * blockDim.x + threadIdx.x;
   if (line >= q.lines) return;
-  const size_t base = (size_t)line * q.nx;
+  const int b = q.off[line], e = q.off[line + 1];
   double ia = 0.0, pel = 0.0;
-  for (int x = 0; x < q.nx; ++x) {
-    ia += q.iv[base + x] * q.dx;
-    pel += ia * q.omega[x] * q.dx;
-    q.ia[base + x] = ia;
-    q.pel[base + x] = pel;
+  for (int n = b; n < e; ++n) {
+    ia += q.iv[n] * q.dx;
+    pel += ia * q.omega[n] * q.dx;
+    q.ia[n] = ia;
+    q.pel[n] = pel;
   }
 }
 

@@ -85,7 +85,7 @@ def _load():
         "lbm_set_mechanism": ([vp, C.POINTER(lbm_mechanism)], C.c_int),
         "lbm_set_faradaic_source": ([vp, _dp, C.c_int32, C.c_int32], C.c_int),
         "lbm_set_chem_kernel": ([vp, C.c_int32], C.c_int),
-        "lbm_set_electrode": ([vp, C.c_double, _dp], C.c_int),
+        "lbm_set_electrode": ([vp, _dp, _dp], C.c_int),
         "lbm_get_charge": ([vp, _dp, _dp, _dp], C.c_int),
         "lbm_step": ([vp, C.c_int64], C.c_int),
         "lbm_set_graph": ([vp, C.c_int32], C.c_int),
@@ -168,6 +168,8 @@ class Lattice:
                                        _ptr(P0), _ptr(T0), C.byref(ctx))
         self.ctx = ctx
         self.M, self.dim = M, dim
+        self.n_lines = ny * nz if col_len is None else int(len(col_len))
+        self.nx = nx
         self.N = int(X0.shape[-1])
         self.K = 0
         self._check(rc)
@@ -242,10 +244,20 @@ class Lattice:
         self._check(_lib.lbm_set_faradaic_source(self.ctx, _ptr(rate), int(fuel), int(product)))
 
     def set_electrode(self, phi_electrode, omega):
-        """Electrode potential (V) and electrolyte resistivity [nx] (Ohm m) of the 1-D charge
-        transport along x; omega None switches it off."""
-        om = _arr(omega)
-        self._check(_lib.lbm_set_electrode(self.ctx, float(phi_electrode), _ptr(om)))
+        """Electrode potential (V; scalar or one per x line) and electrolyte resistivity
+        (Ohm m; [N] per node, or [nx] repeated on every row of a regular grid) of the 1-D
+        charge transport along x; phi_electrode None switches it off."""
+        if phi_electrode is None:
+            self._check(_lib.lbm_set_electrode(self.ctx, None, None))
+            return
+        ped = np.ascontiguousarray(np.broadcast_to(np.asarray(phi_electrode, dtype=np.float64),
+                                                   (self.n_lines,)))
+        om = _arr(omega).reshape(-1)
+        if om.size != self.N:
+            om = np.ascontiguousarray(np.tile(om, self.n_lines))
+        if om.size != self.N:
+            raise ValueError("omega must have N or nx entries")
+        self._check(_lib.lbm_set_electrode(self.ctx, _ptr(ped), _ptr(om)))
 
     def charge(self):
         """(I^(v) A/m^3, I^(a) A/m^2, Phi_electrolyte V) of the last step, host float64 [N] each."""

@@ -148,6 +148,41 @@ def test_charge_transfer_validation(lbm):
         lat.save()
     with pytest.raises(lbm.LBMError):
         lat.set_electrode(0.1, np.full(w.nx, -1.0))
-    lat.set_electrode(0.0, None)                      # off again: snapshots allowed
+    lat.set_electrode(None, None)                     # off again: snapshots allowed
     lat.save()
     lat.close()
+
+
+def test_packed_columns_with_their_own_electrode_potentials(lbm):
+    """Batched ragged D1Q3 cells (packed columns, one launch) with one electrode potential
+    per column and per-node resistivity: each column matches its own oracle run, the charge
+    transport integrating inside each column only."""
+    specs = [(14, 0.35, 0.05), (23, 0.45, 0.02), (9, 0.3, 0.08)]
+    cols = [synth.electrode_slab(nx=L, ny=1, phi=p, phi_ed=e, omega=2.0e-3 * (1 + k), lattice=1)
+            for k, (L, p, e) in enumerate(specs)]
+    cat = lambda k: np.concatenate([getattr(c, k) for c in cols], axis=-1)
+    w0 = cols[0]
+    lengths = [c.nx for c in cols]
+    lat = lbm.Lattice(1, int(sum(lengths)), 1, 1, w0.molar_mass, w0.D_ref_lat, cat("X0"), cat("T0"),
+                      cat("P0"), T_ref=w0.T_ref, bc_lo=w0.bc_lo, bc_hi=w0.bc_hi, col_len=lengths)
+    lat.set_porous_field(cat("phi"), cat("tort"), w0.pore_radius)
+    lat.set_mechanism(w0.mech)
+    lat.set_electrode([c.electrode["phi_ed"] for c in cols],
+                      np.concatenate([c.electrode["omega"] for c in cols]))
+    steps = 20
+    lat.step(steps)
+    got = lat.fields()
+    ch = lat.charge()
+    lat.close()
+    off = 0
+    for c in cols:
+        _log(f"column L={c.nx}")
+        o = Oracle(c)
+        o.step(steps)
+        ref = o.moments()
+        sl = slice(off, off + c.nx)
+        for k in KEYS:
+            assert _err(np.asarray(got[k])[..., sl], ref[k], FLOOR.get(k, 0.0)) <= TOL, k
+        for g, r in zip(ch, (o.i_v, o.i_a, o.phi_el)):
+            assert _err(g[sl], r) <= TOL
+        off += c.nx
