@@ -66,6 +66,15 @@ Readings adopted where the paper is silent, garbled or self-inconsistent
       cells 0..x of each (y, z) line, Phi_electrolyte = 0 before cell 0; a
       step's rates take the potentials integrated from the previous step's
       currents (dPhi = Phi_electrode before the first step).
+  R31 electrical energy source (Section 4.1, eqs for P_elec, P_Omega, U_source):
+      the printed U_source = (-P_Omega + P_elec) dt has both signs reversed
+      against the text that defines the terms (electrical work leaves the
+      fluid, ohmic heat enters it); taken as U_source = (P_Omega - P_elec) dt
+      with P_elec = |dPhi| I^(v), P_Omega = (a_electrolyte / l_TPB) I^(v)^2
+      Omega dx, a_electrolyte the specific area of the second surface phase,
+      dPhi and I^(v) those of the step's chemistry.  It enters the unified
+      internal energy before the adsorbed phases are subtracted (eq
+      InternalEnergyCell_PC), so only with the energy lattice on.
 """
 from __future__ import annotations
 
@@ -469,6 +478,15 @@ class Oracle:
         self._iv = iv
         return src.T.copy(), th.T.copy()
 
+    def electric_energy_source(self, iv):
+        """U_source of R31 per node in lattice energy-density units."""
+        mech = self.mech
+        om = np.asarray(self.electrode["omega"], dtype=np.float64)
+        om = np.tile(om, self.N // om.size) if om.size != self.N else om
+        p_elec = np.abs(self.dphi) * iv                                                  # W/m^3
+        p_om = (mech.a_s2 / mech.l_tpb) * iv * iv * om * self.w.dx                        # W/m^3
+        return (p_om - p_elec) * self.dt / (self.rho_unit * self.c2)
+
     def charge_transport(self, iv):
         """eqs areaCurrentDensity and electrolytePotential along x (R30): the area current
         density I^(a) and the electrolyte potential of every node from the volumetric
@@ -602,6 +620,9 @@ class Oracle:
                 # g^eq,source is g^eq with (rho^pc, U^pc), pre-collision v and RT.
                 phirho_pc = phi * rho + src.sum(axis=0)
                 dEs = self.surface_energy(self.theta, T) - self.surface_energy(theta_new, T)
+                if (self.electrode is not None and self.mech is not None
+                        and getattr(self.mech, "charge_z", None) is not None):
+                    dEs = dEs + self.electric_energy_source(self._iv)                   # R31
                 U_pc = (phi * rho * Umix + dEs) / phirho_pc
                 new_g = new_g + (self.g_equilibrium(phirho_pc, U_pc, RT, v) - geq)
         else:

@@ -639,3 +639,30 @@ def test_charge_transport_closed_form_for_uniform_current():
     dx = w.dx
     assert np.allclose(ia, (i + 1) * I * dx, rtol=1e-13, atol=0)
     assert np.allclose(pel, 0.25 * I * dx * dx * (i + 1) * (i + 2) / 2, rtol=1e-13, atol=0)
+
+
+def test_electrical_energy_source_enters_the_energy_total():
+    """R31 with eqs InternalEnergyCell_PC, g0mom_source, g_source: over one step from rest
+    (bounce-back ends and periodic y keep sum g, no adsorbed-phase thermo, no gas
+    reaction) the energy lattice total changes by exactly the electrical source: minus
+    the electrical work |dPhi| I^(v) dt when the electrolyte has no resistance, and the
+    ohmic heat (a_electrolyte / l_TPB) I^(v)^2 Omega dx dt on top when it has one, both
+    rebuilt here from the step's current (the charge balance pins I^(v))."""
+    for omega in (0.0, 40.0):
+        w = synth.electrode_slab(nx=8, ny=2, energy=True, with_gas=False, omega=omega, phi_ed=0.05)
+        o = lo.Oracle(w)
+        g0 = o.g.sum()
+        dphi = o.dphi.copy()
+        o.step(1)
+        iv = o.i_v
+        m = w.mech
+        work = np.abs(dphi) * iv * o.dt
+        heat = (m.a_s2 / m.l_tpb) * iv ** 2 * omega * w.dx * o.dt
+        expect = (heat - work).sum() / (o.rho_unit * o.c2)
+        dg = o.g.sum() - g0
+        assert np.all(iv > 0)
+        assert abs(dg - expect) <= 1e-9 * abs(expect), (omega, dg, expect)
+        if omega == 0.0:
+            assert dg < 0                                         # work leaves the fluid
+        else:
+            assert heat.sum() > work.sum() and dg > 0             # ohmic heating wins here

@@ -384,14 +384,22 @@ def two_phase_tpb(nx: int = 6, ny: int = 4, phi: float = 0.4, theta_a1: float = 
 
 def electrode_slab(nx: int = 12, ny: int = 2, phi_ed: float = 0.05, omega: float = 5.0e-3,
                    beta: float = 0.5, with_gas: bool = True, kf: float = 3.0e3,
-                   kb: float = 1.0e3, phi: float = 0.4, lattice: int = 2) -> Workload:
+                   kb: float = 1.0e3, phi: float = 0.4, lattice: int = 2,
+                   energy: bool = False) -> Workload:
     """The two-phase TPB mechanism of two_phase_tpb with its edge reaction as a
     charge transfer (A1 + V2 <=> A2 + V1 + e-, one electron into the electrode,
     symmetry factor beta), on a D2Q9 slab periodic in y and bounce-back at both
     x ends; electrode potential phi_ed (V) and a uniform electrolyte resistivity
-    omega (Ohm m) along x.  lattice=1 with ny=1 gives the same cell as a D1Q3 column."""
+    omega (Ohm m) along x.  lattice=1 with ny=1 gives the same cell as a D1Q3 column.
+    energy turns the energy lattice on (gas cv_a = (5/2) R_U / m_a, u_form 0, no
+    adsorbed-phase thermo), so the electrical energy source acts on the temperature."""
     w = two_phase_tpb(nx=nx, ny=ny, phi=phi, with_gas=with_gas, kf=kf, kb=kb)
     w.lattice = lattice
+    if energy:
+        m = np.asarray(w.molar_mass)
+        w.energy_on = True
+        w.cv = 2.5 * 8.314462618 / m
+        w.u_form = np.zeros(len(m))
     R = w.mech.R
     z = np.zeros(R, dtype=np.int32)
     z[0] = 1
