@@ -69,6 +69,8 @@ struct lbm_ctx {
   std::vector<int> line_off;            // [n_lines + 1] first node of each line
   int *d_line_off = nullptr;
   double *iv = nullptr, *ia = nullptr, *pel = nullptr, *ped = nullptr, *omega_n = nullptr;
+  double *uel = nullptr;                // [N] electrical energy source (energy lattice on)
+  double a_el = 0.0;                    // specific area of the electrolyte (second) surface phase
   ChemParams chem;
   ChemTables *chem_tab = nullptr;
   ChemTables chem_host;                 // host copy of the installed mechanism
@@ -490,6 +492,8 @@ int enqueue_step(lbm_ctx *c, int record_slot) {
   p.T_prev = c->energy ? c->T[1 - q] : c->Tfield;
   p.T_cur = c->energy ? c->T[q] : nullptr;
   p.srcsum_cur = c->srcsum;
+  const bool elec_energy = c->energy && c->electrode && c->has_ct;
+  p.uel = elec_energy ? c->uel : nullptr;
   hipEvent_t *ev = record_slot >= 0 ? c->ev[record_slot] : nullptr;
   if (ev) HIPCHK(c, hipEventRecord(ev[0], c->stream));
   HIPCHK(c, launch_species(c->dim, p, c->stream));
@@ -514,6 +518,11 @@ int enqueue_step(lbm_ctx *c, int record_slot) {
     cp.iv = c->has_ct ? c->iv : nullptr;
     cp.pel = c->electrode ? c->pel : nullptr;
     cp.ped = c->electrode ? c->ped : nullptr;
+    cp.uel = elec_energy ? c->uel : nullptr;
+    cp.omega = c->omega_n;
+    cp.a_el = c->a_el;
+    cp.dx = c->dx;
+    cp.inv_e_unit = 1.0 / (c->rho_unit * c->c2);
     for (int a = 0; a < c->M; ++a) cp.m[a] = c->m[a];
     if (c->chem_fn)
       HIPCHK(c, launch_chem_specialized(c->chem_fn, cp, c->stream));
@@ -829,6 +838,7 @@ int lbm_set_mechanism(lbm_ctx *c, const lbm_mechanism *mech) {
     HIPCHK(c, hipMemset(c->iv, 0, sizeof(double) * c->N));
   }
   c->has_ct = has_ct ? 1 : 0;
+  c->a_el = mech->a_s2;
   c->K = K;
   c->has_mech = 1;
   return LBM_OK;
@@ -854,7 +864,7 @@ int lbm_set_electrode(lbm_ctx *c, const double *phi_electrode, const double *ome
     if (!std::isfinite(omega[n]) || omega[n] < 0.0)
       return fail(c, LBM_EINVAL, "resistivity omega[%d] must be finite and >= 0", n);
   if (!c->pel) {
-    double **bufs[] = {&c->ia, &c->pel, &c->ped, &c->omega_n};
+    double **bufs[] = {&c->ia, &c->pel, &c->ped, &c->omega_n, &c->uel};
     for (double **b : bufs) {
       const int rc = dalloc(c, b, c->N);
       if (rc) return rc;
@@ -1322,7 +1332,7 @@ void lbm_destroy(lbm_ctx *c) {
   if (c->timing) lbm_set_timing(c, 0);
   double *bufs[] = {c->pop[0], c->pop[1], c->phi, c->kfac, c->Tfield, c->X0, c->Plat, c->rA, c->rRT, c->rFk,
                     c->rrho, c->rY, c->rqd, c->rec[0], c->rec[1], c->T[0], c->T[1], c->srcsum, c->theta, c->rEs, c->faradaic, c->macro, c->partials,
-                    c->iv, c->ia, c->pel, c->ped, c->omega_n};
+                    c->iv, c->ia, c->pel, c->ped, c->omega_n, c->uel};
   for (double *b : bufs) dfree(b);
   dfree(c->colflag);
   dfree(c->d_line_off);

@@ -71,6 +71,7 @@ struct KParams {
   int K, esrc;
   const double *theta;      // [K][N] coverages (after this step's chemistry in k_mixture)
   double *rEs;              // [N] E_s before this step's chemistry
+  const double *uel;        // [N] electrical energy source of this step's chemistry, or NULL
   double es_u[LBM_KMAX], es_c[LBM_KMAX];
 };
 
@@ -109,6 +110,11 @@ struct ChemParams {
   const double *ped, *pel;
   double F_C;
   double *iv;
+  // electrical energy source (energy lattice on): uel[n] = (P_Omega - P_elec) dt in lattice
+  // energy units, P_elec = |dPhi| I^(v), P_Omega = (a_el / l_TPB) I^(v)^2 omega[n] dx
+  const double *omega;
+  double a_el, dx, inv_e_unit;
+  double *uel;
 };
 
 // 1-D charge transport along x: line l holds the nodes off[l] .. off[l + 1] - 1 in x order

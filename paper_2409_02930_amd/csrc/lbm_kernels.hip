@@ -837,6 +837,7 @@ __global__ __launch_bounds__(256) void k_mixture(const KParams p) {
         for (int k = 0; k < p.K; ++k) es += p.theta[(size_t)k * N + n] * (p.es_u[k] + p.es_c[k] * T);
         dEs = p.rEs[n] - es;
       }
+      if (p.uel) dEs += p.uel[n];               // the electrical source joins the unified energy
       U_pc = (phirho * U + dEs) / phirho_pc;
     }
 #pragma unroll
@@ -1155,6 +1156,11 @@ void k_chem(const ChemParams cp) {
     iv += cp.F_C * tb->l_tpb * ze / cp.dt;   // eq volumetricCurrent
   }
   if (cp.iv) cp.iv[n] = iv;
+  if (cp.uel) {                 // electrical work out, ohmic heat in (eqs for P_elec, P_Omega, U_source)
+    const double p_elec = fabs(cp.ped[n] - cp.pel[n]) * iv;
+    const double p_om = (cp.a_el / tb->l_tpb) * iv * iv * cp.omega[n] * cp.dx;
+    cp.uel[n] = (p_om - p_elec) * cp.dt * cp.inv_e_unit;
+  }
   if (cp.faradaic) {
     const double r = cp.faradaic[n] * cp.dt;
 #pragma unroll

@@ -186,3 +186,19 @@ def test_packed_columns_with_their_own_electrode_potentials(lbm):
         for g, r in zip(ch, (o.i_v, o.i_a, o.phi_el)):
             assert _err(g[sl], r) <= TOL
         off += c.nx
+
+
+@pytest.mark.parametrize("omega", [0.0, 2.0e-3])
+def test_electrical_energy_source_with_energy_lattice(lbm, omega):
+    """The electrical work and ohmic heat of the charge transfer enter the unified internal
+    energy (energy lattice on): temperature, populations' moments and charge outputs match
+    the oracle over 25 steps, with and without electrolyte resistance."""
+    w = synth.electrode_slab(nx=16, ny=2, energy=True, omega=omega, phi_ed=0.05)
+    _log(f"energy electrode omega={omega}")
+    lat = lbm.lattice_from_workload(w)
+    o = Oracle(w)
+    for chunk in (1, 24):
+        lat.step(chunk)
+        o.step(chunk)
+        _check(lat, o)
+    lat.close()
