@@ -75,6 +75,13 @@ Readings adopted where the paper is silent, garbled or self-inconsistent
       dPhi and I^(v) those of the step's chemistry.  It enters the unified
       internal energy before the adsorbed phases are subtracted (eq
       InternalEnergyCell_PC), so only with the energy lattice on.
+  R32 current control (Section 4.2, the secant on the electrode potential): with
+      a target area current density per x line, each step first varies the
+      line's electrode potential so that I^(a) at the line's last node, from
+      this step's chemistry at the step's electrolyte potential, equals the
+      target: secant iterates start at the line's present potential and 10 mV
+      above it, a fixed number of updates, none where the two last currents
+      are equal; the step then runs at the last iterate.
 """
 from __future__ import annotations
 
@@ -223,8 +230,11 @@ class Oracle:
         self.i_a = np.zeros(self.N)
         self.phi_el = np.zeros(self.N)
         self.dphi = np.zeros(self.N)
+        self.n_lines = w.ny * w.nz                       # x lines: node n lies on line n // nx
+        self.line = np.arange(self.N) // w.nx
+        self.line_end = np.arange(self.n_lines) * w.nx + (w.nx - 1)
         if self.electrode is not None:
-            self.dphi[:] = float(self.electrode["phi_ed"])
+            self.set_electrode_potential(self.electrode["phi_ed"])
         self.step_count = 0
         self._init_state()
 
@@ -487,6 +497,32 @@ class Oracle:
         p_om = (mech.a_s2 / mech.l_tpb) * iv * iv * om * self.w.dx                        # W/m^3
         return (p_om - p_elec) * self.dt / (self.rho_unit * self.c2)
 
+    def set_electrode_potential(self, phi_ed):
+        """Electrode potential of every x line (scalar or one per line), V."""
+        self.ped = np.array(np.broadcast_to(np.asarray(phi_ed, dtype=np.float64), (self.n_lines,)))
+        self.dphi = self.ped[self.line] - self.phi_el
+
+    def match_current(self, mac):
+        """R32: per-line secant on the electrode potential for the target end current."""
+        el = self.electrode
+        target = np.broadcast_to(np.asarray(el["target_ia"], dtype=np.float64), (self.n_lines,))
+
+        def end_current(p_line):
+            self.dphi = p_line[self.line] - self.phi_el
+            self.chemistry(mac)                                  # trial: the state is not changed
+            ia, _ = self.charge_transport(self._iv)
+            return ia[self.line_end] - target
+
+        p0 = self.ped.copy()
+        f0 = end_current(p0)
+        p1 = p0 + 0.01
+        for _ in range(int(el["n_secant"])):
+            f1 = end_current(p1)
+            d = f1 - f0
+            p2 = np.where(d != 0.0, p1 - f1 * (p1 - p0) / np.where(d != 0.0, d, 1.0), p1)
+            p0, f0, p1 = p1, f1, p2
+        self.set_electrode_potential(p1)
+
     def charge_transport(self, iv):
         """eqs areaCurrentDensity and electrolytePotential along x (R30): the area current
         density I^(a) and the electrolyte potential of every node from the volumetric
@@ -533,6 +569,8 @@ class Oracle:
         rho_a, rho, u, v = mac["rho_a"], mac["rho"], mac["u"], mac["v"]
         RaT, RT, Y = mac["RaT"], mac["RT"], mac["Y"]
         # S7 chemistry
+        if self.electrode is not None and self.electrode.get("target_ia") is not None:
+            self.match_current(mac)
         if self.mech is not None:
             src, theta_new = self.chemistry(mac)
         elif w.faradaic_rate is not None:
@@ -636,7 +674,7 @@ class Oracle:
         if self.electrode is not None:
             self.i_v = self._iv if self.mech is not None else np.zeros(self.N)
             self.i_a, self.phi_el = self.charge_transport(self.i_v)
-            self.dphi = float(self.electrode["phi_ed"]) - self.phi_el
+            self.dphi = self.ped[self.line] - self.phi_el
         self.step_count += 1
 
     # ----- S11 ---------------------------------------------------------------

@@ -98,8 +98,7 @@ def test_potential_sweep_between_steps_and_graph_replay(lbm):
     lats[1].set_graph(4)
     for ph in (0.05, 0.02, 0.09):
         _log(f"phi_ed {ph}")
-        o.electrode["phi_ed"] = ph
-        o.dphi = ph - o.phi_el
+        o.set_electrode_potential(ph)
         o.step(9)
         for lat in lats:
             lat.set_electrode(ph, om)

@@ -666,3 +666,19 @@ def test_electrical_energy_source_enters_the_energy_total():
             assert dg < 0                                         # work leaves the fluid
         else:
             assert heat.sum() > work.sum() and dg > 0             # ohmic heating wins here
+
+
+def test_current_control_reaches_the_target_on_every_line():
+    """R32 (Section 4.2): with a target area current density per x line, every step's end
+    current I^(a)(x = nx - 1) equals the target to rounding, and the line asked for the
+    larger current runs at the higher electrode potential (oxidation current grows with
+    the potential)."""
+    w = synth.electrode_slab(nx=12, ny=2, omega=5e-3)
+    target = np.array([1.0e6, 1.6e6])
+    w.electrode["target_ia"] = target
+    w.electrode["n_secant"] = 6
+    o = lo.Oracle(w)
+    for _ in range(4):
+        o.step(1)
+        assert np.allclose(o.i_a[o.line_end], target, rtol=1e-12, atol=0)
+        assert o.ped[1] > o.ped[0]
