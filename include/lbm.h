@@ -219,6 +219,22 @@ int lbm_set_electrode(lbm_ctx *ctx, const double *phi_electrode, const double *o
  * charge-transfer mechanism or an electrode.                                               */
 int lbm_get_charge(lbm_ctx *ctx, double *iv, double *ia, double *phi_el);
 
+/* Current control (Section 4.2: the electrode potential found by the secant method so that
+ * the current matches a target).  target_ia: host [n_lines] area current density in A/m^2
+ * wanted at the last node of each x line; NULL switches the control off.  Each step, after
+ * the species kernel and before its chemistry, the library runs 1 + n_secant trial
+ * chemistry passes (state unchanged, current only) with the line's charge integration:
+ * iterates start at the line's present electrode potential and 10 mV above it, then
+ * n_secant secant updates (none on a line whose two last currents are equal); the step
+ * runs at the last iterate, which becomes the line's electrode potential
+ * (lbm_get_electrode_potential).  n_secant in 1..64.  Needs lbm_set_electrode and a
+ * charge-transfer mechanism (LBM_ESTATE otherwise); drops a captured step graph.        */
+int lbm_set_current_target(lbm_ctx *ctx, const double *target_ia, int32_t n_secant);
+
+/* Copies the electrode potential of each x line (host [n_lines], V); synchronizes the
+ * stream.  LBM_ESTATE without an electrode.                                                */
+int lbm_get_electrode_potential(lbm_ctx *ctx, double *phi_line);
+
 /* Advances n_steps time steps, asynchronously on the configured stream. */
 int lbm_step(lbm_ctx *ctx, int64_t n_steps);
 

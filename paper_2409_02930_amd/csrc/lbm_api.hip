@@ -70,6 +70,10 @@ struct lbm_ctx {
   int *d_line_off = nullptr;
   double *iv = nullptr, *ia = nullptr, *pel = nullptr, *ped = nullptr, *omega_n = nullptr;
   double *uel = nullptr;                // [N] electrical energy source (energy lattice on)
+  // current control: per-line target I^(a) and secant state, trial buffers [N]
+  int n_secant = 0;
+  double *d_phi_line = nullptr, *d_target = nullptr, *d_p0 = nullptr, *d_f0 = nullptr, *d_p1 = nullptr;
+  double *iv_try = nullptr, *ia_try = nullptr, *pel_try = nullptr, *ped_try = nullptr;
   double a_el = 0.0;                    // specific area of the electrolyte (second) surface phase
   ChemParams chem;
   ChemTables *chem_tab = nullptr;
@@ -524,6 +528,42 @@ int enqueue_step(lbm_ctx *c, int record_slot) {
     cp.dx = c->dx;
     cp.inv_e_unit = 1.0 / (c->rho_unit * c->c2);
     for (int a = 0; a < c->M; ++a) cp.m[a] = c->m[a];
+    if (c->n_secant && c->electrode && c->has_ct) {   // current control before the step's chemistry
+      ChemParams tp = cp;
+      tp.dry = 1;
+      tp.ped = c->ped_try;
+      tp.iv = c->iv_try;
+      tp.uel = nullptr;
+      ChargeParams tq;
+      tq.lines = c->n_lines;
+      tq.off = c->d_line_off;
+      tq.dx = c->dx;
+      tq.iv = c->iv_try;
+      tq.omega = c->omega_n;
+      tq.ia = c->ia_try;
+      tq.pel = c->pel_try;
+      SecantParams sp;
+      sp.lines = c->n_lines;
+      sp.off = c->d_line_off;
+      sp.ia = c->ia_try;
+      sp.target = c->d_target;
+      sp.p0 = c->d_p0;
+      sp.f0 = c->d_f0;
+      sp.p1 = c->d_p1;
+      sp.phi_line = c->d_phi_line;
+      sp.ped_try = c->ped_try;
+      sp.ped = c->ped;
+      sp.stage = 0;
+      sp.final_iter = 0;
+      HIPCHK(c, launch_secant(sp, true, c->stream));
+      for (int it = 0; it <= c->n_secant; ++it) {
+        HIPCHK(c, launch_chem(tp, c->stream));
+        HIPCHK(c, launch_charge(tq, c->stream));
+        sp.stage = it == 0 ? 0 : 1;
+        sp.final_iter = it == c->n_secant ? 1 : 0;
+        HIPCHK(c, launch_secant(sp, false, c->stream));
+      }
+    }
     if (c->chem_fn)
       HIPCHK(c, launch_chem_specialized(c->chem_fn, cp, c->stream));
     else
@@ -864,11 +904,18 @@ int lbm_set_electrode(lbm_ctx *c, const double *phi_electrode, const double *ome
     if (!std::isfinite(omega[n]) || omega[n] < 0.0)
       return fail(c, LBM_EINVAL, "resistivity omega[%d] must be finite and >= 0", n);
   if (!c->pel) {
-    double **bufs[] = {&c->ia, &c->pel, &c->ped, &c->omega_n, &c->uel};
+    double **bufs[] = {&c->ia, &c->pel, &c->ped, &c->omega_n, &c->uel,
+                       &c->iv_try, &c->ia_try, &c->pel_try, &c->ped_try};
     for (double **b : bufs) {
       const int rc = dalloc(c, b, c->N);
       if (rc) return rc;
       HIPCHK(c, hipMemset(*b, 0, sizeof(double) * c->N));
+    }
+    double **lb[] = {&c->d_phi_line, &c->d_target, &c->d_p0, &c->d_f0, &c->d_p1};
+    for (double **b : lb) {
+      const int rc = dalloc(c, b, L);
+      if (rc) return rc;
+      HIPCHK(c, hipMemset(*b, 0, sizeof(double) * L));
     }
     const hipError_t e = hipMalloc((void **)&c->d_line_off, sizeof(int) * (L + 1));
     if (e != hipSuccess) return fail(c, LBM_ENOMEM, "hipMalloc line offsets");
@@ -884,8 +931,34 @@ int lbm_set_electrode(lbm_ctx *c, const double *phi_electrode, const double *ome
   for (int l = 0; l < L; ++l)
     for (int n = c->line_off[l]; n < c->line_off[l + 1]; ++n) ped[n] = phi_electrode[l];
   HIPCHK(c, hipMemcpy(c->ped, ped.data(), sizeof(double) * c->N, hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(c->d_phi_line, phi_electrode, sizeof(double) * L, hipMemcpyHostToDevice));
   HIPCHK(c, hipMemcpy(c->omega_n, omega, sizeof(double) * c->N, hipMemcpyHostToDevice));
   c->electrode = 1;
+  return LBM_OK;
+}
+
+int lbm_set_current_target(lbm_ctx *c, const double *target_ia, int32_t n_secant) {
+  if (!c) return LBM_EINVAL;
+  drop_graph(c);
+  if (!target_ia) {
+    c->n_secant = 0;
+    return LBM_OK;
+  }
+  if (!c->electrode || !c->has_ct)
+    return fail(c, LBM_ESTATE, "current control needs an electrode and a charge-transfer mechanism");
+  if (n_secant < 1 || n_secant > 64) return fail(c, LBM_EINVAL, "n_secant must lie in 1..64");
+  for (int l = 0; l < c->n_lines; ++l)
+    if (!std::isfinite(target_ia[l])) return fail(c, LBM_EINVAL, "target current of line %d not finite", l);
+  HIPCHK(c, hipMemcpy(c->d_target, target_ia, sizeof(double) * c->n_lines, hipMemcpyHostToDevice));
+  c->n_secant = n_secant;
+  return LBM_OK;
+}
+
+int lbm_get_electrode_potential(lbm_ctx *c, double *phi_line) {
+  if (!c || !phi_line) return LBM_EINVAL;
+  if (!c->electrode) return fail(c, LBM_ESTATE, "no electrode installed");
+  HIPCHK(c, c->stream ? hipStreamSynchronize(c->stream) : hipDeviceSynchronize());
+  HIPCHK(c, hipMemcpy(phi_line, c->d_phi_line, sizeof(double) * c->n_lines, hipMemcpyDeviceToHost));
   return LBM_OK;
 }
 
@@ -1332,7 +1405,9 @@ void lbm_destroy(lbm_ctx *c) {
   if (c->timing) lbm_set_timing(c, 0);
   double *bufs[] = {c->pop[0], c->pop[1], c->phi, c->kfac, c->Tfield, c->X0, c->Plat, c->rA, c->rRT, c->rFk,
                     c->rrho, c->rY, c->rqd, c->rec[0], c->rec[1], c->T[0], c->T[1], c->srcsum, c->theta, c->rEs, c->faradaic, c->macro, c->partials,
-                    c->iv, c->ia, c->pel, c->ped, c->omega_n, c->uel};
+                    c->iv, c->ia, c->pel, c->ped, c->omega_n, c->uel,
+                    c->d_phi_line, c->d_target, c->d_p0, c->d_f0, c->d_p1,
+                    c->iv_try, c->ia_try, c->pel_try, c->ped_try};
   for (double *b : bufs) dfree(b);
   dfree(c->colflag);
   dfree(c->d_line_off);

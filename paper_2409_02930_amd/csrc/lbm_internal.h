@@ -115,6 +115,18 @@ struct ChemParams {
   const double *omega;
   double a_el, dx, inv_e_unit;
   double *uel;
+  int dry;                  // trial of the current control: write iv only
+};
+
+// Current control: per-line secant state (lines of ChargeParams).
+struct SecantParams {
+  int lines, stage, final_iter;
+  const int *off;           // [lines + 1]
+  const double *ia;         // [N] I^(a) of the trial
+  const double *target;     // [lines] A/m^2
+  double *p0, *f0, *p1;     // [lines] iterates and the current error of p0
+  double *phi_line;         // [lines] electrode potential of the line
+  double *ped_try, *ped;    // [N] trial / step electrode potential per node
 };
 
 // 1-D charge transport along x: line l holds the nodes off[l] .. off[l + 1] - 1 in x order
@@ -166,6 +178,7 @@ hipError_t launch_species(int dim, const KParams &p, hipStream_t s);
 hipError_t launch_mixture(int dim, const KParams &p, hipStream_t s);
 hipError_t launch_chem(const ChemParams &cp, hipStream_t s);
 hipError_t launch_charge(const ChargeParams &q, hipStream_t s);
+hipError_t launch_secant(const SecantParams &sp, bool start, hipStream_t s);
 hipError_t launch_surface_energy(const KParams &p, hipStream_t s);
 hipError_t launch_moments(int dim, const KParams &p, double *out, hipStream_t s);
 hipError_t launch_diag(int dim, int L, int Mmom, const KParams &p, const void *pop, double *partials,

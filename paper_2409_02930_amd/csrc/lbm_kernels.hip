@@ -1156,6 +1156,7 @@ void k_chem(const ChemParams cp) {
     iv += cp.F_C * tb->l_tpb * ze / cp.dt;   // eq volumetricCurrent
   }
   if (cp.iv) cp.iv[n] = iv;
+  if (cp.dry) return;           // a trial of the current control: only the current is wanted
   if (cp.uel) {                 // electrical work out, ohmic heat in (eqs for P_elec, P_Omega, U_source)
     const double p_elec = fabs(cp.ped[n] - cp.pel[n]) * iv;
     const double p_om = (cp.a_el / tb->l_tpb) * iv * iv * cp.omega[n] * cp.dx;
@@ -1441,6 +1442,48 @@ __global__ __launch_bounds__(256) void k_charge(const ChargeParams q) {
     q.ia[n] = ia;
     q.pel[n] = pel;
   }
+}
+
+// Current control (secant on each line's electrode potential): k_secant_start takes the
+// line's present potential as the first iterate; k_secant reads the trial's end current
+// I^(a) - target and forms the next iterate (stage 0: 10 mV above the first; stage 1: the
+// secant update, none where the two last currents are equal), then fills the trial (or,
+// for the final iterate, the step's) electrode potential of the line's nodes.
+__global__ __launch_bounds__(256) void k_secant_start(const SecantParams s) {
+  const int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= s.lines) return;
+  const double p = s.phi_line[l];
+  s.p0[l] = p;
+  for (int n = s.off[l]; n < s.off[l + 1]; ++n) s.ped_try[n] = p;
+}
+
+__global__ __launch_bounds__(256) void k_secant(const SecantParams s) {
+  const int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= s.lines) return;
+  const int b = s.off[l], e = s.off[l + 1];
+  const double f = s.ia[e - 1] - s.target[l];
+  double p;
+  if (s.stage == 0) {
+    s.f0[l] = f;
+    p = s.p0[l] + 0.01;
+  } else {
+    const double p0 = s.p0[l], p1 = s.p1[l], d = f - s.f0[l];
+    p = d != 0.0 ? p1 - f * (p1 - p0) / d : p1;
+    s.p0[l] = p1;
+    s.f0[l] = f;
+  }
+  s.p1[l] = p;
+  double *dst = s.final_iter ? s.ped : s.ped_try;
+  for (int n = b; n < e; ++n) dst[n] = p;
+  if (s.final_iter) s.phi_line[l] = p;
+}
+
+hipError_t launch_secant(const SecantParams &sp, bool start, hipStream_t s) {
+  if (start)
+    hipLaunchKernelGGL(k_secant_start, dim3((sp.lines + 255) / 256), dim3(256), 0, s, sp);
+  else
+    hipLaunchKernelGGL(k_secant, dim3((sp.lines + 255) / 256), dim3(256), 0, s, sp);
+  return hipGetLastError();
 }
 
 hipError_t launch_charge(const ChargeParams &q, hipStream_t s) {

@@ -87,6 +87,8 @@ def _load():
         "lbm_set_chem_kernel": ([vp, C.c_int32], C.c_int),
         "lbm_set_electrode": ([vp, _dp, _dp], C.c_int),
         "lbm_get_charge": ([vp, _dp, _dp, _dp], C.c_int),
+        "lbm_set_current_target": ([vp, _dp, C.c_int32], C.c_int),
+        "lbm_get_electrode_potential": ([vp, _dp], C.c_int),
         "lbm_step": ([vp, C.c_int64], C.c_int),
         "lbm_set_graph": ([vp, C.c_int32], C.c_int),
         "lbm_adjoint_outlet_flux": ([vp, C.c_int64, C.c_int32, _dp, vp, _dp, C.c_int32], C.c_int),
@@ -110,7 +112,8 @@ def _load():
 _lib = _load()
 
 EXPORTED = ["lbm_init", "lbm_init_columns", "lbm_set_porous_field", "lbm_set_mechanism",
-            "lbm_set_chem_kernel", "lbm_set_faradaic_source", "lbm_set_electrode", "lbm_get_charge", "lbm_step", "lbm_set_graph", "lbm_adjoint_outlet_flux", "lbm_moments", "lbm_moment_rows",
+            "lbm_set_chem_kernel", "lbm_set_faradaic_source", "lbm_set_electrode", "lbm_get_charge",
+            "lbm_set_current_target", "lbm_get_electrode_potential", "lbm_step", "lbm_set_graph", "lbm_adjoint_outlet_flux", "lbm_moments", "lbm_moment_rows",
             "lbm_get_diagnostics", "lbm_set_timing", "lbm_get_timing", "lbm_save", "lbm_load",
             "lbm_last_error", "lbm_destroy"]
 
@@ -259,6 +262,21 @@ class Lattice:
             raise ValueError("omega must have N or nx entries")
         self._check(_lib.lbm_set_electrode(self.ctx, _ptr(ped), _ptr(om)))
 
+    def set_current_target(self, target_ia, n_secant=6):
+        """Area current density (A/m^2; scalar or one per x line) each step's electrode
+        potentials are solved for; None switches the control off."""
+        if target_ia is None:
+            self._check(_lib.lbm_set_current_target(self.ctx, None, 0))
+            return
+        t = np.ascontiguousarray(np.broadcast_to(np.asarray(target_ia, dtype=np.float64), (self.n_lines,)))
+        self._check(_lib.lbm_set_current_target(self.ctx, _ptr(t), int(n_secant)))
+
+    def electrode_potential(self):
+        """Electrode potential of each x line, V."""
+        out = np.empty(self.n_lines)
+        self._check(_lib.lbm_get_electrode_potential(self.ctx, _ptr(out)))
+        return out
+
     def charge(self):
         """(I^(v) A/m^3, I^(a) A/m^2, Phi_electrolyte V) of the last step, host float64 [N] each."""
         out = [np.empty(self.N) for _ in range(3)]
@@ -367,6 +385,8 @@ def lattice_from_workload(w, stream=None, col_len=None, precision=FP64) -> Latti
     el = getattr(w, "electrode", None)
     if el is not None:
         lat.set_electrode(el["phi_ed"], el["omega"])
+        if el.get("target_ia") is not None:
+            lat.set_current_target(el["target_ia"], el.get("n_secant", 6))
     return lat
 
 

@@ -201,3 +201,29 @@ def test_electrical_energy_source_with_energy_lattice(lbm, omega):
         o.step(chunk)
         _check(lat, o)
     lat.close()
+
+
+def test_current_control_secant_matches_oracle(lbm):
+    """Current control: each step's electrode potential of every line is solved by the secant
+    method for a target end current density (one target per line), then the step runs at
+    it.  Potentials, fields and charge outputs match the oracle after every step, and the
+    end currents meet the targets; the graph step loop replays the same launches."""
+    import torch
+    stream = torch.cuda.Stream()
+    w = synth.electrode_slab(nx=12, ny=3, omega=5e-3)
+    target = np.array([1.0e6, 1.6e6, 0.4e6])
+    w.electrode["target_ia"] = target
+    w.electrode["n_secant"] = 10
+    o = Oracle(w)
+    lats = [lbm.lattice_from_workload(w, stream=stream.cuda_stream) for _ in range(2)]
+    lats[1].set_graph(2)
+    for chunk in (1, 4, 4):
+        o.step(chunk)
+        for lat in lats:
+            lat.step(chunk)
+            _check(lat, o)
+            assert _err(lat.electrode_potential(), o.ped) <= TOL
+            _, ia, _ = lat.charge()
+            assert np.allclose(ia[o.line_end], target, rtol=1e-11, atol=0)
+    for lat in lats:
+        lat.close()
