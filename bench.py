@@ -189,6 +189,55 @@ def bench_c4(args, lbm, torch):
     print(json.dumps(out), flush=True)
 
 
+def bench_c4_electrode(args, lbm, torch):
+    """Polarisation form of the batched cells: the 64 ragged D1Q3 columns of c4 (lengths and
+    porosities), each a closed cell with the two-phase TPB mechanism whose edge reaction is a
+    one-electron charge transfer, under current control: every step solves each column's
+    electrode potential by the secant for its target current density (c4's 0..2 A/cm^2, at
+    least 0.1), then integrates the charge transport along the column."""
+    from workloads import synth
+    lengths, phis, currents = synth.config4_columns()
+    targets = np.maximum(np.asarray(currents, dtype=np.float64), 0.1) * 1.0e4     # A/m^2
+    cols = [synth.electrode_slab(nx=int(L), ny=1, phi=float(p_), lattice=1, kf=3.0e-2, kb=1.0e-2,
+                                 omega=1.0e-3) for L, p_ in zip(lengths, phis)]
+    stream = torch.cuda.Stream()
+    cat = lambda k: np.concatenate([getattr(c, k) for c in cols], axis=-1)
+    w0 = cols[0]
+    N = int(sum(lengths))
+    lat = lbm.Lattice(1, N, 1, 1, w0.molar_mass, w0.D_ref_lat, cat("X0"), cat("T0"), cat("P0"),
+                      T_ref=w0.T_ref, bc_lo=w0.bc_lo, bc_hi=w0.bc_hi,
+                      col_len=[int(L) for L in lengths], stream=stream.cuda_stream)
+    lat.set_porous_field(cat("phi"), cat("tort"), w0.pore_radius)
+    lat.set_mechanism(w0.mech)
+    lat.set_electrode(np.full(len(cols), 0.3), np.concatenate([c.electrode["omega"] for c in cols]))
+    lat.set_current_target(targets, args.n_secant)
+    lat.set_graph(args.graph_steps)
+    log(f"electrode cells: {len(cols)} columns, {N} nodes, {args.n_secant} secant updates; warmup {args.warmup}")
+    lat.step(args.warmup)
+    stream.synchronize()
+    t0 = time.perf_counter()
+    lat.step(args.steps)
+    stream.synchronize()
+    el = time.perf_counter() - t0
+    pot = lat.electrode_potential()
+    _, ia, _ = lat.charge()
+    ends = np.cumsum(lengths) - 1
+    miss = float(np.max(np.abs(ia[ends] / targets - 1.0)))
+    lat.close()
+    out = {"metric": "MLUPS", "value": N * args.steps / el / 1e6, "unit": "MLUPS", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": el * 1e3 / args.steps,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": f"c4_electrode {len(cols)} packed D1Q3 columns, {N} nodes, M=3 K=4 R=3, "
+                                  f"charge transfer + charge transport, current control with "
+                                  f"{args.n_secant} secant updates, graph step loop of {args.graph_steps} steps",
+                      "nodes": N, "parallelism": "single GPU"},
+           "polarisation": {"target_A_cm2": [round(t / 1e4, 4) for t in targets[::9]],
+                            "electrode_potential_V": [round(float(v), 6) for v in pot[::9]],
+                            "max_relative_current_miss": miss}}
+    print(json.dumps(out), flush=True)
+
+
 def bench_c5_adjoint(args, lbm, torch):
     """C5 (D2Q9 1024x256, 3 species, GRF porosity, inlet/outflow): forward steps
     alone vs the adjoint gradient of the outlet flux (forward with checkpoints,
@@ -235,6 +284,8 @@ def main():
                     help="mechanism-specialised (default) or generic chemistry kernel")
     ap.add_argument("--graph-steps", type=int, default=32,
                     help="c4: steps per captured graph of the batched run (0 = plain launches)")
+    ap.add_argument("--n-secant", type=int, default=6,
+                    help="c4_electrode: secant updates of the current control per step")
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64",
                     help="population storage (arithmetic is FP64 either way)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -260,6 +311,8 @@ def main():
         del src, dst
     if args.workload == "c4":
         return bench_c4(args, lbm, torch)
+    if args.workload == "c4_electrode":
+        return bench_c4_electrode(args, lbm, torch)
     if args.workload == "c5_adjoint":
         return bench_c5_adjoint(args, lbm, torch)
     log(f"building workload {args.workload}")

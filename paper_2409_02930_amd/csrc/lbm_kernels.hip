@@ -1428,19 +1428,45 @@ hipError_t launch_surface_energy(const KParams &p, hipStream_t s) {
   return hipGetLastError();
 }
 
-// eqs areaCurrentDensity and electrolytePotential: one lane per line walks x, I^(a)
-// and Phi_electrolyte accumulated cell by cell from the line's first node (Phi = 0
-// before it).
+// Inclusive sum over the 256 threads of a block (Hillis-Steele in LDS); every thread
+// also receives the block total.
+__device__ __forceinline__ double block_scan256(double v, double *s, double &total) {
+  const int t = threadIdx.x;
+  __syncthreads();                              // earlier readers of s are done
+  s[t] = v;
+  __syncthreads();
+#pragma unroll
+  for (int off = 1; off < 256; off <<= 1) {
+    const double add = t >= off ? s[t - off] : 0.0;
+    __syncthreads();
+    v += add;
+    s[t] = v;
+    __syncthreads();
+  }
+  total = s[255];
+  return v;
+}
+
+// eqs areaCurrentDensity and electrolytePotential: one block per line, I^(a) and
+// Phi_electrolyte as prefix sums along x from the line's first node (Phi = 0 before
+// it), 256 cells at a time with the running totals carried.
 __global__ __launch_bounds__(256) void k_charge(const ChargeParams q) {
-  const int line = blockIdx.x * blockDim.x + threadIdx.x;
-  if (line >= q.lines) return;
+  __shared__ double s[256];
+  const int line = blockIdx.x;
   const int b = q.off[line], e = q.off[line + 1];
-  double ia = 0.0, pel = 0.0;
-  for (int n = b; n < e; ++n) {
-    ia += q.iv[n] * q.dx;
-    pel += ia * q.omega[n] * q.dx;
-    q.ia[n] = ia;
-    q.pel[n] = pel;
+  double cia = 0.0, cpel = 0.0;                 // totals of the cells before this chunk
+  for (int c0 = b; c0 < e; c0 += 256) {
+    const int n = c0 + (int)threadIdx.x;
+    const bool in = n < e;
+    double tot;
+    const double ia = cia + block_scan256(in ? q.iv[n] * q.dx : 0.0, s, tot);
+    cia += tot;
+    const double pel = cpel + block_scan256(in ? ia * q.omega[n] * q.dx : 0.0, s, tot);
+    cpel += tot;
+    if (in) {
+      q.ia[n] = ia;
+      q.pel[n] = pel;
+    }
   }
 }
 
@@ -1487,7 +1513,7 @@ hipError_t launch_secant(const SecantParams &sp, bool start, hipStream_t s) {
 }
 
 hipError_t launch_charge(const ChargeParams &q, hipStream_t s) {
-  hipLaunchKernelGGL(k_charge, dim3((q.lines + 255) / 256), dim3(256), 0, s, q);
+  hipLaunchKernelGGL(k_charge, dim3(q.lines), dim3(256), 0, s, q);
   return hipGetLastError();
 }
 
