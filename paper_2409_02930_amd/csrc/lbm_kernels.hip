@@ -1475,40 +1475,43 @@ __global__ __launch_bounds__(256) void k_charge(const ChargeParams q) {
 // I^(a) - target and forms the next iterate (stage 0: 10 mV above the first; stage 1: the
 // secant update, none where the two last currents are equal), then fills the trial (or,
 // for the final iterate, the step's) electrode potential of the line's nodes.
+// One block per line: every thread forms the line's iterate (the same arithmetic), thread
+// 0 stores the state once all have read it, and the block fills the line's nodes.
 __global__ __launch_bounds__(256) void k_secant_start(const SecantParams s) {
-  const int l = blockIdx.x * blockDim.x + threadIdx.x;
-  if (l >= s.lines) return;
+  const int l = blockIdx.x;
   const double p = s.phi_line[l];
-  s.p0[l] = p;
-  for (int n = s.off[l]; n < s.off[l + 1]; ++n) s.ped_try[n] = p;
+  if (threadIdx.x == 0) s.p0[l] = p;
+  for (int n = s.off[l] + (int)threadIdx.x; n < s.off[l + 1]; n += 256) s.ped_try[n] = p;
 }
 
 __global__ __launch_bounds__(256) void k_secant(const SecantParams s) {
-  const int l = blockIdx.x * blockDim.x + threadIdx.x;
-  if (l >= s.lines) return;
+  const int l = blockIdx.x;
   const int b = s.off[l], e = s.off[l + 1];
   const double f = s.ia[e - 1] - s.target[l];
+  const double p0 = s.p0[l], p1 = s.p1[l], f0 = s.f0[l];
   double p;
   if (s.stage == 0) {
-    s.f0[l] = f;
-    p = s.p0[l] + 0.01;
+    p = p0 + 0.01;
   } else {
-    const double p0 = s.p0[l], p1 = s.p1[l], d = f - s.f0[l];
+    const double d = f - f0;
     p = d != 0.0 ? p1 - f * (p1 - p0) / d : p1;
-    s.p0[l] = p1;
-    s.f0[l] = f;
   }
-  s.p1[l] = p;
+  __syncthreads();                              // every thread has read the state
+  if (threadIdx.x == 0) {
+    if (s.stage != 0) s.p0[l] = p1;
+    s.f0[l] = f;
+    s.p1[l] = p;
+    if (s.final_iter) s.phi_line[l] = p;
+  }
   double *dst = s.final_iter ? s.ped : s.ped_try;
-  for (int n = b; n < e; ++n) dst[n] = p;
-  if (s.final_iter) s.phi_line[l] = p;
+  for (int n = b + (int)threadIdx.x; n < e; n += 256) dst[n] = p;
 }
 
 hipError_t launch_secant(const SecantParams &sp, bool start, hipStream_t s) {
   if (start)
-    hipLaunchKernelGGL(k_secant_start, dim3((sp.lines + 255) / 256), dim3(256), 0, s, sp);
+    hipLaunchKernelGGL(k_secant_start, dim3(sp.lines), dim3(256), 0, s, sp);
   else
-    hipLaunchKernelGGL(k_secant, dim3((sp.lines + 255) / 256), dim3(256), 0, s, sp);
+    hipLaunchKernelGGL(k_secant, dim3(sp.lines), dim3(256), 0, s, sp);
   return hipGetLastError();
 }
 
