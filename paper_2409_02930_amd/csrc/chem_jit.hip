@@ -323,7 +323,9 @@ struct Gen {
     o("    const double *__restrict__ rrho, double *__restrict__ theta, double *__restrict__ rec,");
     o("    double *__restrict__ srcsum, const double *__restrict__ faradaic, const int fuel,");
     o("    const int product, const double dt, const double rho_unit, const double gam,");
-    o("    const double a_s) {");
+    o("    const double a_s, const double *__restrict__ ped, const double *__restrict__ pel,");
+    o("    double *__restrict__ ivo, const double *__restrict__ omega, double *__restrict__ uel,");
+    o("    const int dry, const double F_C, const double a_el, const double dx, const double inv_e_unit) {");
     o("  __shared__ double sk[%d][64];   // rate constants of this lane's node", 2 * R);
     o("  __shared__ double sy[%d][64];   // state at the start of the sub-step", S);
     o("  const int lane = threadIdx.x;");
@@ -342,6 +344,16 @@ struct Gen {
         else
           o("  sk[%d][lane] = %s * exp(-%s * inv_RT);", 2 * r + dirn, lit(A).c_str(), lit(Ea).c_str());
       }
+    // charge transfer: Butler-Volmer factors at dPhi = Phi_electrode - Phi_electrolyte
+    o("  const double fpot = pel ? F_C * (ped[n] - pel[n]) * inv_RT : 0.0;");
+    o("  (void)fpot; (void)omega; (void)a_el; (void)dx; (void)inv_e_unit;");
+    for (int r = 0; r < R; ++r)
+      if (sp.charge_z[r]) {
+        const double z = (double)sp.charge_z[r];
+        o("  sk[%d][lane] *= exp(%s * fpot);", 2 * r, lit(sp.beta_ct[r] * z).c_str());
+        o("  sk[%d][lane] *= exp(%s * fpot);", 2 * r + 1, lit(-(1.0 - sp.beta_ct[r]) * z).c_str());
+      }
+    o("  double iv = 0.0;   // charge released per unit volume over the step / dt");
     o("#define y0(s) sy[s][lane]");
     o("  double src[%d];", M);
     for (int a = 0; a < M; ++a) {
@@ -373,6 +385,7 @@ struct Gen {
     o("    double C[%d], dn[%d];", S, S);
     concentrations(o);
     for (int s = 0; s < S; ++s) o("    dn[%d] = 0.0;", s);
+    o("    double ze = 0.0;   // sum_r z_r xi_r");
     for (int r = 0; r < R; ++r) {
       if (!active(r, 0) && !active(r, 1)) continue;
       o("    {");
@@ -381,14 +394,24 @@ struct Gen {
       o("      const double dxi = h * (%s);", rate(r).c_str());
       for (int s = 0; s < S; ++s)
         if (st[r][s]) o("      dn[%d]%s;", s, acc(r, s, st[r][s], "dxi").c_str());
+      if (sp.charge_z[r]) o("      ze += %d.0 * dxi;", sp.charge_z[r]);
       o("    }");
     }
+    if (sp.has_ct) o("    iv += F_C * %s * ze / dt;   // eq volumetricCurrent", lit(sp.l_tpb).c_str());
+    o("    (void)ze;");
     for (int k = 0; k < K; ++k) o("    y0(%d) += dn[%d] / %s;", M + k, M + k, lit(sp.gam_k[k]).c_str());
     for (int a = 0; a < M; ++a) {
       o("    { const double dgas = dn[%d];   // mol per m^3 of REV", a);
       o("      y0(%d) += dgas / phi;", a);
       o("      src[%d] += dgas * %s / rho_unit; }", a, lit(sp.m[a]).c_str());
     }
+    o("  }");
+    o("  if (ivo) ivo[n] = iv;");
+    o("  if (dry) return;   // a trial of the current control: only the current is wanted");
+    o("  if (uel) {         // electrical work out, ohmic heat in");
+    o("    const double p_elec = fabs(ped[n] - pel[n]) * iv;");
+    o("    const double p_om = (a_el / %s) * iv * iv * omega[n] * dx;", lit(sp.l_tpb > 0 ? sp.l_tpb : 1.0).c_str());
+    o("    uel[n] = (p_om - p_elec) * dt * inv_e_unit;");
     o("  }");
     o("  if (faradaic) {");
     o("    const double r = faradaic[n] * dt;");
@@ -562,7 +585,12 @@ hipError_t launch_chem_specialized(hipFunction_t fn, const ChemParams &cp, hipSt
   double *theta = cp.theta, *rec = cp.rec, *srcsum = cp.srcsum;
   int fuel = cp.fuel, product = cp.product;
   double dt = cp.dt, rho_unit = cp.rho_unit, gam = cp.gamma, a_s = cp.a_s;
-  void *args[] = {&N, &T, &phi, &rrho, &theta, &rec, &srcsum, &far, &fuel, &product, &dt, &rho_unit, &gam, &a_s};
+  const double *ped = cp.ped, *pel = cp.pel, *omega = cp.omega;
+  double *iv = cp.iv, *uel = cp.uel;
+  int dry = cp.dry;
+  double F_C = cp.F_C, a_el = cp.a_el, dx = cp.dx, inv_e_unit = cp.inv_e_unit;
+  void *args[] = {&N, &T, &phi, &rrho, &theta, &rec, &srcsum, &far, &fuel, &product, &dt, &rho_unit, &gam, &a_s,
+                  &ped, &pel, &iv, &omega, &uel, &dry, &F_C, &a_el, &dx, &inv_e_unit};
   const unsigned nb = (unsigned)((N + 63) / 64);
   return hipModuleLaunchKernel(fn, nb, 1, 1, 64, 1, 1, 0, s, args, nullptr);
 }

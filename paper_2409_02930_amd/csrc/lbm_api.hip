@@ -430,7 +430,10 @@ int specialize_chemistry(lbm_ctx *c) {
     sp.Ea_b[r] = c->chem_host.Ea_b[r];
     sp.kind[r] = c->chem_host.kind[r];
     sp.w_r[r] = c->chem_host.w_r[r];
+    sp.charge_z[r] = c->chem_host.charge_z[r];
+    sp.beta_ct[r] = c->chem_host.beta_ct[r];
   }
+  sp.has_ct = c->has_ct;
   for (int a = 0; a < M; ++a) sp.m[a] = c->m[a];
   for (int k = 0; k < K; ++k) {
     sp.gam_k[k] = c->chem_host.gam_k[k];
@@ -557,7 +560,10 @@ int enqueue_step(lbm_ctx *c, int record_slot) {
       sp.final_iter = 0;
       HIPCHK(c, launch_secant(sp, true, c->stream));
       for (int it = 0; it <= c->n_secant; ++it) {
-        HIPCHK(c, launch_chem(tp, c->stream));
+        if (c->chem_fn)
+          HIPCHK(c, launch_chem_specialized(c->chem_fn, tp, c->stream));
+        else
+          HIPCHK(c, launch_chem(tp, c->stream));
         HIPCHK(c, launch_charge(tq, c->stream));
         sp.stage = it == 0 ? 0 : 1;
         sp.final_iter = it == c->n_secant ? 1 : 0;
@@ -633,7 +639,7 @@ int capture_steps(lbm_ctx *c) {
 // chemistry kernel of the remaining run in place.
 bool graph_ready(const lbm_ctx *c) {
   if (!c->graph_steps || c->first_step || c->steps_done < 1) return false;
-  if (c->has_mech && !c->has_ct && c->chem_kernel == LBM_CHEM_SPECIALIZED && !c->chem_fn) return false;
+  if (c->has_mech && c->chem_kernel == LBM_CHEM_SPECIALIZED && !c->chem_fn) return false;
   return true;
 }
 
@@ -1029,8 +1035,7 @@ int lbm_step(lbm_ctx *c, int64_t n_steps) {
   const int64_t first_timed = n_steps > kTimingRing ? n_steps - kTimingRing : 0;
   int slot = 0;
   for (int64_t s = 0; s < n_steps;) {
-    if (c->has_mech && !c->has_ct && c->chem_kernel == LBM_CHEM_SPECIALIZED && !c->chem_fn &&
-        c->steps_done >= 1) {
+    if (c->has_mech && c->chem_kernel == LBM_CHEM_SPECIALIZED && !c->chem_fn && c->steps_done >= 1) {
       const int rc = specialize_chemistry(c);   // after the first step (generic kernel)
       if (rc) return rc;
     }

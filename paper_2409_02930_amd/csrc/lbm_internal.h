@@ -170,6 +170,9 @@ struct ChemSpec {
   double w_r[LBM_RMAX];                          // gas-row weight of a surface reaction (a^(s))
   double gam_k[16], a_k[16];                     // per surface species: site density, area
   double l_tpb;
+  int charge_z[LBM_RMAX];                        // electrons released by the forward reaction
+  double beta_ct[LBM_RMAX];                      // symmetry factor of a charge transfer
+  int has_ct;
 };
 
 // launchers (lbm_kernels.hip)

@@ -68,14 +68,17 @@ def _z2(w):
     return w
 
 
+@pytest.mark.parametrize("kernel", ["specialized", "generic"])
 @pytest.mark.parametrize("case", list(CASES))
-def test_charge_transfer_and_transport_match_oracle(lbm, case):
+def test_charge_transfer_and_transport_match_oracle(lbm, case, kernel):
     """Butler-Volmer charge transfer on the TPB edge, the volumetric current and its
     integration along x into I^(a) and Phi_electrolyte, coupled back into the next
-    step's rates, over 30 steps."""
+    step's rates, over 30 steps, with the generated (from the second step) and the
+    generic chemistry kernel."""
     w = CASES[case]()
-    _log(f"case {case} N={w.N}")
+    _log(f"case {case} N={w.N} kernel={kernel}")
     lat = lbm.lattice_from_workload(w)
+    lat.set_chem_kernel(lbm.CHEM_SPECIALIZED if kernel == "specialized" else lbm.CHEM_GENERIC)
     o = Oracle(w)
     for chunk in (1, 9, 20):
         lat.step(chunk)
@@ -187,14 +190,16 @@ def test_packed_columns_with_their_own_electrode_potentials(lbm):
         off += c.nx
 
 
+@pytest.mark.parametrize("kernel", ["specialized", "generic"])
 @pytest.mark.parametrize("omega", [0.0, 2.0e-3])
-def test_electrical_energy_source_with_energy_lattice(lbm, omega):
+def test_electrical_energy_source_with_energy_lattice(lbm, omega, kernel):
     """The electrical work and ohmic heat of the charge transfer enter the unified internal
     energy (energy lattice on): temperature, populations' moments and charge outputs match
     the oracle over 25 steps, with and without electrolyte resistance."""
     w = synth.electrode_slab(nx=16, ny=2, energy=True, omega=omega, phi_ed=0.05)
-    _log(f"energy electrode omega={omega}")
+    _log(f"energy electrode omega={omega} kernel={kernel}")
     lat = lbm.lattice_from_workload(w)
+    lat.set_chem_kernel(lbm.CHEM_SPECIALIZED if kernel == "specialized" else lbm.CHEM_GENERIC)
     o = Oracle(w)
     for chunk in (1, 24):
         lat.step(chunk)
@@ -203,7 +208,8 @@ def test_electrical_energy_source_with_energy_lattice(lbm, omega):
     lat.close()
 
 
-def test_current_control_secant_matches_oracle(lbm):
+@pytest.mark.parametrize("kernel", ["specialized", "generic"])
+def test_current_control_secant_matches_oracle(lbm, kernel):
     """Current control: each step's electrode potential of every line is solved by the secant
     method for a target end current density (one target per line), then the step runs at
     it.  Potentials, fields and charge outputs match the oracle after every step, and the
@@ -216,6 +222,8 @@ def test_current_control_secant_matches_oracle(lbm):
     w.electrode["n_secant"] = 10
     o = Oracle(w)
     lats = [lbm.lattice_from_workload(w, stream=stream.cuda_stream) for _ in range(2)]
+    for lat in lats:
+        lat.set_chem_kernel(lbm.CHEM_SPECIALIZED if kernel == "specialized" else lbm.CHEM_GENERIC)
     lats[1].set_graph(2)
     for chunk in (1, 4, 4):
         o.step(chunk)
