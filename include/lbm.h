@@ -146,8 +146,7 @@ typedef struct {
    * the node, the mass-action constants become k_f exp(beta z F dPhi / (R_U T)) and
    * k_b exp(-(1 - beta) z F dPhi / (R_U T)) (dPhi = 0 without lbm_set_electrode), and the
    * step's volumetric current I^(v) = F l_TPB sum_r z_r xi_r / dt (A/m^3, extents xi_r per
-   * unit TPB length over the step) is kept for lbm_get_charge.  Mechanisms with charge
-   * transfer run the generic chemistry kernel.                                             */
+   * unit TPB length over the step) is kept for lbm_get_charge.                            */
   const int32_t *charge_z;
   const double *beta_ct;
 } lbm_mechanism;
