@@ -298,7 +298,8 @@ int lbm_get_timing(lbm_ctx *ctx, double *total_ms, double *species_ms, double *c
                    double *source_ms, double *mixture_ms);
 
 /* Snapshot of the complete state (populations, node records, coverages, step
- * counter): call with buf == NULL to query *size. */
+ * counter): call with buf == NULL to query *size.  Both return LBM_ESTATE while an
+ * electrode is installed (its potentials and currents are not part of a snapshot). */
 int lbm_save(lbm_ctx *ctx, void *buf, size_t *size);
 int lbm_load(lbm_ctx *ctx, const void *buf, size_t size);
 

@@ -1368,6 +1368,7 @@ int lbm_save(lbm_ctx *c, void *buf, size_t *size) {
 
 int lbm_load(lbm_ctx *c, const void *buf, size_t size) {
   if (!c || !buf || size < sizeof(SnapHeader)) return LBM_EINVAL;
+  if (c->electrode) return fail(c, LBM_ESTATE, "snapshots do not hold the electrode state");
   SnapHeader h;
   memcpy(&h, buf, sizeof(h));
   const size_t N = c->N, D = c->dim, M = c->M;

@@ -148,6 +148,11 @@ def test_charge_transfer_validation(lbm):
     lat = lbm.lattice_from_workload(w)
     with pytest.raises(lbm.LBMError):
         lat.save()
+    plain = lbm.lattice_from_workload(replace(w, electrode=None))
+    blob = plain.save()
+    plain.close()
+    with pytest.raises(lbm.LBMError):
+        lat.load(blob)
     with pytest.raises(lbm.LBMError):
         lat.set_electrode(0.1, np.full(w.nx, -1.0))
     lat.set_electrode(None, None)                     # off again: snapshots allowed
