@@ -58,13 +58,15 @@ def _check(lat, o):
 CASES = {
     "transfer_only_12x2": lambda: synth.electrode_slab(nx=12, ny=2, with_gas=False),
     "adsorption_transfer_desorption_37x3": lambda: synth.electrode_slab(nx=37, ny=3, omega=1.0e-3),
-    "z2_beta03_anodic_24x1": lambda: _z2(synth.electrode_slab(nx=24, ny=1, beta=0.3, phi_ed=0.08,
-                                                              omega=2.0e-3)),
+    "z2_beta03_anodic_24x1": lambda: _z(synth.electrode_slab(nx=24, ny=1, beta=0.3, phi_ed=0.08,
+                                                             omega=2.0e-3), 2),
+    "cathodic_zm1_beta07_20x2": lambda: _z(synth.electrode_slab(nx=20, ny=2, beta=0.7, phi_ed=-0.06,
+                                                                omega=2.0e-3), -1),
 }
 
 
-def _z2(w):
-    w.mech.charge_z = np.array([2, 0, 0], dtype=np.int32)
+def _z(w, z):
+    w.mech.charge_z = np.array([z, 0, 0], dtype=np.int32)
     return w
 
 
@@ -85,6 +87,7 @@ def test_charge_transfer_and_transport_match_oracle(lbm, case, kernel):
         o.step(chunk)
         _check(lat, o)
     assert np.max(np.abs(o.phi_el)) > 1e-3          # the coupling is exercised
+    assert np.all(np.sign(o.i_v) == np.sign(o._iv[0]))
     lat.close()
 
 
