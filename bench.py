@@ -196,10 +196,8 @@ def bench_c4_electrode(args, lbm, torch):
     electrode potential by the secant for its target current density (c4's 0..2 A/cm^2, at
     least 0.1), then integrates the charge transport along the column."""
     from workloads import synth
-    lengths, phis, currents = synth.config4_columns()
-    targets = np.maximum(np.asarray(currents, dtype=np.float64), 0.1) * 1.0e4     # A/m^2
-    cols = [synth.electrode_slab(nx=int(L), ny=1, phi=float(p_), lattice=1, kf=3.0e-2, kb=1.0e-2,
-                                 omega=1.0e-3) for L, p_ in zip(lengths, phis)]
+    cols, targets = synth.config4_electrode_cells()
+    lengths = [c.nx for c in cols]
     stream = torch.cuda.Stream()
     cat = lambda k: np.concatenate([getattr(c, k) for c in cols], axis=-1)
     w0 = cols[0]
@@ -209,7 +207,7 @@ def bench_c4_electrode(args, lbm, torch):
                       col_len=[int(L) for L in lengths], stream=stream.cuda_stream)
     lat.set_porous_field(cat("phi"), cat("tort"), w0.pore_radius)
     lat.set_mechanism(w0.mech)
-    lat.set_electrode(np.full(len(cols), 0.3), np.concatenate([c.electrode["omega"] for c in cols]))
+    lat.set_electrode([c.electrode["phi_ed"] for c in cols], np.concatenate([c.electrode["omega"] for c in cols]))
     lat.set_current_target(targets, args.n_secant)
     lat.set_graph(args.graph_steps)
     log(f"electrode cells: {len(cols)} columns, {N} nodes, {args.n_secant} secant updates; warmup {args.warmup}")

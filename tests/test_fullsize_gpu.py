@@ -136,3 +136,45 @@ def test_c4_full_batched_columns_vs_oracle(lbm):
         got = {k: np.asarray(f[k])[..., sl] for k in ("rho_a", "u", "P", "X", "j_a", "theta")}
         errs = _sample_compare(got, {k: m[k] for k in got}, got.keys())
         _log(f"c4 column {c_idx} (L={c.nx}, i={c.meta['current_A_cm2']:.2f} A/cm2): {errs}")
+
+
+def test_c4_electrode_cells_full_size_vs_oracle(lbm):
+    """The c4_electrode benchmark configuration (64 ragged electrode cells, current control
+    with 6 secant updates, graph step loop of 32 steps): after 33 steps (one plain step,
+    one graph replay) three whole cells (first, longest, last) match their oracle runs,
+    potentials and charge outputs included."""
+    import torch
+    stream = torch.cuda.Stream()
+    cells, targets = synth.config4_electrode_cells()
+    lengths = [c.nx for c in cells]
+    cat = lambda k: np.concatenate([getattr(c, k) for c in cells], axis=-1)
+    w0 = cells[0]
+    lat = lbm.Lattice(1, int(sum(lengths)), 1, 1, w0.molar_mass, w0.D_ref_lat, cat("X0"), cat("T0"),
+                      cat("P0"), T_ref=w0.T_ref, bc_lo=w0.bc_lo, bc_hi=w0.bc_hi, col_len=lengths,
+                      stream=stream.cuda_stream)
+    lat.set_porous_field(cat("phi"), cat("tort"), w0.pore_radius)
+    lat.set_mechanism(w0.mech)
+    lat.set_electrode([c.electrode["phi_ed"] for c in cells], np.concatenate([c.electrode["omega"] for c in cells]))
+    lat.set_current_target(targets, 6)
+    lat.set_graph(32)
+    steps = 33
+    lat.step(steps)
+    f = lat.fields()
+    iv, ia, pel = lat.charge()
+    pot = lat.electrode_potential()
+    lat.close()
+    offs = np.concatenate([[0], np.cumsum(lengths)])
+    for c_idx in (0, int(np.argmax(lengths)), len(cells) - 1):
+        c = cells[c_idx]
+        c.electrode["target_ia"] = targets[c_idx]
+        c.electrode["n_secant"] = 6
+        o = Oracle(c)
+        o.step(steps)
+        m = o.moments()
+        sl = slice(int(offs[c_idx]), int(offs[c_idx + 1]))
+        got = {k: np.asarray(f[k])[..., sl] for k in ("rho_a", "u", "P", "X", "j_a", "theta")}
+        got.update(iv=iv[sl], ia=ia[sl], pel=pel[sl], pot=np.array([pot[c_idx]]))
+        ref = {k: m[k] for k in ("rho_a", "u", "P", "X", "j_a", "theta")}
+        ref.update(iv=o.i_v, ia=o.i_a, pel=o.phi_el, pot=o.ped)
+        errs = _sample_compare(got, ref, got.keys())
+        _log(f"electrode cell {c_idx} (L={c.nx}, target {targets[c_idx]:.0f} A/m2): {errs}")

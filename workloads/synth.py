@@ -420,6 +420,18 @@ def config4_columns(seed: int = 4, n_cols: int = 64, lmin: int = 200, lmax: int 
     return lengths, phis, currents
 
 
+def config4_electrode_cells(seed: int = 4):
+    """The 64 ragged c4 column lengths and porosities as closed D1Q3 electrode cells
+    (electrode_slab with slow kinetics kf 3e-2, kb 1e-2, resistivity 1e-3 Ohm m, initial
+    electrode potential 0.3 V), each with a target area current density: c4's currents,
+    at least 0.1 A/cm^2, in A/m^2.  Returns (cells, targets)."""
+    lengths, phis, currents = config4_columns(seed)
+    cells = [electrode_slab(nx=int(L), ny=1, phi=float(p_), lattice=1, kf=3.0e-2, kb=1.0e-2,
+                            omega=1.0e-3, phi_ed=0.3) for L, p_ in zip(lengths, phis)]
+    targets = np.maximum(np.asarray(currents, dtype=np.float64), 0.1) * 1.0e4
+    return cells, targets
+
+
 def config4_column(length: int, phi: float, current_A_cm2: float, seed: int = 4,
                    steps: int = 50000, n_sub: int = 1, n_newton: int = 2,
                    n_util: int = 2, delta_util: float = 2e-6) -> Workload:
