@@ -558,16 +558,15 @@ int enqueue_step(lbm_ctx *c, int record_slot) {
       sp.ped = c->ped;
       sp.stage = 0;
       sp.final_iter = 0;
-      HIPCHK(c, launch_secant(sp, true, c->stream));
+      HIPCHK(c, launch_secant_start(sp, c->stream));
       for (int it = 0; it <= c->n_secant; ++it) {
         if (c->chem_fn)
           HIPCHK(c, launch_chem_specialized(c->chem_fn, tp, c->stream));
         else
           HIPCHK(c, launch_chem(tp, c->stream));
-        HIPCHK(c, launch_charge(tq, c->stream));
         sp.stage = it == 0 ? 0 : 1;
         sp.final_iter = it == c->n_secant ? 1 : 0;
-        HIPCHK(c, launch_secant(sp, false, c->stream));
+        HIPCHK(c, launch_charge(tq, &sp, c->stream));   // integrates the trial and takes the secant step
       }
     }
     if (c->chem_fn)
@@ -584,7 +583,7 @@ int enqueue_step(lbm_ctx *c, int record_slot) {
     q.omega = c->omega_n;
     q.ia = c->ia;
     q.pel = c->pel;
-    HIPCHK(c, launch_charge(q, c->stream));
+    HIPCHK(c, launch_charge(q, nullptr, c->stream));
   }
   if (ev) HIPCHK(c, hipEventRecord(ev[2], c->stream));
   if (ev) HIPCHK(c, hipEventRecord(ev[3], c->stream));   // no separate source pass (added at the pull)

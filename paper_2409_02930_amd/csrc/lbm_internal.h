@@ -180,8 +180,8 @@ hipError_t launch_init(int dim, const InitParams &ip, hipStream_t s);
 hipError_t launch_species(int dim, const KParams &p, hipStream_t s);
 hipError_t launch_mixture(int dim, const KParams &p, hipStream_t s);
 hipError_t launch_chem(const ChemParams &cp, hipStream_t s);
-hipError_t launch_charge(const ChargeParams &q, hipStream_t s);
-hipError_t launch_secant(const SecantParams &sp, bool start, hipStream_t s);
+hipError_t launch_charge(const ChargeParams &q, const SecantParams *sp, hipStream_t s);   // sp: trial
+hipError_t launch_secant_start(const SecantParams &sp, hipStream_t s);
 hipError_t launch_surface_energy(const KParams &p, hipStream_t s);
 hipError_t launch_moments(int dim, const KParams &p, double *out, hipStream_t s);
 hipError_t launch_diag(int dim, int L, int Mmom, const KParams &p, const void *pop, double *partials,

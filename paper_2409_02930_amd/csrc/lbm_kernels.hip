@@ -1428,6 +1428,42 @@ hipError_t launch_surface_energy(const KParams &p, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Current control (secant on each line's electrode potential): k_secant_start takes the
+// line's present potential as the first iterate; k_secant reads the trial's end current
+// I^(a) - target and forms the next iterate (stage 0: 10 mV above the first; stage 1: the
+// secant update, none where the two last currents are equal), then fills the trial (or,
+// for the final iterate, the step's) electrode potential of the line's nodes.
+// One block per line: every thread forms the line's iterate (the same arithmetic), thread
+// 0 stores the state once all have read it, and the block fills the line's nodes.
+__global__ __launch_bounds__(256) void k_secant_start(const SecantParams s) {
+  const int l = blockIdx.x;
+  const double p = s.phi_line[l];
+  if (threadIdx.x == 0) s.p0[l] = p;
+  for (int n = s.off[l] + (int)threadIdx.x; n < s.off[l + 1]; n += 256) s.ped_try[n] = p;
+}
+
+__device__ __forceinline__ void secant_line(const SecantParams &s, int l, double ia_end) {
+  const int b = s.off[l], e = s.off[l + 1];
+  const double f = ia_end - s.target[l];
+  const double p0 = s.p0[l], p1 = s.p1[l], f0 = s.f0[l];
+  double p;
+  if (s.stage == 0) {
+    p = p0 + 0.01;
+  } else {
+    const double d = f - f0;
+    p = d != 0.0 ? p1 - f * (p1 - p0) / d : p1;
+  }
+  __syncthreads();                              // every thread has read the state
+  if (threadIdx.x == 0) {
+    if (s.stage != 0) s.p0[l] = p1;
+    s.f0[l] = f;
+    s.p1[l] = p;
+    if (s.final_iter) s.phi_line[l] = p;
+  }
+  double *dst = s.final_iter ? s.ped : s.ped_try;
+  for (int n = b + (int)threadIdx.x; n < e; n += 256) dst[n] = p;
+}
+
 // Inclusive sum over the 256 threads of a block (Hillis-Steele in LDS); every thread
 // also receives the block total.
 __device__ __forceinline__ double block_scan256(double v, double *s, double &total) {
@@ -1450,7 +1486,10 @@ __device__ __forceinline__ double block_scan256(double v, double *s, double &tot
 // eqs areaCurrentDensity and electrolytePotential: one block per line, I^(a) and
 // Phi_electrolyte as prefix sums along x from the line's first node (Phi = 0 before
 // it), 256 cells at a time with the running totals carried.
-__global__ __launch_bounds__(256) void k_charge(const ChargeParams q) {
+// SEC: a trial of the current control; the block then also takes the line's secant
+// step (k_secant below, fused so the trial costs one launch fewer).
+template <bool SEC>
+__global__ __launch_bounds__(256) void k_charge(const ChargeParams q, const SecantParams sp) {
   __shared__ double s[256];
   const int line = blockIdx.x;
   const int b = q.off[line], e = q.off[line + 1];
@@ -1468,55 +1507,19 @@ __global__ __launch_bounds__(256) void k_charge(const ChargeParams q) {
       q.pel[n] = pel;
     }
   }
+  if constexpr (SEC) secant_line(sp, line, cia);    // cia: I^(a) at the line's last node
 }
 
-// Current control (secant on each line's electrode potential): k_secant_start takes the
-// line's present potential as the first iterate; k_secant reads the trial's end current
-// I^(a) - target and forms the next iterate (stage 0: 10 mV above the first; stage 1: the
-// secant update, none where the two last currents are equal), then fills the trial (or,
-// for the final iterate, the step's) electrode potential of the line's nodes.
-// One block per line: every thread forms the line's iterate (the same arithmetic), thread
-// 0 stores the state once all have read it, and the block fills the line's nodes.
-__global__ __launch_bounds__(256) void k_secant_start(const SecantParams s) {
-  const int l = blockIdx.x;
-  const double p = s.phi_line[l];
-  if (threadIdx.x == 0) s.p0[l] = p;
-  for (int n = s.off[l] + (int)threadIdx.x; n < s.off[l + 1]; n += 256) s.ped_try[n] = p;
-}
-
-__global__ __launch_bounds__(256) void k_secant(const SecantParams s) {
-  const int l = blockIdx.x;
-  const int b = s.off[l], e = s.off[l + 1];
-  const double f = s.ia[e - 1] - s.target[l];
-  const double p0 = s.p0[l], p1 = s.p1[l], f0 = s.f0[l];
-  double p;
-  if (s.stage == 0) {
-    p = p0 + 0.01;
-  } else {
-    const double d = f - f0;
-    p = d != 0.0 ? p1 - f * (p1 - p0) / d : p1;
-  }
-  __syncthreads();                              // every thread has read the state
-  if (threadIdx.x == 0) {
-    if (s.stage != 0) s.p0[l] = p1;
-    s.f0[l] = f;
-    s.p1[l] = p;
-    if (s.final_iter) s.phi_line[l] = p;
-  }
-  double *dst = s.final_iter ? s.ped : s.ped_try;
-  for (int n = b + (int)threadIdx.x; n < e; n += 256) dst[n] = p;
-}
-
-hipError_t launch_secant(const SecantParams &sp, bool start, hipStream_t s) {
-  if (start)
-    hipLaunchKernelGGL(k_secant_start, dim3(sp.lines), dim3(256), 0, s, sp);
-  else
-    hipLaunchKernelGGL(k_secant, dim3(sp.lines), dim3(256), 0, s, sp);
+hipError_t launch_secant_start(const SecantParams &sp, hipStream_t s) {
+  hipLaunchKernelGGL(k_secant_start, dim3(sp.lines), dim3(256), 0, s, sp);
   return hipGetLastError();
 }
 
-hipError_t launch_charge(const ChargeParams &q, hipStream_t s) {
-  hipLaunchKernelGGL(k_charge, dim3(q.lines), dim3(256), 0, s, q);
+hipError_t launch_charge(const ChargeParams &q, const SecantParams *sp, hipStream_t s) {
+  if (sp)
+    hipLaunchKernelGGL(k_charge<true>, dim3(q.lines), dim3(256), 0, s, q, *sp);
+  else
+    hipLaunchKernelGGL(k_charge<false>, dim3(q.lines), dim3(256), 0, s, q, SecantParams{});
   return hipGetLastError();
 }
 
