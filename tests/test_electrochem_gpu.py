@@ -138,7 +138,8 @@ def test_charge_transfer_without_electrode_has_zero_potential(lbm):
 
 def test_charge_transfer_validation(lbm):
     """Host validation: charge only on TPB edge reactions, beta_ct in [0, 1] and required,
-    no charge transport on packed columns, no snapshot while the electrode is on."""
+    resistivity >= 0, current control only with an electrode and 1..64 secant updates, no
+    snapshot save or load while the electrode is on."""
     w = synth.electrode_slab(nx=6, ny=2)
     bad = [replace(w.mech, charge_z=np.array([0, 1, 0], dtype=np.int32)),     # a surface reaction
            replace(w.mech, beta_ct=np.array([1.5, 0.5, 0.5])),
@@ -158,7 +159,15 @@ def test_charge_transfer_validation(lbm):
         lat.load(blob)
     with pytest.raises(lbm.LBMError):
         lat.set_electrode(0.1, np.full(w.nx, -1.0))
+    with pytest.raises(lbm.LBMError):
+        lat.set_current_target(1.0e6, 0)              # n_secant must lie in 1..64
+    lat.set_current_target(1.0e6, 3)
+    lat.set_current_target(None)                      # off
     lat.set_electrode(None, None)                     # off again: snapshots allowed
+    with pytest.raises(lbm.LBMError):
+        lat.set_current_target(1.0e6, 3)              # needs an electrode
+    with pytest.raises(lbm.LBMError):
+        lat.electrode_potential()
     lat.save()
     lat.close()
 
