@@ -208,8 +208,8 @@ int lbm_set_faradaic_source(lbm_ctx *ctx, const double *rate, int32_t fuel, int3
  * Phi_electrolyte(x) = sum I^(a) Omega dx; the next step's charge-transfer rates see
  * dPhi = phi_electrode - Phi_electrolyte(x) (dPhi = phi_electrode before the first
  * integration).  May be called between steps (e.g. to sweep the potential: the
- * electrolyte potential is kept); it drops a captured step graph.  The electrode state is
- * not part of snapshots (lbm_save returns LBM_ESTATE while the coupling is on).            */
+ * electrolyte potential is kept); it drops a captured step graph.  Snapshots (lbm_save)
+ * carry the electrode state.                                                              */
 int lbm_set_electrode(lbm_ctx *ctx, const double *phi_electrode, const double *omega);
 
 /* Copies to host [N] arrays (each may be NULL) the last step's volumetric current I^(v)
@@ -298,8 +298,10 @@ int lbm_get_timing(lbm_ctx *ctx, double *total_ms, double *species_ms, double *c
                    double *source_ms, double *mixture_ms);
 
 /* Snapshot of the complete state (populations, node records, coverages, step
- * counter): call with buf == NULL to query *size.  Both return LBM_ESTATE while an
- * electrode is installed (its potentials and currents are not part of a snapshot). */
+ * counter, and with an electrode installed its electrolyte potential, currents and
+ * electrode potentials): call with buf == NULL to query *size.  Loading needs a context
+ * set up the same way (lattice, mechanism, electrode coupling installed or not; the
+ * resistivity, targets and other settings are configuration, not state). */
 int lbm_save(lbm_ctx *ctx, void *buf, size_t *size);
 int lbm_load(lbm_ctx *ctx, const void *buf, size_t size);
 

@@ -1316,7 +1316,7 @@ namespace {
 struct SnapHeader {
   uint64_t magic, N, L, Q, M, K, D;
   int64_t steps_done;
-  int32_t first_step, have_perm, fp32, pad1;
+  int32_t first_step, have_perm, fp32, electrode;
   int32_t perm[16];          // elimination order of the specialised chemistry kernel
 };
 constexpr uint64_t kMagic = 0x324d424c5844ull;
@@ -1324,11 +1324,12 @@ constexpr uint64_t kMagic = 0x324d424c5844ull;
 
 int lbm_save(lbm_ctx *c, void *buf, size_t *size) {
   if (!c || !size) return LBM_EINVAL;
-  if (c->electrode) return fail(c, LBM_ESTATE, "snapshots do not hold the electrode state");
   const size_t N = c->N, D = c->dim, M = c->M;
   const size_t npop = pop_words(c);
   const size_t nrec = (size_t)kRec * N + (c->energy ? N : 0) + (c->has_mech ? (size_t)c->K * N : 0);
-  const size_t need = sizeof(SnapHeader) + sizeof(double) * (npop + nrec);
+  // electrode state: electrolyte potential, currents, electrode potential per node and per line
+  const size_t nel = c->electrode ? 4 * N + (size_t)c->n_lines : 0;
+  const size_t need = sizeof(SnapHeader) + sizeof(double) * (npop + nrec + nel);
   if (!buf) {
     *size = need;
     return LBM_OK;
@@ -1347,6 +1348,7 @@ int lbm_save(lbm_ctx *c, void *buf, size_t *size) {
   h.first_step = c->first_step;
   h.have_perm = c->have_perm;
   h.fp32 = c->fp32;
+  h.electrode = c->electrode;
   memcpy(h.perm, c->chem_perm, sizeof(h.perm));
   memcpy(buf, &h, sizeof(h));
   double *o = (double *)((char *)buf + sizeof(h));
@@ -1360,23 +1362,37 @@ int lbm_save(lbm_ctx *c, void *buf, size_t *size) {
     HIPCHK(c, hipMemcpy(o, c->T[q_last], sizeof(double) * N, hipMemcpyDeviceToHost));
     o += N;
   }
-  if (c->has_mech) HIPCHK(c, hipMemcpy(o, c->theta, sizeof(double) * c->K * N, hipMemcpyDeviceToHost));
+  if (c->has_mech) {
+    HIPCHK(c, hipMemcpy(o, c->theta, sizeof(double) * c->K * N, hipMemcpyDeviceToHost));
+    o += (size_t)c->K * N;
+  }
+  if (c->electrode) {
+    const double *src[] = {c->pel, c->iv, c->ia, c->ped};
+    for (const double *s : src) {
+      HIPCHK(c, hipMemcpy(o, s, sizeof(double) * N, hipMemcpyDeviceToHost));
+      o += N;
+    }
+    HIPCHK(c, hipMemcpy(o, c->d_phi_line, sizeof(double) * c->n_lines, hipMemcpyDeviceToHost));
+  }
   *size = need;
   return LBM_OK;
 }
 
 int lbm_load(lbm_ctx *c, const void *buf, size_t size) {
   if (!c || !buf || size < sizeof(SnapHeader)) return LBM_EINVAL;
-  if (c->electrode) return fail(c, LBM_ESTATE, "snapshots do not hold the electrode state");
   SnapHeader h;
   memcpy(&h, buf, sizeof(h));
   const size_t N = c->N, D = c->dim, M = c->M;
   if (h.magic != kMagic || h.N != N || h.L != (uint64_t)c->L || h.Q != (uint64_t)c->Q || h.M != M ||
       h.D != D || h.K != (uint64_t)c->K || h.fp32 != c->fp32)
     return fail(c, LBM_EINVAL, "snapshot does not match this context");
+  if (h.electrode != c->electrode)
+    return fail(c, LBM_EINVAL, "snapshot and context differ in the electrode coupling (install it before loading)");
   const size_t npop = pop_words(c);
   const size_t nrec = (size_t)kRec * N + (c->energy ? N : 0) + (c->has_mech ? (size_t)c->K * N : 0);
-  if (size < sizeof(SnapHeader) + sizeof(double) * (npop + nrec)) return fail(c, LBM_EINVAL, "snapshot truncated");
+  const size_t nel = c->electrode ? 4 * N + (size_t)c->n_lines : 0;
+  if (size < sizeof(SnapHeader) + sizeof(double) * (npop + nrec + nel))
+    return fail(c, LBM_EINVAL, "snapshot truncated");
   drop_graph(c);
   c->steps_done = h.steps_done;
   c->first_step = h.first_step;
@@ -1396,7 +1412,18 @@ int lbm_load(lbm_ctx *c, const void *buf, size_t size) {
     HIPCHK(c, hipMemcpy(c->T[q_last], o, sizeof(double) * N, hipMemcpyHostToDevice));
     o += N;
   }
-  if (c->has_mech) HIPCHK(c, hipMemcpy(c->theta, o, sizeof(double) * c->K * N, hipMemcpyHostToDevice));
+  if (c->has_mech) {
+    HIPCHK(c, hipMemcpy(c->theta, o, sizeof(double) * c->K * N, hipMemcpyHostToDevice));
+    o += (size_t)c->K * N;
+  }
+  if (c->electrode) {
+    double *dst[] = {c->pel, c->iv, c->ia, c->ped};
+    for (double *d : dst) {
+      HIPCHK(c, hipMemcpy(d, o, sizeof(double) * N, hipMemcpyHostToDevice));
+      o += N;
+    }
+    HIPCHK(c, hipMemcpy(c->d_phi_line, o, sizeof(double) * c->n_lines, hipMemcpyHostToDevice));
+  }
   return LBM_OK;
 }
 

@@ -139,7 +139,7 @@ def test_charge_transfer_without_electrode_has_zero_potential(lbm):
 def test_charge_transfer_validation(lbm):
     """Host validation: charge only on TPB edge reactions, beta_ct in [0, 1] and required,
     resistivity >= 0, current control only with an electrode and 1..64 secant updates, no
-    snapshot save or load while the electrode is on."""
+    loading a snapshot taken without the electrode into a context with one."""
     w = synth.electrode_slab(nx=6, ny=2)
     bad = [replace(w.mech, charge_z=np.array([0, 1, 0], dtype=np.int32)),     # a surface reaction
            replace(w.mech, beta_ct=np.array([1.5, 0.5, 0.5])),
@@ -150,13 +150,11 @@ def test_charge_transfer_validation(lbm):
             lat.set_mechanism(m)
         lat.close()
     lat = lbm.lattice_from_workload(w)
-    with pytest.raises(lbm.LBMError):
-        lat.save()
     plain = lbm.lattice_from_workload(replace(w, electrode=None))
     blob = plain.save()
     plain.close()
     with pytest.raises(lbm.LBMError):
-        lat.load(blob)
+        lat.load(blob)                                # snapshot without the electrode state
     with pytest.raises(lbm.LBMError):
         lat.set_electrode(0.1, np.full(w.nx, -1.0))
     with pytest.raises(lbm.LBMError):
@@ -252,3 +250,28 @@ def test_current_control_secant_matches_oracle(lbm, kernel):
             assert np.allclose(ia[o.line_end], target, rtol=1e-11, atol=0)
     for lat in lats:
         lat.close()
+
+
+def test_snapshot_round_trip_with_electrode_and_current_control(lbm):
+    """Save after 7 steps, continue 9 steps; a fresh context set up the same way loads the
+    snapshot and runs the same 9 steps: fields, charge outputs and electrode potentials are
+    bitwise equal (the electrode state travels with the snapshot)."""
+    w = synth.electrode_slab(nx=12, ny=2, omega=5e-3)
+    w.electrode["target_ia"] = np.array([1.0e6, 1.5e6])
+    w.electrode["n_secant"] = 5
+    a = lbm.lattice_from_workload(w)
+    a.step(7)
+    blob = a.save()
+    a.step(9)
+    fa, ca, pa = a.fields(), a.charge(), a.electrode_potential()
+    a.close()
+    b = lbm.lattice_from_workload(w)
+    b.load(blob)
+    b.step(9)
+    fb, cb, pb = b.fields(), b.charge(), b.electrode_potential()
+    b.close()
+    for k in KEYS:
+        assert np.array_equal(np.asarray(fa[k]), np.asarray(fb[k])), k
+    for x, y in zip(ca, cb):
+        assert np.array_equal(x, y)
+    assert np.array_equal(pa, pb)
