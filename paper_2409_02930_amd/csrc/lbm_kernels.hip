@@ -1464,23 +1464,25 @@ __device__ __forceinline__ void secant_line(const SecantParams &s, int l, double
   for (int n = b + (int)threadIdx.x; n < e; n += 256) dst[n] = p;
 }
 
-// Inclusive sum over the 256 threads of a block (Hillis-Steele in LDS); every thread
-// also receives the block total.
+// Inclusive sum over the 256 threads of a block: each wave scans with lane shifts
+// (no barrier), the four wave totals meet in LDS; every thread also receives the
+// block total.
 __device__ __forceinline__ double block_scan256(double v, double *s, double &total) {
-  const int t = threadIdx.x;
-  __syncthreads();                              // earlier readers of s are done
-  s[t] = v;
-  __syncthreads();
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
 #pragma unroll
-  for (int off = 1; off < 256; off <<= 1) {
-    const double add = t >= off ? s[t - off] : 0.0;
-    __syncthreads();
-    v += add;
-    s[t] = v;
-    __syncthreads();
+  for (int off = 1; off < 64; off <<= 1) {
+    const double u = __shfl_up(v, off, 64);
+    if (lane >= off) v += u;
   }
-  total = s[255];
-  return v;
+  __syncthreads();                              // earlier readers of s are done
+  if (lane == 63) s[wv] = v;
+  __syncthreads();
+  double before = 0.0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+    if (k < wv) before += s[k];
+  total = ((s[0] + s[1]) + s[2]) + s[3];
+  return before + v;
 }
 
 // eqs areaCurrentDensity and electrolytePotential: one block per line, I^(a) and
@@ -1494,13 +1496,17 @@ __global__ __launch_bounds__(256) void k_charge(const ChargeParams q, const Seca
   const int line = blockIdx.x;
   const int b = q.off[line], e = q.off[line + 1];
   double cia = 0.0, cpel = 0.0;                 // totals of the cells before this chunk
-  for (int c0 = b; c0 < e; c0 += 256) {
-    const int n = c0 + (int)threadIdx.x;
+  int n = b + (int)threadIdx.x;
+  double ivn = n < e ? q.iv[n] : 0.0, omn = n < e ? q.omega[n] : 0.0;
+  for (int c0 = b; c0 < e; c0 += 256, n += 256) {
     const bool in = n < e;
+    const double ivc = ivn, omc = omn;
+    ivn = n + 256 < e ? q.iv[n + 256] : 0.0;    // the next chunk's loads cross this chunk's barriers
+    omn = n + 256 < e ? q.omega[n + 256] : 0.0;
     double tot;
-    const double ia = cia + block_scan256(in ? q.iv[n] * q.dx : 0.0, s, tot);
+    const double ia = cia + block_scan256(in ? ivc * q.dx : 0.0, s, tot);
     cia += tot;
-    const double pel = cpel + block_scan256(in ? ia * q.omega[n] * q.dx : 0.0, s, tot);
+    const double pel = cpel + block_scan256(in ? ia * omc * q.dx : 0.0, s, tot);
     cpel += tot;
     if (in) {
       q.ia[n] = ia;
