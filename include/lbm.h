@@ -15,7 +15,11 @@
  *   - optionally the local heterogeneous surface-reaction source that couples
  *     gas and adsorbed species: Section 4, eqs totalFluidReactionRate,
  *     molarToMassRates, surfaceMoleFractions, totalSurfaceReactionRate,
- *     rho_pc, fsourceHetero.
+ *     rho_pc, fsourceHetero;
+ *   - optionally charge transfer at the triple-phase boundary with the 1-D
+ *     charge transport along x, the electrical energy source and current
+ *     control by the electrode potential: Sections 4.1-4.2, eqs
+ *     volumetricCurrent, areaCurrentDensity, electrolytePotential.
  *
  * Conventions
  *   - Every entry point returns an lbm_status; nothing throws or aborts across
