@@ -682,3 +682,41 @@ def test_current_control_reaches_the_target_on_every_line():
         o.step(1)
         assert np.allclose(o.i_a[o.line_end], target, rtol=1e-12, atol=0)
         assert o.ped[1] > o.ped[0]
+
+
+def test_faradaic_source_moves_the_prescribed_moles():
+    """R26 against a mole balance: in a periodic D1Q3 column (streaming and collision keep
+    every species' total), one step changes the fuel total by minus and the product total by
+    plus sum_n rate_n dt moles (per unit lattice volume), the other species not at all."""
+    w = synth.config4_column(40, 0.4, 1.5)
+    w = replace(w, bc_lo=synth.BC_PERIODIC, bc_hi=synth.BC_PERIODIC, mech=None, inlet_lo_X=None)
+    o = lo.Oracle(w)
+    before = o.fa.sum(axis=(1, 2))
+    o.step(1)
+    moles = (o.fa.sum(axis=(1, 2)) - before) * o.rho_unit / o.m
+    fu, pr = w.faradaic_species
+    expect = np.asarray(w.faradaic_rate).sum() * o.dt
+    assert expect > 0
+    assert abs(moles[fu] + expect) <= 1e-9 * expect and abs(moles[pr] - expect) <= 1e-9 * expect
+    others = [a for a in range(w.M) if a not in (fu, pr)]
+    assert np.all(np.abs(moles[others]) <= 1e-12 * expect)
+
+
+def test_inlet_and_outflow_keep_a_matching_rest_state():
+    """R17, R18 on rest states: with the whole domain at the inlet's composition, pressure and
+    temperature and at rest, an inlet at x = 0 and an outflow at x = nx - 1 (porosity 0.45)
+    leave every field unchanged for 30 steps (the inlet equilibrium at the node's zero
+    velocity equals the state it replaces: a wrong composition, pressure, temperature or
+    porosity factor there fails)."""
+    w = synth.config5(nx=24, ny=4, steps=10, porosity="uniform")
+    N = w.N
+    X = np.repeat(np.asarray(w.inlet_lo_X)[:, None], N, axis=1)
+    w = replace(w, X0=X, P0=np.full(N, w.inlet_P), T0=np.full(N, w.inlet_T))
+    assert w.bc_lo == synth.BC_INLET and w.bc_hi == synth.BC_OUTFLOW
+    o = lo.Oracle(w)
+    m0 = o.moments()
+    o.step(30)
+    m1 = o.moments()
+    for k in ("rho_a", "P", "X"):
+        assert np.max(np.abs(np.asarray(m1[k]) - np.asarray(m0[k]))) <= 1e-13 * np.max(np.abs(m0[k])), k
+    assert np.max(np.abs(m1["u"])) <= 1e-15
