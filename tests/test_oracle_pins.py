@@ -720,3 +720,28 @@ def test_inlet_and_outflow_keep_a_matching_rest_state():
     for k in ("rho_a", "P", "X"):
         assert np.max(np.abs(np.asarray(m1[k]) - np.asarray(m0[k]))) <= 1e-13 * np.max(np.abs(m0[k])), k
     assert np.max(np.abs(m1["u"])) <= 1e-15
+
+
+def test_inlet_and_outflow_keep_a_matching_uniform_flow():
+    """R17, R18 with velocity: the domain at the inlet's composition, pressure and temperature,
+    every lattice at its equilibrium moving with u = 0.02 along x (Knudsen off, uniform
+    porosity, so a periodic domain would keep it), an inlet at x = 0 and an outflow at
+    x = nx - 1: 30 steps change nothing.  An inlet equilibrium at rest instead of the node's
+    velocity, or an outflow that copies another direction, fails."""
+    w = synth.config5(nx=24, ny=4, steps=10, porosity="uniform")
+    N = w.N
+    X = np.repeat(np.asarray(w.inlet_lo_X)[:, None], N, axis=1)
+    w = replace(w, X0=X, P0=np.full(N, w.inlet_P), T0=np.full(N, w.inlet_T), pore_radius=float("inf"))
+    o = lo.Oracle(w)
+    RaT = o.RaT(o.T_field)
+    rho_a = X * (w.P0 / w.P_ref)[None, :] / RaT
+    v = [np.full(N, 0.02 / o.phi[0]), np.zeros(N)]
+    o.fa = np.stack([o.species_eq(o.phi * rho_a[a], v, RaT[a]) for a in range(o.M)])
+    Y, _, _ = o.composition(rho_a)
+    RT = (Y * RaT).sum(axis=0)
+    o.f = (o.phi * rho_a.sum(axis=0)) * lo.product_form(o.c, v, [RT + v[d] ** 2 for d in range(o.D)])
+    m0 = o.moments()
+    o.step(30)
+    m1 = o.moments()
+    for k in ("rho_a", "P", "X", "u", "j_a"):
+        assert np.max(np.abs(np.asarray(m1[k]) - np.asarray(m0[k]))) <= 1e-13 * np.max(np.abs(m0[k])), k
