@@ -82,6 +82,13 @@ Readings adopted where the paper is silent, garbled or self-inconsistent
       target: secant iterates start at the line's present potential and 10 mV
       above it, a fixed number of updates, none where the two last currents
       are equal; the step then runs at the last iterate.
+
+Pins: tests/test_oracle_pins.py checks this code against statements independent of it
+(conservation, closed forms, equilibria, continuum models, marginalisation, mole and
+charge balances).  Parity unpinned (no pin of their own, covered by the GPU parity tests
+only): R5, R10, R11, R19, R24, the kinetic-energy term of R7, the mirror ghost of R9 at
+non-periodic ends, R20's pointwise use of a varying porosity, and which upstream node
+the outflow of R18 copies from.
 """
 from __future__ import annotations
 
