@@ -745,3 +745,56 @@ def test_inlet_and_outflow_keep_a_matching_uniform_flow():
     m1 = o.moments()
     for k in ("rho_a", "P", "X", "u", "j_a"):
         assert np.max(np.abs(np.asarray(m1[k]) - np.asarray(m0[k]))) <= 1e-13 * np.max(np.abs(m0[k])), k
+
+
+def test_absent_species_changes_nothing():
+    """R19 by marginalisation: a third species with zero density everywhere (18 g/mol, not the
+    lightest, so the unit system is unchanged) stays at zero and leaves the binary run of
+    the other two unchanged, Knudsen drag on, 20 steps, to 1e-13 (an unguarded division by
+    rho_a = 0 gives NaN; a nonzero quasi-equilibrium for it moves mass)."""
+    w2 = synth.config1(nx=16, ny=4)
+    m3 = np.array([2.0, 28.0, 18.0])
+    D3 = synth.synthetic_D_ref(m3)
+    D3[:2, :2] = w2.D_ref_lat
+    w3 = replace(w2, molar_mass=m3 * 1e-3, D_ref_lat=D3, X0=np.vstack([w2.X0, np.zeros(w2.N)]))
+    a, b = lo.Oracle(w2), lo.Oracle(w3)
+    a.step(20)
+    b.step(20)
+    ma, mb = a.moments(), b.moments()
+    for k in ("rho_a", "j_a"):
+        ra, rb = np.asarray(ma[k]), np.asarray(mb[k])
+        assert np.max(np.abs(rb[:2] - ra)) <= 1e-13 * np.max(np.abs(ra)), k
+        assert np.all(rb[2] == 0.0), k
+    for k in ("u", "P"):
+        assert np.max(np.abs(np.asarray(mb[k]) - np.asarray(ma[k]))) <= 1e-13 * max(np.max(np.abs(ma[k])), 1e-3), k
+
+
+def test_temperature_of_a_moving_mixture():
+    """R7 with the energy equilibrium's pinned zeroth moment phi rho (U + v^2/2): a uniform
+    binary mixture moving at u = (0.03, -0.01) in porosity 0.4 (v = u / phi), every lattice at
+    its moving equilibrium at 1073 K, periodic, Knudsen off: the temperature read back from
+    the energy lattice is 1073 K at the start and after 5 steps (1e-12), and the flow keeps
+    its velocity.  Reading the kinetic energy with u instead of v = u / phi fails."""
+    R_U = lo.R_U
+    w = synth.config1(nx=8, ny=4, pore_radius=float("inf"))
+    N = w.N
+    m = np.asarray(w.molar_mass)
+    X = np.stack([np.full(N, 0.5), np.full(N, 0.5)])
+    w = replace(w, X0=X, energy_on=True, cv=2.5 * R_U / m, u_form=np.zeros(2))
+    o = lo.Oracle(w)
+    RaT = o.RaT(o.T_field)
+    rho_a = X * (w.P0 / w.P_ref)[None, :] / RaT
+    u = (0.03, -0.01)
+    v = [np.full(N, u[0] / o.phi[0]), np.full(N, u[1] / o.phi[0])]
+    o.fa = np.stack([o.species_eq(o.phi * rho_a[a], v, RaT[a]) for a in range(o.M)])
+    Y, _, _ = o.composition(rho_a)
+    RT = (Y * RaT).sum(axis=0)
+    rho = rho_a.sum(axis=0)
+    o.f = (o.phi * rho) * lo.product_form(o.c, v, [RT + v[d] ** 2 for d in range(o.D)])
+    U = (Y * (o.uf_lat[:, None] + o.cv_lat[:, None] * o.T_field[None, :])).sum(axis=0)
+    o.g = o.g_equilibrium(o.phi * rho, U, RT, v)
+    assert np.allclose(o.macro()["T"], 1073.0, rtol=1e-12, atol=0)
+    o.step(5)
+    assert np.allclose(o.macro()["T"], 1073.0, rtol=1e-12, atol=0)
+    mu = np.asarray(o.moments()["u"])
+    assert np.allclose(mu[0], u[0], rtol=1e-12, atol=0) and np.allclose(mu[1], u[1], rtol=1e-12, atol=0)
