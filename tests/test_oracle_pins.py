@@ -798,3 +798,20 @@ def test_temperature_of_a_moving_mixture():
     assert np.allclose(o.macro()["T"], 1073.0, rtol=1e-12, atol=0)
     mu = np.asarray(o.moments()["u"])
     assert np.allclose(mu[0], u[0], rtol=1e-12, atol=0) and np.allclose(mu[1], u[1], rtol=1e-12, atol=0)
+
+
+def test_gradient_of_linear_fields_with_mirror_ends():
+    """R9 on closed forms: for A = 2x (D2Q9, bounce-back x ends, periodic y) the isotropic
+    gradient 3 sum_i w_i c_i A(x + c_i) is exactly (2, 0) at interior nodes (sum_i w_i c_i c_i
+    = I/3); at the x ends the ghost A(x + c) := A(x) halves the x component to 1 (the three
+    outward directions see no difference); the y component stays 0 everywhere."""
+    nx, ny = 7, 5
+    w = replace(synth.config1(nx=nx, ny=ny), bc_lo=synth.BC_BOUNCEBACK, bc_hi=synth.BC_BOUNCEBACK)
+    o = lo.Oracle(w)
+    x = np.tile(np.arange(nx), ny).astype(np.float64)
+    A = 2.0 * x
+    gx, gy = o.gradient(A, 0), o.gradient(A, 1)
+    ends = (x == 0) | (x == nx - 1)
+    assert np.allclose(gx[~ends], 2.0, rtol=0, atol=1e-13)
+    assert np.allclose(gx[ends], 1.0, rtol=0, atol=1e-13)
+    assert np.allclose(gy, 0.0, rtol=0, atol=1e-13)
