@@ -86,8 +86,7 @@ Readings adopted where the paper is silent, garbled or self-inconsistent
 Pins: tests/test_oracle_pins.py checks this code against statements independent of it
 (conservation, closed forms, equilibria, continuum models, marginalisation, mole and
 charge balances).  Parity unpinned (no pin of their own, covered by the GPU parity tests
-only): R5, R10, R11, R24, R20's pointwise use of a varying porosity, and which upstream
-node the outflow of R18 copies from.
+only): R5, R10, R11, R24 and which upstream node the outflow of R18 copies from.
 """
 from __future__ import annotations
 

@@ -815,3 +815,22 @@ def test_gradient_of_linear_fields_with_mirror_ends():
     assert np.allclose(gx[~ends], 2.0, rtol=0, atol=1e-13)
     assert np.allclose(gx[ends], 1.0, rtol=0, atol=1e-13)
     assert np.allclose(gy, 0.0, rtol=0, atol=1e-13)
+
+
+def test_varying_porosity_rests_at_uniform_phi_p():
+    """R20 (porosity applied pointwise): the model's pressure tensor is phi P I, so a binary
+    mixture at rest in a porosity varying along x (0.4 +- 0.1) is in equilibrium when phi P
+    is uniform (P = P0 0.4 / phi): 20 steps keep every velocity below 1e-15, while the same
+    porosity with uniform P starts a flow (|u| > 1e-3)."""
+    nx, ny = 16, 4
+    w = synth.config1(nx=nx, ny=ny)
+    x = np.tile(np.arange(nx), ny)
+    phi = 0.4 + 0.1 * np.sin(2 * np.pi * x / nx)
+    X = np.stack([np.full(w.N, 0.5), np.full(w.N, 0.5)])
+    out = {}
+    for label, P in (("phiP", 101325.0 * 0.4 / phi), ("P", np.full(w.N, 101325.0))):
+        o = lo.Oracle(replace(w, phi=phi, P0=P, X0=X))
+        o.step(20)
+        m = o.moments()
+        out[label] = max(np.max(np.abs(m["u"])), np.max(np.abs(m["j_a"])))
+    assert out["phiP"] < 1e-15 and out["P"] > 1e-3, out
