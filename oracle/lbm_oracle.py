@@ -86,7 +86,8 @@ Readings adopted where the paper is silent, garbled or self-inconsistent
 Pins: tests/test_oracle_pins.py checks this code against statements independent of it
 (conservation, closed forms, equilibria, continuum models, marginalisation, mole and
 charge balances).  Parity unpinned (no pin of their own, covered by the GPU parity tests
-only): R5, R10, R11, R24 and which upstream node the outflow of R18 copies from.
+only): R5, R10, R11, the momentum-lattice rho of R24 in P and f^ex (its use in the
+mass-source ratio is pinned), and which upstream node the outflow of R18 copies from.
 """
 from __future__ import annotations
 
