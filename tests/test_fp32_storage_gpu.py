@@ -45,7 +45,14 @@ CASES = {
     "c2_energy_inlets": (lambda: synth.config2(kn_index=3, nx=64, ny=4), 150),
     "c3_d3q27_chemistry": (lambda: synth.config3(nx=10, ny=6, nz=4), 12),
     "c3_row_blocks": (lambda: synth.config3(nx=64, ny=3, nz=8), 6),
+    "electrode_current_control": (lambda: _controlled(synth.electrode_slab(nx=16, ny=2, omega=5e-3)), 20),
 }
+
+
+def _controlled(w):
+    w.electrode["target_ia"] = np.array([1.0e6, 1.5e6])
+    w.electrode["n_secant"] = 6
+    return w
 
 
 @pytest.mark.parametrize("case", list(CASES))
