@@ -253,7 +253,8 @@ int lbm_step(lbm_ctx *ctx, int64_t n_steps);
 int lbm_set_graph(lbm_ctx *ctx, int32_t steps_per_graph);
 
 /* Gradient of an outlet-flux objective by the adjoint of the step (isothermal,
- * no surface mechanism or Faradaic source, D2Q9 grid; LBM_EINVAL otherwise),
+ * no surface mechanism or Faradaic source, D1Q3/D2Q9/D3Q27 grid with FP64
+ * storage, not packed columns; LBM_EINVAL otherwise),
  * starting from the initial state (LBM_ESTATE after a step has been taken):
  *   J = (1/T) sum_{t=1..T} sum_{nodes with x = nx-1} j_{s,x}(t) / m_s,
  * with j_s the second-order species momentum of the species solve (eq

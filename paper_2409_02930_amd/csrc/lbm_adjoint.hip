@@ -931,13 +931,22 @@ hipError_t adj_dispatch_m(const KParams &k, const AdjBuffers &b, int stage, hipS
 
 }  // namespace
 
-hipError_t launch_adjoint(int dim, const KParams &k, const AdjBuffers &b, int stage, hipStream_t s) {
-  if (dim != 2) return hipErrorInvalidValue;
+template <int D>
+hipError_t adj_dispatch_d(const KParams &k, const AdjBuffers &b, int stage, hipStream_t s) {
   switch (k.M) {
-    case 2: return adj_dispatch_m<2, 2>(k, b, stage, s);
-    case 3: return adj_dispatch_m<2, 3>(k, b, stage, s);
-    case 4: return adj_dispatch_m<2, 4>(k, b, stage, s);
-    case 5: return adj_dispatch_m<2, 5>(k, b, stage, s);
+    case 2: return adj_dispatch_m<D, 2>(k, b, stage, s);
+    case 3: return adj_dispatch_m<D, 3>(k, b, stage, s);
+    case 4: return adj_dispatch_m<D, 4>(k, b, stage, s);
+    case 5: return adj_dispatch_m<D, 5>(k, b, stage, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_adjoint(int dim, const KParams &k, const AdjBuffers &b, int stage, hipStream_t s) {
+  switch (dim) {
+    case 1: return adj_dispatch_d<1>(k, b, stage, s);
+    case 2: return adj_dispatch_d<2>(k, b, stage, s);
+    case 3: return adj_dispatch_d<3>(k, b, stage, s);
   }
   return hipErrorInvalidValue;
 }

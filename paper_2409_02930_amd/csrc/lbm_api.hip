@@ -1068,8 +1068,8 @@ int lbm_adjoint_outlet_flux(lbm_ctx *c, int64_t n_steps, int32_t species, double
   if (!c || !J || !grad_phi || !grad_rp) return LBM_EINVAL;
   if (n_steps < 1) return fail(c, LBM_EINVAL, "n_steps must be >= 1");
   if (species < 0 || species >= c->M) return fail(c, LBM_EINVAL, "species out of range");
-  if (c->dim != 2 || c->energy || c->has_mech || c->has_faradaic || c->colflag || c->fp32)
-    return fail(c, LBM_EINVAL, "the adjoint covers isothermal, reaction-free D2Q9 grids with FP64 storage");
+  if (c->energy || c->has_mech || c->has_faradaic || c->colflag || c->fp32)
+    return fail(c, LBM_EINVAL, "the adjoint covers isothermal, reaction-free grids with FP64 storage");
   if (c->steps_done != 0) return fail(c, LBM_ESTATE, "the adjoint starts from the initial state (no step taken)");
   const size_t N = c->N, L = c->L, Q = c->Q, D = c->dim;
   const size_t P = L * Q * N, R = (size_t)kRec * N, A = D * N;

@@ -30,6 +30,13 @@ def _log(msg):
 def _case(name):
     if name == "c5_inlet_outflow":
         return synth.config5(nx=36, ny=8), 24
+    if name == "d3q27_periodic_knudsen":
+        return synth.config3(nx=8, ny=4, nz=3, with_mech=False), 10
+    if name == "d1q3_inlet_outflow":
+        w = synth.config5(nx=30, ny=4)
+        n = w.nx
+        return replace(w, lattice=1, ny=1, X0=w.X0[:, :n], P0=w.P0[:n], T0=w.T0[:n], phi=w.phi[:n],
+                       tort=w.tort[:n]), 24
     w = synth.config5(nx=24, ny=8)
     w = replace(w, bc_lo=synth.BC_PERIODIC, bc_hi=synth.BC_PERIODIC, inlet_lo_X=None)
     if name == "periodic_no_knudsen":
@@ -49,7 +56,8 @@ def _gpu(lbm, w, T):
     return J, g, grp
 
 
-CASES = ["periodic_no_knudsen", "periodic_knudsen", "c5_inlet_outflow"]
+CASES = ["periodic_no_knudsen", "periodic_knudsen", "c5_inlet_outflow", "d3q27_periodic_knudsen",
+         "d1q3_inlet_outflow"]
 
 
 @pytest.mark.parametrize("name", CASES)
