@@ -43,7 +43,10 @@ Readings adopted where the paper is silent, garbled or self-inconsistent
   R16 lattice units: theta_ref = R_lightest T_ref = 1/3, pressure unit P_ref,
       density unit P_ref / c^2, c^2 = R_U T_ref / (m_min theta_ref).
   R17 inlet: missing populations := equilibrium of the inlet state moving with
-      the boundary node's velocity at the time level being streamed.
+      the boundary node's velocity at the time level being streamed.  For the
+      energy lattice the inlet fixes the temperature of what enters: its missing
+      populations are the equilibrium at the inlet temperature of the node's own
+      mixture (momentum-lattice density and composition at that time level).
   R18 outflow: missing populations copied from the upstream neighbour.
   R19 rho_a = 0: f*_a := 0, u_a := u.
   R21 D^k_a = (phi/tau) (d_0/3) sqrt(8 R_U T / (pi m_a)), d_0 = 2 r_p.
@@ -365,7 +368,7 @@ class Oracle:
                     tau_ab[a, b] = Dab[a, b] * (self.m[b] / mmix) / RaT[a]
                     inv_tau_ab[a, b] = 1.0 / tau_ab[a, b]
         inv_tau_a = np.stack([sum(Y[b] * inv_tau_ab[a, b] for b in range(M) if b != a) for a in range(M)])
-        beta = 1.0 / (2.0 / inv_tau_a + 1.0)                               # eq betaa
+        beta = inv_tau_a / (2.0 + inv_tau_a)                               # eq betaa: dt / (2 tau_a + dt)
         if self.knudsen:
             d0 = 2.0 * w.pore_radius
             Dk = (phi / self.tort)[None, :] * (d0 / (3.0 * w.dx)) * np.sqrt(8.0 * RaT / math.pi)
@@ -702,8 +705,15 @@ class Oracle:
         if which[0] == "momentum":
             return (self.phi * rho) * product_form(self.c, [v[d] for d in range(self.D)],
                                                    [RT + v[d] ** 2 for d in range(self.D)])
-        U = (Y * (self.uf_lat[:, None] + self.cv_lat[:, None] * Tin[None, :])).sum(axis=0)
-        return self.g_equilibrium(self.phi * rho, U, RT, v)
+        # energy lattice (R17, energy part): the inlet prescribes the temperature of what
+        # enters; the entering energy populations are the equilibrium at the inlet
+        # temperature of the mixture that is at the node (its density and composition at
+        # step t), moving with the node velocity
+        Yn = mac["Y"]
+        RaTn = self.RaT(Tin)
+        Un = (Yn * (self.uf_lat[:, None] + self.cv_lat[:, None] * Tin[None, :])).sum(axis=0)
+        RTn = (Yn * RaTn).sum(axis=0)
+        return self.g_equilibrium(self.phi * mac["rho"], Un, RTn, v)
 
     def stream(self, post, which, mac):
         w, c = self.w, self.c

@@ -158,6 +158,7 @@ InletState make_inlet(const lbm_ctx *c, const double *X, double P_Pa, double T_K
   }
   s.RT = RT;
   s.U = U;
+  s.T_K = T_K;
   return s;
 }
 

@@ -207,11 +207,14 @@ __device__ __forceinline__ bool is_inlet_node(const KParams &p, const Node &nd) 
          (((nd.flag & 1) && p.bc_lo == BC_INLET) || ((nd.flag & 2) && p.bc_hi == BC_INLET));
 }
 
-// Equilibrium population of lattice `lat` entering direction i through the
-// inlet of side kind (eq 27eq for species, eq feqmix for the momentum lattice,
-// eq geq_i for the energy lattice) at the node velocity vb.
+// Equilibrium population of lattice `lat` entering direction i of node n through
+// the inlet of side kind (eq 27eq for species, eq feqmix for the momentum
+// lattice, eq geq_i for the energy lattice) at the node velocity vb.  The
+// energy lattice's inlet fixes the temperature of what enters: its equilibrium
+// is that of the node's own mixture at the inlet temperature, from the records
+// the previous step wrote for inlet nodes (density, U and R T, planes kRecEin..).
 template <int D, int M>
-__device__ __forceinline__ double inlet_population(const KParams &p, int kind, int lat, int i,
+__device__ __forceinline__ double inlet_population(const KParams &p, int kind, int lat, int i, int n,
                                                    double phi, const double *vb) {
   const InletSel in = inlet_sel(p, kind, lat);
   double P[D];
@@ -225,7 +228,8 @@ __device__ __forceinline__ double inlet_population(const KParams &p, int kind, i
     for (int d = 0; d < D; ++d) P[d] = in.RT + vb[d] * vb[d];
     return phi * in.rho * psi_dir<D>(i, vb, P);
   }
-  return geq_dir<D>(i, phi * in.rho, in.U, in.RT, vb);
+  const double *e = p.rec_prev + (size_t)kRecEin * p.N + n;
+  return geq_dir<D>(i, phi * e[0], e[p.N], e[2 * (size_t)p.N], vb);
 }
 
 // Post-stream populations of lattice `lat` at node nd (pull scheme).  All Q
@@ -326,7 +330,7 @@ __device__ __forceinline__ void inlet_replace(const KParams &p, const Node &nd, 
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     const int kind = inlet_kind<D>(p, nd, i);
-    if (kind) f[i] = inlet_population<D, M>(p, kind, lat, i, phi, vb);
+    if (kind) f[i] = inlet_population<D, M>(p, kind, lat, i, nd.n, phi, vb);
   }
 }
 

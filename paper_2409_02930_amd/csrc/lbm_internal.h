@@ -13,8 +13,10 @@
 
 enum { BC_PERIODIC = 0, BC_BOUNCEBACK = 1, BC_INLET = 2, BC_OUTFLOW = 3 };
 
-constexpr int kRec = 8;     // planes of the node records (velocity + species source)
+constexpr int kRec = 11;    // planes of the node records (velocity, species source, energy inlet)
 constexpr int kRecSrc = 3;  // first plane of the species source
+constexpr int kRecEin = 8;  // inlet nodes with the energy lattice: rho, U and R T of the node's
+                            //   mixture at the inlet temperature (planes 8, 9, 10)
 
 // Equilibrium state of a prescribed inlet mixture (lattice units).
 struct InletState {
@@ -23,6 +25,7 @@ struct InletState {
   double rho;               // sum of rho_a
   double RT;                // mixture R T
   double U;                 // mixture internal energy (energy lattice)
+  double T_K;               // inlet temperature, kelvin
 };
 
 // Everything the per-node stream/collide kernels read.  Passed by value.
@@ -60,7 +63,8 @@ struct KParams {
                             //   sum_a (cv_a + R_a / T) Y_a, so sum_a H_a(T) Y_a = row M + T row M+1
   double *rqd;              // [D][N] sum_a H_a Y_a (u_a - u_bar) (energy lattice)
   // ping-pong node records between consecutive steps, kRec planes of N doubles:
-  //   planes 0..2 v = u/phi, planes 3..7 species source rho_dot_a dt (lattice units)
+  //   planes 0..2 v = u/phi, planes 3..7 species source rho_dot_a dt (lattice units),
+  //   planes 8..10 the energy-inlet state of inlet nodes (energy lattice only)
   const double *rec_prev;   // written by the previous step
   double *rec_cur;          // written by this step
   const double *T_prev;     // [N] temperature of the previous step (energy) or Tfield

@@ -653,6 +653,22 @@ __global__ __launch_bounds__(64 * (M + 1 + (ENERGY ? 1 : 0))) void k_species(con
       }
       if constexpr (ENERGY) {
         p.T_cur[n] = s.T;
+        // inlet node: the state the next step's entering energy populations take
+        // (the node's mixture at the inlet temperature)
+        const int side = ((nd.flag & 1) && p.bc_lo == BC_INLET) ? 0 : (((nd.flag & 2) && p.bc_hi == BC_INLET) ? 1 : -1);
+        if (side >= 0) {
+          const double Tin = side == 0 ? p.inlet[0].T_K : p.inlet[1].T_K;
+          double Ui = 0.0, RTi = 0.0;
+#pragma unroll
+          for (int a = 0; a < M; ++a) {
+            Ui += s.Y[a] * (p.uf[a] + p.cv[a] * Tin);
+            RTi += s.Y[a] * (p.theta_ref * p.mmin_over_m[a] * (Tin * p.inv_T_ref));
+          }
+          double *e = p.rec_cur + (size_t)kRecEin * N + n;
+          e[0] = s.rho;
+          e[N] = Ui;
+          e[2 * (size_t)N] = RTi;
+        }
 #pragma unroll
         for (int d = 0; d < D; ++d) {
           double ub = 0.0;
