@@ -360,8 +360,8 @@ class Oracle:
         # coefficients (Section 2.3 with R1, R2, R14, R21)
         Tr = T / w.T_ref
         Dab = w.D_ref_lat[:, :, None] * (Tr ** 1.5)[None, None, :] / Ps[None, None, :]
-        tau_ab = np.zeros((M, M, self.N))
-        inv_tau_ab = np.zeros((M, M, self.N))
+        tau_ab = np.zeros((M, M, self.N), dtype=Dab.dtype)        # dtype follows the inputs (complex
+        inv_tau_ab = np.zeros((M, M, self.N), dtype=Dab.dtype)    # for the complex-step tangent)
         for a in range(M):
             for b in range(M):
                 if a != b:
@@ -376,7 +376,7 @@ class Oracle:
         else:
             inv_tau_k = np.zeros((M, self.N))
         # R4: second-order species momenta, one M x M solve per direction and node
-        A = np.zeros((self.N, M, M))
+        A = np.zeros((self.N, M, M), dtype=np.result_type(inv_tau_a, inv_tau_k))
         for a in range(M):
             for b in range(M):
                 if a == b:
@@ -751,7 +751,7 @@ class Oracle:
         acc = 0.0
         for _ in range(steps):
             ja = self.macro()["ja"]                                                      # (M, D, N)
-            acc += float(np.sum(ja[species, 0, outlet])) / self.m[species]
+            acc = acc + np.sum(ja[species, 0, outlet]) / self.m[species]
             self.step(1)
         return acc / steps
 

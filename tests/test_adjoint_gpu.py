@@ -1,7 +1,9 @@
 """Adjoint of the isothermal reaction-free step (through the C ABI) against the
-oracle: the objective itself to 1e-11, and its gradient with respect to the
-porosity field and the pore radius against central finite differences of the
-oracle (relative step 1e-6, tortuosity held fixed)."""
+oracle: the objective itself to 1e-11; its gradient with respect to the porosity
+field and the pore radius against central finite differences of the oracle
+(relative step 1e-6, tortuosity held fixed); and the dot-product test: the
+adjoint gradient contracted with a direction equals the oracle's exact
+complex-step tangent along it (tests/oracle_tangent.py)."""
 import sys
 from dataclasses import replace
 
@@ -9,6 +11,7 @@ import numpy as np
 import pytest
 
 from oracle.lbm_oracle import Oracle
+from oracle_tangent import outlet_flux_tangent
 from workloads import synth
 
 pytestmark = pytest.mark.gpu
@@ -32,6 +35,12 @@ def _case(name):
         return synth.config5(nx=36, ny=8), 24
     if name == "d3q27_periodic_knudsen":
         return synth.config3(nx=8, ny=4, nz=3, with_mech=False), 10
+    if name == "d3q27_inlet_outflow":
+        # C3 gas and porosity recipe on 8 x 4 x 3 with an inlet of another composition at
+        # x = 0 (at that end's temperature) and an outflow at the other end
+        w = synth.config3(nx=8, ny=4, nz=3, with_mech=False)
+        return replace(w, bc_lo=synth.BC_INLET, bc_hi=synth.BC_OUTFLOW,
+                       inlet_lo_X=np.array([0.6, 0.1, 0.1, 0.1, 0.1]), inlet_T=float(w.T0[0])), 10
     if name == "d1q3_inlet_outflow":
         w = synth.config5(nx=30, ny=4)
         n = w.nx
@@ -57,7 +66,7 @@ def _gpu(lbm, w, T):
 
 
 CASES = ["periodic_no_knudsen", "periodic_knudsen", "c5_inlet_outflow", "d3q27_periodic_knudsen",
-         "d1q3_inlet_outflow"]
+         "d3q27_inlet_outflow", "d1q3_inlet_outflow"]
 
 
 @pytest.mark.parametrize("name", CASES)
@@ -119,3 +128,24 @@ def test_adjoint_as_torch_autograd_function(lbm):
     assert float(J) == J2
     assert np.array_equal(phi.grad.cpu().numpy(), g2)
     assert float(rp.grad) == grp2
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_adjoint_dot_product_with_oracle_tangent(lbm, name):
+    """<dJ/dphi, v> + dJ/dr_p s from the GPU adjoint equals the oracle's complex-step
+    directional derivative along (v, s), for a random porosity direction, a smooth
+    one, and the pore radius alone."""
+    w, T = _case(name)
+    J, g, grp = _gpu(lbm, w, T)
+    rng = np.random.default_rng(3)
+    N = w.N
+    x = np.arange(N) % w.nx
+    dirs = [(rng.standard_normal(N) * w.phi, 0.0),
+            (np.cos(2 * np.pi * (x + 0.5) / w.nx) * w.phi, 0.0)]
+    if np.isfinite(w.pore_radius):
+        dirs.append((None, w.pore_radius))
+    for v, s_ in dirs:
+        Jo, tan = outlet_flux_tangent(w, T, 0, dphi=v, drp=s_)
+        ad = (float(np.dot(g, v)) if v is not None else 0.0) + grp * s_
+        _log(f"{name}: adjoint {ad:.15e} tangent {tan:.15e} rel {abs(ad - tan) / abs(tan):.2e}")
+        assert abs(ad - tan) <= 1e-10 * abs(tan), (ad, tan)

@@ -17,8 +17,7 @@ from workloads import synth
 
 pytestmark = pytest.mark.gpu
 
-TOL = 1e-11
-FLOOR = {"u": 1e-3, "j_a": 1e-2}
+from parity_util import TOL, normalized_error
 KEYS = ("rho_a", "u", "T", "P", "j_a", "X", "rho", "theta")
 
 
@@ -35,19 +34,14 @@ def _log(msg):
     sys.stdout.flush()
 
 
-def _err(g, r, floor=0.0):
-    g = np.asarray(g, dtype=np.float64).reshape(-1)
-    r = np.asarray(r, dtype=np.float64).reshape(-1)
-    assert g.shape == r.shape
-    assert np.all(np.isfinite(g))
-    scale = max(float(np.max(np.abs(r))), floor)
-    return 0.0 if scale == 0 else float(np.max(np.abs(g - r)) / scale)
+def _err(g, r, key=None, ref=None):
+    return normalized_error(np.asarray(g).reshape(-1), np.asarray(r).reshape(-1), key, ref)
 
 
 def _check(lat, o):
     got = lat.fields()
     ref = o.moments()
-    errs = {k: _err(got[k], ref[k], FLOOR.get(k, 0.0)) for k in KEYS}
+    errs = {k: _err(got[k], ref[k], k, ref) for k in KEYS}
     iv, ia, pel = lat.charge()
     errs.update(iv=_err(iv, o.i_v), ia=_err(ia, o.i_a), pel=_err(pel, o.phi_el))
     bad = {k: e for k, e in errs.items() if not e <= TOL}
@@ -129,7 +123,7 @@ def test_charge_transfer_without_electrode_has_zero_potential(lbm):
     got = lat.fields()
     ref = o.moments()
     for k in KEYS:
-        assert _err(got[k], ref[k], FLOOR.get(k, 0.0)) <= TOL, k
+        assert _err(got[k], ref[k], k, ref) <= TOL, k
     iv, ia, pel = lat.charge()
     assert _err(iv, o._iv) <= TOL
     assert np.all(ia == 0.0) and np.all(pel == 0.0)
@@ -199,7 +193,7 @@ def test_packed_columns_with_their_own_electrode_potentials(lbm):
         ref = o.moments()
         sl = slice(off, off + c.nx)
         for k in KEYS:
-            assert _err(np.asarray(got[k])[..., sl], ref[k], FLOOR.get(k, 0.0)) <= TOL, k
+            assert _err(np.asarray(got[k])[..., sl], ref[k], k, ref) <= TOL, k
         for g, r in zip(ch, (o.i_v, o.i_a, o.phi_el)):
             assert _err(g[sl], r) <= TOL
         off += c.nx

@@ -20,8 +20,7 @@ from workloads import synth
 
 pytestmark = pytest.mark.gpu
 
-TOL = 1e-11
-FLOOR = {"u": 1e-3, "j_a": 1e-2}
+from parity_util import TOL, compare
 
 
 @pytest.fixture(scope="module")
@@ -52,17 +51,8 @@ def _patch(w, center, R):
     return pw, c
 
 
-def _sample_compare(got_at, ref_at, keys):
-    errs = {}
-    for k in keys:
-        g = np.asarray(got_at[k], dtype=np.float64)
-        r = np.asarray(ref_at[k], dtype=np.float64)
-        scale = max(float(np.max(np.abs(r))), FLOOR.get(k, 0.0))
-        errs[k] = 0.0 if scale == 0 else float(np.max(np.abs(g - r)) / scale)
-        assert np.all(np.isfinite(g)), k
-    bad = {k: e for k, e in errs.items() if not e <= TOL}
-    assert not bad, f"errors above {TOL}: {bad} (all {errs})"
-    return errs
+def _sample_compare(got_at, ref_at, keys, label=""):
+    return compare(got_at, ref_at, keys, label=label)
 
 
 def _field_at(f, n):
