@@ -238,7 +238,14 @@ int lbm_set_current_target(lbm_ctx *ctx, const double *target_ia, int32_t n_seca
  * stream.  LBM_ESTATE without an electrode.                                                */
 int lbm_get_electrode_potential(lbm_ctx *ctx, double *phi_line);
 
-/* Advances n_steps time steps, asynchronously on the configured stream. */
+/* Advances n_steps time steps, asynchronously on the configured stream.  One step is
+ * the method's update of every lattice at every node (Sections 2.3, 3 and 4): stream
+ * (pull) with the boundary conditions, moments and composition, temperature (eq
+ * temperature), the species-momentum solve (eq transform1), the species collision (eq
+ * finalNumericalEquationsReactive, with the reaction populations of eq fsourceHetero),
+ * the local chemistry (Section 4) and the momentum and energy collisions (eqs f_source,
+ * g_source).  n_steps >= 0; returns LBM_EHIP when a launch fails (the context is then
+ * unusable) and allocates nothing. */
 int lbm_step(lbm_ctx *ctx, int64_t n_steps);
 
 /* Graph step loop: with steps_per_graph = G (even, >= 2), lbm_step captures G
@@ -293,14 +300,12 @@ int lbm_get_diagnostics(lbm_ctx *ctx, lbm_diag *out);
 
 /* Kernel time of the last lbm_step call's launches, measured with HIP events
  * on the configured stream: total ms of the call and, over its last <= 64
- * steps, the per-step averages of the species kernel, the chemistry kernel,
- * the source pass and the mixture kernel.  The reaction populations of a step
- * (eq fsourceHetero) are added inside the next species kernel's pull, so
- * source_ms is the empty interval between the chemistry and mixture launches
- * (kept for a stable signature).  Enabled with lbm_set_timing(ctx, 1). */
+ * steps, the per-step averages of the species kernel, the chemistry kernel and
+ * the mixture kernel (any output pointer may be NULL).  Enabled with
+ * lbm_set_timing(ctx, 1). */
 int lbm_set_timing(lbm_ctx *ctx, int32_t enable);
 int lbm_get_timing(lbm_ctx *ctx, double *total_ms, double *species_ms, double *chem_ms,
-                   double *source_ms, double *mixture_ms);
+                   double *mixture_ms);
 
 /* Snapshot of the complete state (populations, node records, coverages, step
  * counter, and with an electrode installed its electrolyte potential, currents and

@@ -16,10 +16,11 @@
 //           (Psi products, the collision update) are differentiated by hand;
 //           the small coefficient map from the moments, phi and the Knudsen
 //           factor to the collision coefficients (composition, rates, the M x M
-//           solve, omega, u^ex, P^ex, the record rA, the objective) is
-//           differentiated in forward mode with dual numbers, one pass per
-//           moment-space input.  Lambda_t = explicit population terms + the
-//           moment chain; phi and the Knudsen factor accumulate their adjoints.
+//           solve, omega, u^ex, P^ex, the record rA, the objective) by a
+//           hand-written reverse sweep (coef_map_reverse) that reuses the
+//           solve's factorisation for the transposed system.  Lambda_t =
+//           explicit population terms + the moment chain; phi and the Knudsen
+//           factor accumulate their adjoints.
 // Objective: J = (1/T) sum_{t=1..T} sum_{x = nx-1} j_{s,x}(F_t) / m_s, the
 // solved momentum of species s through the last x plane, averaged over the
 // collision steps (time levels 0..T-1).
@@ -27,37 +28,8 @@
 
 namespace {
 
-// ---- dual numbers (value, one tangent) -------------------------------------
-struct Dual {
-  double v, d;
-};
-__device__ __forceinline__ Dual mkd(double v, double d = 0.0) { return Dual{v, d}; }
-__device__ __forceinline__ Dual operator+(Dual a, Dual b) { return {a.v + b.v, a.d + b.d}; }
-__device__ __forceinline__ Dual operator-(Dual a, Dual b) { return {a.v - b.v, a.d - b.d}; }
-__device__ __forceinline__ Dual operator-(Dual a) { return {-a.v, -a.d}; }
-__device__ __forceinline__ Dual operator*(Dual a, Dual b) { return {a.v * b.v, a.d * b.v + a.v * b.d}; }
-__device__ __forceinline__ Dual operator/(Dual a, Dual b) {
-  const double q = a.v / b.v;
-  return {q, (a.d - q * b.d) / b.v};
-}
-__device__ __forceinline__ Dual operator+(Dual a, double b) { return {a.v + b, a.d}; }
-__device__ __forceinline__ Dual operator+(double a, Dual b) { return {a + b.v, b.d}; }
-__device__ __forceinline__ Dual operator-(Dual a, double b) { return {a.v - b, a.d}; }
-__device__ __forceinline__ Dual operator-(double a, Dual b) { return {a - b.v, -b.d}; }
-__device__ __forceinline__ Dual operator*(Dual a, double b) { return {a.v * b, a.d * b}; }
-__device__ __forceinline__ Dual operator*(double a, Dual b) { return {a * b.v, a * b.d}; }
-__device__ __forceinline__ Dual operator/(Dual a, double b) { return {a.v / b, a.d / b}; }
-__device__ __forceinline__ Dual operator/(double a, Dual b) {
-  const double q = a / b.v;
-  return {q, -q * b.d / b.v};
-}
-__device__ __forceinline__ Dual sqrt(Dual a) {
-  const double r = ::sqrt(a.v);
-  return {r, a.d / (2.0 * r)};
-}
+// Value of a coefficient-map quantity (the map is written once for its scalar type).
 __device__ __forceinline__ double val(double a) { return a; }
-__device__ __forceinline__ double val(Dual a) { return a.v; }
-__device__ __forceinline__ double tan_(Dual a) { return a.d; }
 
 // ---- coefficient map --------------------------------------------------------
 // Inputs: raw lattice sums s0_l = sum_i f_li, s1_ld = sum_i f_li c_id (species
@@ -696,25 +668,6 @@ __device__ __forceinline__ void collision_adjoint(const KParams &p, double T, co
       cb.Pex[d] += fexb * c.phirho * dP[d];
     }
   }
-}
-
-template <class S, int D, int M>
-__device__ __forceinline__ double coef_dot(const Coef<S, D, M> &c, const Coef<double, D, M> &cb) {
-  double s = 0.0;
-#pragma unroll
-  for (int a = 0; a < M; ++a) {
-    s += cb.beta[a] * tan_(c.beta[a]) + cb.Y[a] * tan_(c.Y[a]) + cb.itk[a] * tan_(c.itk[a]) +
-         cb.pra[a] * tan_(c.pra[a]);
-#pragma unroll
-    for (int b = 0; b < M; ++b) s += cb.iab[a][b] * tan_(c.iab[a][b]);
-#pragma unroll
-    for (int d = 0; d < D; ++d) s += cb.xs[a][d] * tan_(c.xs[a][d]);
-  }
-#pragma unroll
-  for (int d = 0; d < D; ++d)
-    s += cb.v[d] * tan_(c.v[d]) + cb.xi[d] * tan_(c.xi[d]) + cb.Pex[d] * tan_(c.Pex[d]) + cb.rA[d] * tan_(c.rA[d]);
-  s += cb.omega * tan_(c.omega) + cb.gfac * tan_(c.gfac) + cb.phirho * tan_(c.phirho) + cb.N * tan_(c.N);
-  return s;
 }
 
 // ---- pass 1: lambda'_t and dJ/dG ------------------------------------------

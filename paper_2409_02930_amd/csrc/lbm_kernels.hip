@@ -415,40 +415,46 @@ __device__ __forceinline__ void node_state(const KParams &p, const SpeciesShared
 }
 
 // Second-order species momenta (eq transform1 with the Knudsen terms): solves
-// A x = j from the rows in LDS (Gaussian elimination, M x M, D right sides).
+// A x = j from the rows in LDS (Gaussian elimination, M x M) and writes x to LDS.
+// The matrix is factored once; the D right-hand sides are then solved one at a
+// time in a loop kept rolled, so only one column of momenta is live: this is the
+// kernel's register peak, and with it at 156 VGPRs two blocks fit on a CU.
 template <int D, int M, bool ENERGY>
-__device__ __forceinline__ void species_momenta(const SpeciesShared<D, M, ENERGY> &sh, int lane,
-                                                double (&x)[M][D]) {
+__device__ __forceinline__ void species_momenta(SpeciesShared<D, M, ENERGY> &sh, int lane) {
   double A[M][M];
 #pragma unroll
-  for (int a = 0; a < M; ++a) {
+  for (int a = 0; a < M; ++a)
 #pragma unroll
     for (int c = 0; c < M; ++c) A[a][c] = sh.u.s.A[a][c][lane];
-#pragma unroll
-    for (int d = 0; d < D; ++d) x[a][d] = sh.u.s.m1[a][d][lane];
-  }
   double inv[M];
 #pragma unroll
   for (int k = 0; k < M; ++k) {
     inv[k] = 1.0 / A[k][k];
 #pragma unroll
     for (int r = k + 1; r < M; ++r) {
-      const double l = A[r][k] * inv[k];
+      A[r][k] *= inv[k];                      // multiplier l_rk
 #pragma unroll
-      for (int c = k + 1; c < M; ++c) A[r][c] -= l * A[k][c];
-#pragma unroll
-      for (int d = 0; d < D; ++d) x[r][d] -= l * x[k][d];
+      for (int c = k + 1; c < M; ++c) A[r][c] -= A[r][k] * A[k][c];
     }
   }
+#pragma unroll 1
+  for (int d = 0; d < D; ++d) {
+    double x[M];
 #pragma unroll
-  for (int k = M - 1; k >= 0; --k) {
+    for (int a = 0; a < M; ++a) x[a] = sh.u.s.m1[a][d][lane];
 #pragma unroll
-    for (int d = 0; d < D; ++d) {
-      double sacc = x[k][d];
+    for (int k = 0; k < M; ++k)
 #pragma unroll
-      for (int c = k + 1; c < M; ++c) sacc -= A[k][c] * x[c][d];
-      x[k][d] = sacc * inv[k];
+      for (int r = k + 1; r < M; ++r) x[r] -= A[r][k] * x[k];
+#pragma unroll
+    for (int k = M - 1; k >= 0; --k) {
+      double sacc = x[k];
+#pragma unroll
+      for (int c = k + 1; c < M; ++c) sacc -= A[k][c] * x[c];
+      x[k] = sacc * inv[k];
     }
+#pragma unroll
+    for (int a = 0; a < M; ++a) sh.x[a][d][lane] = x[a];
   }
 }
 
@@ -622,14 +628,9 @@ __global__ __launch_bounds__(64 * (M + 1 + (ENERGY ? 1 : 0))) void k_species(con
     //      chemistry and mixture kernels and for the next step.
     double jm[D], itk[M];
     if (valid) {
-      double x[M][D];
-      species_momenta<D, M, ENERGY>(sh, lane, x);
+      species_momenta<D, M, ENERGY>(sh, lane);
 #pragma unroll
-      for (int c = 0; c < M; ++c) {
-        itk[c] = sh.u.s.itk[c][lane];
-#pragma unroll
-        for (int d = 0; d < D; ++d) sh.x[c][d][lane] = x[c][d];
-      }
+      for (int c = 0; c < M; ++c) itk[c] = sh.u.s.itk[c][lane];
 #pragma unroll
       for (int d = 0; d < D; ++d) jm[d] = sh.u.s.m1[M][d][lane];
     }
@@ -1220,15 +1221,35 @@ __global__ __launch_bounds__(256) void k_faradaic(const ChemParams cp) {
 // every lattice, the first moment of the momentum lattice, the minimum
 // population and the count of non-finite values.  partials: [block][L + D + 2]
 // ---------------------------------------------------------------------------
+// Block reductions of a 256-thread block: a butterfly over the 64 lanes of each
+// wave (cross-lane moves, no LDS), then the four wave results in wave order.  The
+// order is fixed, so a reduction gives the same bits on every call.  The result is
+// valid in thread 0; sh holds 4 doubles and is free again on return.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_min(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+  return v;
+}
 __device__ __forceinline__ double block_sum(double v, double *sh) {
   const int t = threadIdx.x;
-  sh[t] = v;
+  v = wave_sum(v);
+  if ((t & 63) == 0) sh[t >> 6] = v;
   __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (t < w) sh[t] += sh[t + w];
-    __syncthreads();
-  }
-  const double r = sh[0];
+  const double r = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+  __syncthreads();
+  return r;
+}
+__device__ __forceinline__ double block_min(double v, double *sh) {
+  const int t = threadIdx.x;
+  v = wave_min(v);
+  if ((t & 63) == 0) sh[t >> 6] = v;
+  __syncthreads();
+  const double r = fmin(fmin(sh[0], sh[1]), fmin(sh[2], sh[3]));
   __syncthreads();
   return r;
 }
@@ -1249,7 +1270,7 @@ __global__ __launch_bounds__(256) void k_surface_energy(const KParams p) {
 template <int D, typename PT>
 __global__ __launch_bounds__(256) void k_diag(int L, int Mmom, const KParams p, const PT *pop,
                                               double *partials) {
-  __shared__ double sh[256];
+  __shared__ double sh[4];
   constexpr int Q = LQ<D>::Q;
   const int N = p.N;
   const int n = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1284,14 +1305,8 @@ __global__ __launch_bounds__(256) void k_diag(int L, int Mmom, const KParams p, 
     const double r = block_sum(s, sh);
     if (t == 0) partials[(size_t)blockIdx.x * W + L + d] = r;
   }
-  sh[t] = mn;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (t < w) sh[t] = fmin(sh[t], sh[t + w]);
-    __syncthreads();
-  }
-  if (t == 0) partials[(size_t)blockIdx.x * W + L + D] = sh[0];
-  __syncthreads();
+  const double bm = block_min(mn, sh);
+  if (t == 0) partials[(size_t)blockIdx.x * W + L + D] = bm;
   const double nb = block_sum(bad, sh);
   if (t == 0) partials[(size_t)blockIdx.x * W + L + D + 1] = nb;
 }

@@ -96,7 +96,7 @@ def _load():
         "lbm_moment_rows": ([vp, C.c_uint32, _ip], C.c_int),
         "lbm_get_diagnostics": ([vp, C.POINTER(lbm_diag)], C.c_int),
         "lbm_set_timing": ([vp, C.c_int32], C.c_int),
-        "lbm_get_timing": ([vp, _dp, _dp, _dp, _dp, _dp], C.c_int),
+        "lbm_get_timing": ([vp, _dp, _dp, _dp, _dp], C.c_int),
         "lbm_save": ([vp, vp, C.POINTER(C.c_size_t)], C.c_int),
         "lbm_load": ([vp, vp, C.c_size_t], C.c_int),
         "lbm_last_error": ([vp], C.c_char_p),
@@ -353,10 +353,10 @@ class Lattice:
         self._check(_lib.lbm_set_timing(self.ctx, 1 if on else 0))
 
     def timing(self):
-        t = [C.c_double() for _ in range(5)]
+        t = [C.c_double() for _ in range(4)]
         self._check(_lib.lbm_get_timing(self.ctx, *[C.byref(x) for x in t]))
         return {"total_ms": t[0].value, "species_ms": t[1].value, "chem_ms": t[2].value,
-                "source_ms": t[3].value, "mixture_ms": t[4].value}
+                "mixture_ms": t[3].value}
 
     def save(self) -> bytes:
         size = C.c_size_t()
