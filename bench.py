@@ -140,10 +140,10 @@ def cpu_baseline(name, budget_s=20.0):
             "sample": f"{sample}: {steps} steps of {w.N} nodes in {el:.1f} s, numpy single thread"}
 
 
-def bench_c4(args, lbm, torch):
+def measure_c4(lbm, torch, steps, warmup, graph_steps):
     """Batched ragged 1-D columns (64 D1Q3 button-cell columns, L ~ U{200..2000}) in one
     context with the graph step loop, against the same 64 columns run one after another,
-    each in its own context with plain launches."""
+    each in its own context with plain launches.  Returns (t_batched, t_sequential, N)."""
     from workloads import synth
     lengths, phis, currents = synth.config4_columns()
     cols = [synth.config4_column(int(L), float(p_), float(i)) for L, p_, i in zip(lengths, phis, currents)]
@@ -157,31 +157,36 @@ def bench_c4(args, lbm, torch):
     lat.set_porous_field(cat("phi"), cat("tort"), w0.pore_radius)
     lat.set_faradaic_source(cat("faradaic_rate"), 0, 1)
     lat.set_mechanism(w0.mech)
-    lat.set_graph(args.graph_steps)
-    log(f"batched: {len(cols)} columns, {N} nodes; warmup {args.warmup}")
-    lat.step(args.warmup)
+    lat.set_graph(graph_steps)
+    log(f"batched: {len(cols)} columns, {N} nodes; warmup {warmup}")
+    lat.step(warmup)
     stream.synchronize()
     t0 = time.perf_counter()
-    lat.step(args.steps)
+    lat.step(steps)
     stream.synchronize()
     t_batched = time.perf_counter() - t0
     lat.close()
-    log(f"batched {args.steps} steps: {t_batched:.3f} s; sequential baseline")
+    log(f"batched {steps} steps: {t_batched:.3f} s; sequential baseline")
     t_seq = 0.0
     for c in cols:
         pl = lbm.lattice_from_workload(c, stream=stream.cuda_stream)
-        pl.step(args.warmup)
+        pl.step(warmup)
         stream.synchronize()
         t0 = time.perf_counter()
-        pl.step(args.steps)
+        pl.step(steps)
         stream.synchronize()
         t_seq += time.perf_counter() - t0
         pl.close()
+    return t_batched, t_seq, N, len(cols)
+
+
+def bench_c4(args, lbm, torch):
+    t_batched, t_seq, N, ncol = measure_c4(lbm, torch, args.steps, args.warmup, args.graph_steps)
     mlups = N * args.steps / t_batched / 1e6
     out = {"metric": "MLUPS", "value": mlups, "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": t_batched * 1e3 / args.steps, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-           "config": {"workload": f"c4 {len(cols)} packed D1Q3 columns, {N} nodes, M=5 K=10 R=20, "
+           "config": {"workload": f"c4 {ncol} packed D1Q3 columns, {N} nodes, M=5 K=10 R=20, "
                                   f"graph step loop of {args.graph_steps} steps",
                       "nodes": N, "parallelism": "single GPU"},
            "batched_vs_sequential": t_seq / t_batched,
@@ -236,39 +241,67 @@ def bench_c4_electrode(args, lbm, torch):
     print(json.dumps(out), flush=True)
 
 
-def bench_c5_adjoint(args, lbm, torch):
-    """C5 (D2Q9 1024x256, 3 species, GRF porosity, inlet/outflow): forward steps
-    alone vs the adjoint gradient of the outlet flux (forward with checkpoints,
-    segment recompute and reverse sweep) over the same number of steps."""
+def measure_c5_adjoint(lbm, torch, steps):
+    """C5 as stated (D2Q9 1024x256, 3 species, GRF porosity, Knudsen drag, inlet /
+    outflow): `steps` forward steps alone vs the adjoint gradient of the outlet flux
+    over the same steps (forward with checkpoints, segment recompute, reverse sweep)."""
     from workloads import synth
-    # uniform porosity: with a spatially varying porosity and Knudsen drag the
-    # method develops a growing mode after a few hundred steps (oracle and GPU alike)
-    w = synth.config5(porosity="uniform")
+    w = synth.config5()
     stream = torch.cuda.Stream()
+    lat = lbm.lattice_from_workload(w, stream=stream.cuda_stream)
+    lat.step(2)                                 # first launches (module load) outside the timing
+    stream.synchronize()
+    lat.close()
     lat = lbm.lattice_from_workload(w, stream=stream.cuda_stream)
     stream.synchronize()
     t0 = time.perf_counter()
-    lat.step(args.steps)
+    lat.step(steps)
     stream.synchronize()
     t_fwd = time.perf_counter() - t0
+    d = lat.diagnostics(check=False)
     lat.close()
     lat = lbm.lattice_from_workload(w, stream=stream.cuda_stream)
     g = torch.empty(w.N, dtype=torch.float64, device="cuda")
     stream.synchronize()
     t0 = time.perf_counter()
-    J, g, grp = lat.adjoint_outlet_flux(args.steps, 0, grad_out=g)
+    J, g, grp = lat.adjoint_outlet_flux(steps, 0, grad_out=g)
     stream.synchronize()
     t_adj = time.perf_counter() - t0
     lat.close()
-    out = {"metric": "MLUPS", "value": w.N * args.steps / t_fwd / 1e6, "unit": "MLUPS", "n_gpus": 1,
-           "steps": args.steps, "warmup": 0, "ms_per_step": t_fwd * 1e3 / args.steps, "higher_is_better": True,
-           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-           "config": {"workload": f"c5 D2Q9 {w.nx}x{w.ny} M=3 inlet/outflow, uniform porosity 0.45, "
-                                  f"outlet-flux adjoint",
-                      "nodes": w.N, "parallelism": "single GPU"},
-           "adjoint_s": t_adj, "forward_s": t_fwd, "adjoint_over_forward": t_adj / t_fwd,
-           "J": J, "grad_rp": grp, "grad_phi_absmax": float(g.abs().max())}
+    return {"forward_s": t_fwd, "adjoint_s": t_adj, "adjoint_over_forward": t_adj / t_fwd, "J": J,
+            "grad_rp": grp, "grad_phi_absmax": float(g.abs().max()), "n_nonfinite": d["n_nonfinite"],
+            "N": w.N, "workload": f"c5 D2Q9 {w.nx}x{w.ny} M=3 GRF porosity, Knudsen, inlet/outflow, "
+                                  f"nu {w.nu_lat}, outlet-flux adjoint over {steps} steps"}
+
+
+def bench_c5_adjoint(args, lbm, torch):
+    r = measure_c5_adjoint(lbm, torch, args.steps)
+    out = {"metric": "MLUPS", "value": r["N"] * args.steps / r["forward_s"] / 1e6, "unit": "MLUPS", "n_gpus": 1,
+           "steps": args.steps, "warmup": 0, "ms_per_step": r["forward_s"] * 1e3 / args.steps,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": r["workload"], "nodes": r["N"], "parallelism": "single GPU"},
+           "adjoint_s": r["adjoint_s"], "forward_s": r["forward_s"],
+           "adjoint_over_forward": r["adjoint_over_forward"], "J": r["J"], "grad_rp": r["grad_rp"],
+           "grad_phi_absmax": r["grad_phi_absmax"]}
     print(json.dumps(out), flush=True)
+
+
+def copy_probe_gbps(torch, nbytes=2 << 30, iters=5):
+    """Device-to-device copy of nbytes (read + write counted), timed with events on the
+    current stream: the bandwidth a plain streaming kernel reaches on this part."""
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(iters):
+        dst.copy_(src)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / iters
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2.0 * nbytes / (ms * 1e-3) / 1e9
 
 
 def main():
@@ -286,6 +319,10 @@ def main():
                     help="c4_electrode: secant updates of the current control per step")
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64",
                     help="population storage (arithmetic is FP64 either way)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="c3: skip the batched (c4) and adjoint (c5) ratios and the copy probe")
+    ap.add_argument("--extra-c4-steps", type=int, default=500)
+    ap.add_argument("--extra-c5-steps", type=int, default=2000)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -375,6 +412,26 @@ def main():
         "health": {"min_population": diag["min_population"], "n_nonfinite": diag["n_nonfinite"]},
         "roofline": roof,
     }
+    if args.workload == "c3" and not args.no_extras:
+        # the other targets of the method's metric, measured after the headline step:
+        # a plain copy's bandwidth beside the roofline fraction, batched vs sequential
+        # columns (C4) and adjoint vs forward cost (C5 as stated)
+        log("copy probe")
+        out["copy_probe_GBps"] = copy_probe_gbps(torch)
+        out["roofline"]["frac_of_copy_probe"] = out["roofline"]["achieved"] / out["copy_probe_GBps"] \
+            if out["roofline"]["unit"] == "GB/s" else None
+        log(f"c4 batched vs sequential, {args.extra_c4_steps} steps")
+        tb, ts, n4, ncol = measure_c4(lbm, torch, args.extra_c4_steps, 20, args.graph_steps)
+        log(f"c5 adjoint vs forward, {args.extra_c5_steps} steps")
+        r5 = measure_c5_adjoint(lbm, torch, args.extra_c5_steps)
+        out["ratios"] = {
+            "batched_vs_sequential": ts / tb,
+            "batched_config": f"c4 {ncol} packed D1Q3 columns ({n4} nodes), {args.extra_c4_steps} steps, "
+                              f"graph step loop of {args.graph_steps}; sequential: one context per column",
+            "adjoint_over_forward": r5["adjoint_over_forward"],
+            "adjoint_config": r5["workload"],
+            "adjoint_s": r5["adjoint_s"], "forward_s": r5["forward_s"], "adjoint_J": r5["J"],
+            "adjoint_n_nonfinite": r5["n_nonfinite"]}
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(args.workload)
