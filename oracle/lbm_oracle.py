@@ -86,11 +86,13 @@ Readings adopted where the paper is silent, garbled or self-inconsistent
       above it, a fixed number of updates, none where the two last currents
       are equal; the step then runs at the last iterate.
 
-Pins: tests/test_oracle_pins.py checks this code against statements independent of it
-(conservation, closed forms, equilibria, continuum models, marginalisation, mole and
-charge balances).  Parity unpinned (no pin of their own, covered by the GPU parity tests
-only): R5, R10, R11, the momentum-lattice rho of R24 in P and f^ex (its use in the
-mass-source ratio is pinned), and which upstream node the outflow of R18 copies from.
+Pins: tests/test_oracle_pins.py, tests/test_oracle_pins_flow.py and
+tests/test_oracle_tangent.py check this code against statements independent of it
+(conservation, closed forms, equilibria, continuum models and linear-wave rates,
+Graham's law, marginalisation, mole and charge balances, finite differences).
+Parity unpinned (no pin of their own, covered by the GPU parity tests only): R5, R10,
+the momentum-lattice rho of R24 in P and f^ex (its use in the mass-source ratio is
+pinned), and which upstream node the outflow of R18 copies from.
 """
 from __future__ import annotations
 
