@@ -298,6 +298,21 @@ typedef struct {
 } lbm_diag;
 int lbm_get_diagnostics(lbm_ctx *ctx, lbm_diag *out);
 
+/* lbm_get_diagnostics for callers that cannot allocate (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * reduction and the same totals, bit for bit (the per-block partials are added in
+ * block order on the device), with its scratch in a file-scope device array of
+ * 2 MiB (2^18 doubles) instead of context memory, and no allocation of any kind.
+ * Each GPU holds its own copy of that array until the process ends; it is set up
+ * when the first context is created on the GPU (LBM_ESTATE before that).  A lattice
+ * needs (ceil(N/256) + 1)(L + D + 2) doubles of it (L lattices, D dimensions: up to
+ * about 6 million nodes for 6 lattices in 3-D, 9.5 million for 3 lattices in 2-D);
+ * larger ones get LBM_EINVAL.
+ * Every call on a GPU uses that GPU's one array, so calls that overlap on one GPU
+ * (other host threads, other streams) race; nothing in it needs clearing between
+ * calls.  Synchronises the context's stream. */
+int lbm_get_diagnostics_static(lbm_ctx *ctx, lbm_diag *out);
+
 /* Kernel time of the last lbm_step call's launches, measured with HIP events
  * on the configured stream: total ms of the call and, over its last <= 64
  * steps, the per-step averages of the species kernel, the chemistry kernel and

@@ -6,6 +6,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <vector>
 
 #include "lbm.h"
@@ -295,6 +296,35 @@ int check_config(const lbm_config *cfg, lbm_ctx *c) {
   return LBM_OK;
 }
 
+// ---- file-scope scratch of lbm_get_diagnostics_static -------------------------
+// The partial sums and totals of the no-allocation diagnostics live in this array:
+// one copy on every GPU the library runs on, held until the process ends.  In host
+// code its name is only a stand-in; the device address of each GPU's copy is taken
+// once per device at set-up (hipGetSymbolAddress with that device current) and used
+// wherever host code passes the array on.
+constexpr size_t kScratchDoubles = size_t(1) << 18;   // 2 MiB
+constexpr int kMaxDevices = 64;
+__device__ __align__(256) double scratch[kScratchDoubles];
+double *g_scratch_ptr[kMaxDevices];
+std::mutex g_scratch_mu;
+
+// Address of this device's scratch copy, set up on first use per device (called
+// from the init calls, with the context's device current).
+int setup_scratch(lbm_ctx *c) {
+  int dev = 0;
+  HIPCHK(c, hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(c, LBM_EINVAL, "device %d beyond %d", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(c, LBM_EHIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    g_scratch_ptr[dev] = static_cast<double *>(ptr);
+  }
+  return LBM_OK;
+}
+
 int common_init(const lbm_config *cfg, int N, const double *X0, const double *P0, const double *T0,
                 lbm_ctx *c) {
   c->dim = cfg->dim;
@@ -400,7 +430,7 @@ int common_init(const lbm_config *cfg, int N, const double *X0, const double *P0
   rc = rebuild_populations(c);
   if (rc) return rc;
   HIPCHK(c, hipStreamSynchronize(c->stream));
-  return LBM_OK;
+  return setup_scratch(c);
 }
 
 int sample_order(lbm_ctx *c, ChemSpec &sp);
@@ -1265,6 +1295,41 @@ int lbm_get_diagnostics(lbm_ctx *c, lbm_diag *out) {
     bad += r[c->L + c->dim + 1];
   }
   out->min_population = mn;
+  out->n_nonfinite = (int64_t)bad;
+  out->steps_done = c->steps_done;
+  if (bad > 0) return fail(c, LBM_EUNSTABLE, "%lld non-finite populations", (long long)bad);
+  return LBM_OK;
+}
+
+int lbm_get_diagnostics_static(lbm_ctx *c, lbm_diag *out) {
+  if (!c || !out) return LBM_EINVAL;
+  memset(out, 0, sizeof(*out));
+  const int W = c->L + c->dim + 2;
+  const size_t need = (size_t)c->diag_blocks * W + W;
+  if (need > kScratchDoubles)
+    return fail(c, LBM_EINVAL, "lbm_get_diagnostics_static needs %zu doubles of scratch for %d nodes; "
+                "the static buffer holds %zu (at most about %zu nodes for this lattice set)",
+                need, c->N, kScratchDoubles, (kScratchDoubles - W) / W * 256);
+  int dev = 0;
+  HIPCHK(c, hipGetDevice(&dev));
+  double *ptr = (dev >= 0 && dev < kMaxDevices) ? g_scratch_ptr[dev] : nullptr;
+  if (!ptr) return fail(c, LBM_ESTATE, "no static scratch set up on device %d (create a context there first)", dev);
+  KParams p = base_params(c);
+  fill_prev(c, p);
+  // every block writes all W of its partials and the totals pass writes all W
+  // totals, so nothing in the array has to start at zero
+  double *partials = ptr, *totals = ptr + (size_t)c->diag_blocks * W;
+  HIPCHK(c, launch_diag(c->dim, c->L, c->M, p, c->pop[c->cur], partials, c->diag_blocks, c->stream));
+  HIPCHK(c, launch_diag_totals(partials, c->diag_blocks, W, totals, c->stream));
+  double t[64];
+  HIPCHK(c, hipMemcpyAsync(t, totals, sizeof(double) * W, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (int a = 0; a < c->M && a < 8; ++a) out->species_mass[a] = t[a];
+  out->mixture_mass = t[c->M];
+  if (c->energy) out->energy_total = t[c->M + 1];
+  for (int d = 0; d < c->dim; ++d) out->mixture_momentum[d] = t[c->L + d];
+  out->min_population = t[c->L + c->dim];
+  const double bad = t[c->L + c->dim + 1];
   out->n_nonfinite = (int64_t)bad;
   out->steps_done = c->steps_done;
   if (bad > 0) return fail(c, LBM_EUNSTABLE, "%lld non-finite populations", (long long)bad);

@@ -190,6 +190,7 @@ hipError_t launch_surface_energy(const KParams &p, hipStream_t s);
 hipError_t launch_moments(int dim, const KParams &p, double *out, hipStream_t s);
 hipError_t launch_diag(int dim, int L, int Mmom, const KParams &p, const void *pop, double *partials,
                        int nblocks, hipStream_t s);
+hipError_t launch_diag_totals(const double *partials, int nblocks, int W, double *totals, hipStream_t s);
 int chem_supported(int M, int K);
 
 // adjoint of the isothermal reaction-free step (lbm_adjoint.hip)

@@ -1311,6 +1311,21 @@ __global__ __launch_bounds__(256) void k_diag(int L, int Mmom, const KParams p, 
   if (t == 0) partials[(size_t)blockIdx.x * W + L + D + 1] = nb;
 }
 
+// Totals of the per-block partials [nblocks][W]: thread w adds column w over the
+// blocks in block order (the minimum for column W - 2), the order a host loop over
+// the partials takes, so the totals equal such a loop's bit for bit.
+__global__ __launch_bounds__(64) void k_diag_totals(const double *partials, int nblocks, int W, double *totals) {
+  const int w = threadIdx.x;
+  if (w >= W) return;
+  const bool is_min = w == W - 2;
+  double acc = is_min ? INFINITY : 0.0;
+  for (int b = 0; b < nblocks; ++b) {
+    const double v = partials[(size_t)b * W + w];
+    acc = is_min ? fmin(acc, v) : acc + v;
+  }
+  totals[w] = acc;
+}
+
 unsigned padded_blocks(int N, int bs) {
   unsigned nb = (unsigned)((N + bs - 1) / bs);
   return (nb + 7u) & ~7u;
@@ -1594,6 +1609,12 @@ hipError_t diag_dispatch(int dim, int L, int Mmom, const KParams &p, const void 
     case 2: hipLaunchKernelGGL((k_diag<2, PT>), dim3(nblocks), dim3(256), 0, s, L, Mmom, p, q, partials); break;
     default: hipLaunchKernelGGL((k_diag<3, PT>), dim3(nblocks), dim3(256), 0, s, L, Mmom, p, q, partials); break;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_diag_totals(const double *partials, int nblocks, int W, double *totals, hipStream_t s) {
+  if (W > 64) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_diag_totals, dim3(1), dim3(64), 0, s, partials, nblocks, W, totals);
   return hipGetLastError();
 }
 

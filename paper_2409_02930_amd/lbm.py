@@ -95,6 +95,7 @@ def _load():
         "lbm_moments": ([vp, C.c_uint32, vp, C.c_int32], C.c_int),
         "lbm_moment_rows": ([vp, C.c_uint32, _ip], C.c_int),
         "lbm_get_diagnostics": ([vp, C.POINTER(lbm_diag)], C.c_int),
+        "lbm_get_diagnostics_static": ([vp, C.POINTER(lbm_diag)], C.c_int),
         "lbm_set_timing": ([vp, C.c_int32], C.c_int),
         "lbm_get_timing": ([vp, _dp, _dp, _dp, _dp], C.c_int),
         "lbm_save": ([vp, vp, C.POINTER(C.c_size_t)], C.c_int),
@@ -114,7 +115,7 @@ _lib = _load()
 EXPORTED = ["lbm_init", "lbm_init_columns", "lbm_set_porous_field", "lbm_set_mechanism",
             "lbm_set_chem_kernel", "lbm_set_faradaic_source", "lbm_set_electrode", "lbm_get_charge",
             "lbm_set_current_target", "lbm_get_electrode_potential", "lbm_step", "lbm_set_graph", "lbm_adjoint_outlet_flux", "lbm_moments", "lbm_moment_rows",
-            "lbm_get_diagnostics", "lbm_set_timing", "lbm_get_timing", "lbm_save", "lbm_load",
+            "lbm_get_diagnostics", "lbm_get_diagnostics_static", "lbm_set_timing", "lbm_get_timing", "lbm_save", "lbm_load",
             "lbm_last_error", "lbm_destroy"]
 
 
@@ -342,6 +343,18 @@ class Lattice:
     def diagnostics(self, check=True):
         d = lbm_diag()
         rc = _lib.lbm_get_diagnostics(self.ctx, C.byref(d))
+        if check:
+            self._check(rc)
+        return {"species_mass": np.array(d.species_mass[:self.M]), "mixture_mass": d.mixture_mass,
+                "mixture_momentum": np.array(d.mixture_momentum[:self.dim]),
+                "energy_total": d.energy_total, "min_population": d.min_population,
+                "n_nonfinite": d.n_nonfinite, "steps_done": d.steps_done, "rc": rc}
+
+    def diagnostics_static(self, check=True):
+        """lbm_get_diagnostics_static: the same totals from the library's file-scope
+        scratch, without any allocation (see include/lbm.h)."""
+        d = lbm_diag()
+        rc = _lib.lbm_get_diagnostics_static(self.ctx, C.byref(d))
         if check:
             self._check(rc)
         return {"species_mass": np.array(d.species_mass[:self.M]), "mixture_mass": d.mixture_mass,
