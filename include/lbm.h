@@ -245,7 +245,9 @@ int lbm_get_electrode_potential(lbm_ctx *ctx, double *phi_line);
  * finalNumericalEquationsReactive, with the reaction populations of eq fsourceHetero),
  * the local chemistry (Section 4) and the momentum and energy collisions (eqs f_source,
  * g_source).  n_steps >= 0; returns LBM_EHIP when a launch fails (the context is then
- * unusable) and allocates nothing. */
+ * unusable).  Allocates nothing once the run-time generated kernels exist: the step
+ * after the first compiles the mechanism's chemistry kernel, and the first fused
+ * launch (lbm_set_persistent) compiles that kernel and sizes its buffers. */
 int lbm_step(lbm_ctx *ctx, int64_t n_steps);
 
 /* Graph step loop: with steps_per_graph = G (even, >= 2), lbm_step captures G
@@ -258,6 +260,48 @@ int lbm_step(lbm_ctx *ctx, int64_t n_steps);
  * timing (lbm_get_timing) covers the plain-launch steps only.  For launch-bound
  * runs such as the batched 1-D columns. */
 int lbm_set_graph(lbm_ctx *ctx, int32_t steps_per_graph);
+
+/* Persistent launch of one-dimensional lattices (packed columns of lbm_init_columns,
+ * or a D1Q3 grid): with steps_per_launch = S (odd, 1..7) lbm_step advances the run S
+ * whole steps per launch of one fused kernel, compiled at run time with the
+ * context's constants and the mechanism's chemistry.  Each wave of 64 lanes owns
+ * 64 - 4 S consecutive nodes and carries a window of 64 nodes (2 S more on either
+ * side) through the S steps in registers: species lattices with their reaction
+ * populations (Section 2.3, eqs finalNumericalEquationsReactive, fsourceHetero), the
+ * node chemistry (Section 4) and the momentum lattice (eqs Pex, feqmix, f_source),
+ * the same arithmetic in the same order as the separate kernels.  A step at a node
+ * depends on the previous state within two nodes, so only the window's inner nodes
+ * are stored; nothing is exchanged between waves within a launch.  waves_per_block
+ * (1, 2 or 4) sets the workgroup size.  Covers isothermal D1Q3 runs with FP64
+ * populations, closed x ends, no electrode coupling, and either no chemistry or a
+ * mechanism with the generated chemistry kernel (with or without a Faradaic
+ * source); LBM_EINVAL otherwise.  Steps before the chemistry kernel exists (the
+ * first step) and a remainder shorter than S run the separate kernels; with the
+ * graph step loop the graph holds whole launches (its length rounds up to a
+ * multiple of 2 S).  0 switches it off (default). */
+int lbm_set_persistent(lbm_ctx *ctx, int32_t steps_per_launch, int32_t waves_per_block);
+
+/* One measured configuration of the step loop (lbm_autotune). */
+typedef struct {
+  int32_t fused;             /* 0: separate kernels, 1: fused persistent launch */
+  int32_t graph_steps;       /* graph step loop length (0: plain launches) */
+  int32_t steps_per_launch;  /* fused: steps per launch */
+  int32_t waves_per_block;   /* fused: waves per workgroup */
+  double ms_per_step;        /* measured with HIP events on the context's stream */
+} lbm_tune_entry;
+
+/* Autotuner of the step loop: from the current state (past the first step;
+ * LBM_ESTATE before), times about trial_steps steps (rounded up to whole launches)
+ * of each configuration -- the separate kernels with plain launches and with the
+ * graph step loop of 32 steps and, where lbm_set_persistent applies, the fused
+ * launch at 1, 3 and 5 steps per launch with 1 or 2 waves per block -- restoring
+ * the state before each, installs the fastest and restores the state again, so the
+ * run continues from where it was.  Writes up to max_entries entries to table
+ * (host memory, caller-owned) and their number to n_entries.  Needs a non-null
+ * stream.  Synchronises the stream; allocates a host snapshot of the state
+ * (lbm_save) for the call and compiles the fused variants it times. */
+int lbm_autotune(lbm_ctx *ctx, int32_t trial_steps, lbm_tune_entry *table, int32_t max_entries,
+                 int32_t *n_entries);
 
 /* Gradient of an outlet-flux objective by the adjoint of the step (isothermal,
  * no surface mechanism or Faradaic source, D1Q3/D2Q9/D3Q27 grid with FP64

@@ -89,6 +89,16 @@ struct lbm_ctx {
   int gexec_cur = -1;                   // population buffer index the capture started from
   int gexec_q = -1;                     // record buffer parity (steps_done & 1) it started from
   hipFunction_t gexec_chem = nullptr;   // chemistry kernel the capture launched
+  double *gexec_theta = nullptr;        // coverage buffer the capture started from
+  hipFunction_t gexec_win = nullptr;    // fused kernel the capture launched
+  // fused multi-step launch of 1-D lattices (lbm_set_persistent)
+  int win_steps = 0;                    // whole steps per launch (odd), 0: off
+  int win_wpb = 1;                      // waves per block
+  hipFunction_t win_fn = nullptr;       // compiled for the set-up in win_key
+  long long win_key[8] = {};
+  double *theta_alt = nullptr;          // second coverage buffer: a launch reads one, writes the other
+  double *win_sk = nullptr;             // rate constants per wave and lane
+  size_t win_sk_n = 0;
   int K = 0;
   // timing
   int timing = 0;
@@ -440,10 +450,11 @@ int sample_order(lbm_ctx *c, ChemSpec &sp);
 // the chemistry input and coverages of the last step, so it is called after a
 // first step has run with the generic kernel; compilation happens once per
 // mechanism and process.
-int specialize_chemistry(lbm_ctx *c) {
+// Mechanism of the context as written into generated code (elimination order
+// excluded).
+void fill_chem_spec(const lbm_ctx *c, ChemSpec &sp) {
   const int M = c->M, K = c->K, S = M + K;
   const ChemParams &cp = c->chem;
-  ChemSpec sp;
   memset(&sp, 0, sizeof(sp));
   sp.M = M;
   sp.K = K;
@@ -472,6 +483,11 @@ int specialize_chemistry(lbm_ctx *c) {
   }
   sp.l_tpb = c->chem_host.l_tpb;
   sp.R_U = kRU;
+}
+
+int specialize_chemistry(lbm_ctx *c) {
+  ChemSpec sp;
+  fill_chem_spec(c, sp);
   if (c->have_perm) {
     memcpy(sp.perm, c->chem_perm, sizeof(sp.perm));
   } else {
@@ -626,12 +642,144 @@ int enqueue_step(lbm_ctx *c, int record_slot) {
   return LBM_OK;
 }
 
+// Whether the fused 1-D kernel covers this context: D1Q3, isothermal, FP64
+// populations, non-periodic x ends, and either the specialised chemistry of a
+// mechanism (with or without a Faradaic source) or no chemistry at all, no
+// electrode coupling.  Returns a reason when it does not.
+const char *window_unsupported(const lbm_ctx *c) {
+  if (c->dim != 1) return "the fused kernel is for one-dimensional lattices";
+  if (c->energy) return "the fused kernel has no energy lattice";
+  if (c->fp32) return "the fused kernel stores FP64 populations";
+  if (c->bc_lo == BC_PERIODIC || c->bc_hi == BC_PERIODIC) return "the fused kernel needs closed x ends";
+  if (c->electrode || c->n_secant) return "the fused kernel has no electrode coupling";
+  if (c->has_faradaic && !c->has_mech) return "a Faradaic source without a mechanism runs the separate kernels";
+  if (c->has_mech && c->chem_kernel != LBM_CHEM_SPECIALIZED) return "the fused kernel takes the specialised chemistry";
+  return nullptr;
+}
+
+// A launch can start here: past the first step, the chemistry specialised.
+bool window_ready(const lbm_ctx *c) {
+  if (!c->win_steps || c->first_step || c->steps_done < 1 || window_unsupported(c)) return false;
+  if (c->has_mech && (!c->chem_fn || !c->have_perm)) return false;
+  return true;
+}
+
+int window_blocks(const lbm_ctx *c, int steps, int wpb) {
+  const int use = 64 - 4 * steps;
+  const int waves = (c->N + use - 1) / use;
+  return (waves + wpb - 1) / wpb;
+}
+
+// Compiles the fused kernel for the current configuration and sizes its buffers.
+int window_prepare(lbm_ctx *c) {
+  // what the generated source depends on beyond the constants fixed at init
+  const long long key[8] = {c->win_steps, c->win_wpb, c->has_mech, c->has_faradaic, c->knudsen,
+                            needs_v(c) ? 1 : 0, (long long)(intptr_t)c->chem_fn, c->K};
+  if (c->win_fn && memcmp(key, c->win_key, sizeof(key)) == 0) return LBM_OK;
+  WindowSpec w;
+  memset(&w, 0, sizeof(w));
+  const KParams p = base_params(c);
+  w.M = c->M;
+  w.faradaic = c->has_faradaic;
+  w.knudsen = c->knudsen;
+  w.need_v = needs_v(c) ? 1 : 0;
+  w.bc_lo = c->bc_lo;
+  w.bc_hi = c->bc_hi;
+  w.steps = c->win_steps;
+  w.wpb = c->win_wpb;
+  w.theta_ref = p.theta_ref;
+  w.inv_T_ref = p.inv_T_ref;
+  w.nu = p.nu;
+  memcpy(w.mmin_over_m, p.mmin_over_m, sizeof(w.mmin_over_m));
+  memcpy(w.inv_m, p.inv_m, sizeof(w.inv_m));
+  memcpy(w.imD, p.imD, sizeof(w.imD));
+  w.inlet[0] = c->inlet[0];
+  w.inlet[1] = c->inlet[1];
+  ChemSpec sp;
+  if (c->has_mech) {
+    fill_chem_spec(c, sp);
+    memcpy(sp.perm, c->chem_perm, sizeof(sp.perm));
+    const size_t need = (size_t)window_blocks(c, c->win_steps, c->win_wpb) * c->win_wpb * 2 * c->chem.R * 64;
+    if (need > c->win_sk_n) {
+      dfree(c->win_sk);
+      c->win_sk = nullptr;
+      c->win_sk_n = 0;
+      const int rc = dalloc(c, &c->win_sk, need);
+      if (rc) return rc;
+      c->win_sk_n = need;
+    }
+    if (!c->theta_alt) {
+      const int rc = dalloc(c, &c->theta_alt, (size_t)c->K * c->N);
+      if (rc) return rc;
+    }
+  }
+  std::string log;
+  hipFunction_t fn = nullptr;
+  const hipError_t e = window_specialize(c->has_mech ? &sp : nullptr, w, &fn, &log);
+  if (e != hipSuccess) return fail(c, LBM_EHIP, "fused 1-D kernel: %s (%s)", hipGetErrorString(e), log.c_str());
+  c->win_fn = fn;
+  memcpy(c->win_key, key, sizeof(key));
+  return LBM_OK;
+}
+
+// One launch of win_steps whole steps (an odd count: the populations and the
+// node records land in the buffers the last of that many separate steps would
+// write, the coverages in the other coverage buffer).
+int enqueue_window(lbm_ctx *c) {
+  const int rc = window_prepare(c);
+  if (rc) return rc;
+  if (!c->win_fn || (c->has_mech && (!c->theta || !c->theta_alt || !c->win_sk)))
+    return fail(c, LBM_ESTATE, "fused 1-D kernel: buffers missing");
+  const int q = (int)(c->steps_done & 1);
+  WinArgs a;
+  memset(&a, 0, sizeof(a));
+  a.N = c->N;
+  a.nx = c->colflag ? 0 : c->nx;
+  a.colflag = reinterpret_cast<const signed char *>(c->colflag);
+  a.pin = c->pop[c->cur];
+  a.pout = c->pop[1 - c->cur];
+  a.rec_prev = c->rec[1 - q];
+  a.rec_out = c->rec[q];
+  a.phi = c->phi;
+  a.kfac = c->kfac;
+  a.Tf = c->Tfield;
+  a.far = c->has_faradaic ? c->faradaic : nullptr;
+  a.theta_in = c->theta;
+  a.theta_out = c->theta_alt;
+  a.rrho = c->rrho;
+  a.rRT = c->rRT;
+  a.rA = c->rA;
+  a.rFk = c->rFk;
+  a.srcsum = c->srcsum;
+  a.skg = c->win_sk;
+  a.dt = c->dt;
+  a.rho_unit = c->rho_unit;
+  a.fuel = c->chem.fuel;
+  a.product = c->chem.product;
+  HIPCHK(c, launch_window(c->win_fn, a, window_blocks(c, c->win_steps, c->win_wpb), c->win_wpb, c->stream));
+  c->cur = 1 - c->cur;
+  c->first_step = 0;
+  c->steps_done += c->win_steps;
+  if (c->has_mech) std::swap(c->theta, c->theta_alt);
+  return LBM_OK;
+}
+
+// Steps of one graph replay: graph_steps, or with the fused kernel the next
+// multiple of twice its steps per launch (every buffer back where it started).
+int graph_len(const lbm_ctx *c) {
+  if (!c->win_steps) return c->graph_steps;
+  const int two = 2 * c->win_steps;
+  return (c->graph_steps + two - 1) / two * two;
+}
+
 void drop_graph(lbm_ctx *c) {
   if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
   c->gexec = nullptr;
   c->gexec_cur = -1;
   c->gexec_q = -1;
   c->gexec_chem = nullptr;
+  c->gexec_theta = nullptr;
+  c->gexec_win = nullptr;
 }
 
 // Captures graph_steps steps starting from the current state into c->gexec.
@@ -640,14 +788,30 @@ int capture_steps(lbm_ctx *c) {
   drop_graph(c);
   const int cur0 = c->cur, first0 = c->first_step;
   const long long done0 = c->steps_done;
+  if (c->win_steps) {                   // compile and size the buffers before the capture
+    const int rc0 = window_prepare(c);
+    if (rc0) return rc0;
+  }
+  double *theta0 = c->theta, *theta_alt0 = c->theta_alt;   // the launches swap them
   HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
   int rc = LBM_OK;
-  for (int s = 0; s < c->graph_steps && rc == LBM_OK; ++s) rc = enqueue_step(c, -1);
+  const int len = graph_len(c);
+  for (int s = 0; s < len && rc == LBM_OK;) {
+    if (window_ready(c) && len - s >= c->win_steps) {
+      rc = enqueue_window(c);
+      s += c->win_steps;
+    } else {
+      rc = enqueue_step(c, -1);
+      ++s;
+    }
+  }
   hipGraph_t g = nullptr;
   const hipError_t e = hipStreamEndCapture(c->stream, &g);
   c->cur = cur0;
   c->first_step = first0;
   c->steps_done = done0;
+  c->theta = theta0;
+  c->theta_alt = theta_alt0;
   if (rc) {
     if (g) (void)hipGraphDestroy(g);
     return rc;
@@ -662,6 +826,8 @@ int capture_steps(lbm_ctx *c) {
   c->gexec_cur = cur0;
   c->gexec_q = (int)(done0 & 1);
   c->gexec_chem = c->chem_fn;
+  c->gexec_theta = theta0;
+  c->gexec_win = c->win_fn;
   return LBM_OK;
 }
 
@@ -881,6 +1047,8 @@ int lbm_set_mechanism(lbm_ctx *c, const lbm_mechanism *mech) {
     return fail(c, LBM_EINVAL, "theta0 must sum to 1 on every surface phase");
   dfree(c->theta);
   c->theta = nullptr;
+  dfree(c->theta_alt);
+  c->theta_alt = nullptr;
   int rc = dalloc(c, &c->theta, (size_t)K * c->N);
   if (rc) return rc;
   std::vector<double> th((size_t)K * c->N);
@@ -1055,6 +1223,95 @@ int lbm_set_graph(lbm_ctx *c, int32_t steps_per_graph) {
   return LBM_OK;
 }
 
+int lbm_set_persistent(lbm_ctx *c, int32_t steps_per_launch, int32_t waves_per_block) {
+  if (!c) return LBM_EINVAL;
+  if (steps_per_launch == 0) {
+    c->win_steps = 0;
+    drop_graph(c);
+    return LBM_OK;
+  }
+  if (steps_per_launch < 1 || steps_per_launch > kWindowMaxSteps || steps_per_launch % 2 == 0)
+    return fail(c, LBM_EINVAL, "steps_per_launch must be 0 or odd, 1..%d", kWindowMaxSteps);
+  if (waves_per_block != 1 && waves_per_block != 2 && waves_per_block != 4)
+    return fail(c, LBM_EINVAL, "waves_per_block must be 1, 2 or 4");
+  const char *why = window_unsupported(c);
+  if (why) return fail(c, LBM_EINVAL, "%s", why);
+  c->win_steps = steps_per_launch;
+  c->win_wpb = waves_per_block;
+  drop_graph(c);
+  return LBM_OK;
+}
+
+int lbm_autotune(lbm_ctx *c, int32_t trial_steps, lbm_tune_entry *table, int32_t max_entries,
+                 int32_t *n_entries) {
+  if (!c || !n_entries || (max_entries > 0 && !table)) return LBM_EINVAL;
+  if (trial_steps < 2) return fail(c, LBM_EINVAL, "trial_steps must be >= 2");
+  if (c->steps_done < 1 || c->first_step) return fail(c, LBM_ESTATE, "lbm_autotune needs a completed first step");
+  if (!c->stream) return fail(c, LBM_EINVAL, "lbm_autotune needs a non-null stream");
+  // candidates: the separate kernels (plain launches, graph of 32 steps) and,
+  // where it applies, the fused kernel at 1, 3, 5 steps per launch and 1 or 2
+  // waves per block
+  std::vector<lbm_tune_entry> cand;
+  cand.push_back({0, 0, 0, 0, 0.0});   // {fused, graph_steps, steps_per_launch, waves_per_block, ms}
+  cand.push_back({0, 32, 0, 0, 0.0});
+  if (!window_unsupported(c))
+    for (int st : {1, 3, 5})
+      for (int wpb : {1, 2}) cand.push_back({1, 0, st, wpb, 0.0});
+  size_t snap_n = 0;
+  int rc = lbm_save(c, nullptr, &snap_n);
+  if (rc) return rc;
+  std::vector<char> snap(snap_n);
+  rc = lbm_save(c, snap.data(), &snap_n);
+  if (rc) return rc;
+  const int graph0 = c->graph_steps, win0 = c->win_steps, wpb0 = c->win_wpb, timing0 = c->timing;
+  c->timing = 0;
+  hipEvent_t e0, e1;
+  HIPCHK(c, hipEventCreate(&e0));
+  HIPCHK(c, hipEventCreate(&e1));
+  int best = -1;
+  for (size_t k = 0; k < cand.size() && rc == LBM_OK; ++k) {
+    lbm_tune_entry &t = cand[k];
+    rc = lbm_load(c, snap.data(), snap_n);
+    if (rc) break;
+    c->graph_steps = t.graph_steps;
+    c->win_steps = t.steps_per_launch;
+    c->win_wpb = t.waves_per_block ? t.waves_per_block : 1;
+    drop_graph(c);
+    // whole launches or graph replays only: a multiple of 2 x steps per launch
+    const int unit = t.graph_steps ? graph_len(c) : (t.steps_per_launch ? 2 * t.steps_per_launch : 2);
+    const int n = (trial_steps + unit - 1) / unit * unit;
+    rc = lbm_step(c, unit);                  // compiles and captures outside the timed steps
+    if (rc) break;
+    HIPCHK(c, hipEventRecord(e0, c->stream));
+    rc = lbm_step(c, n);
+    if (rc) break;
+    HIPCHK(c, hipEventRecord(e1, c->stream));
+    HIPCHK(c, hipEventSynchronize(e1));
+    float ms = 0.0f;
+    HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+    t.ms_per_step = (double)ms / n;
+    if (best < 0 || t.ms_per_step < cand[best].ms_per_step) best = (int)k;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  c->timing = timing0;
+  const int rcl = lbm_load(c, snap.data(), snap_n);
+  if (rc || rcl || best < 0) {
+    c->graph_steps = graph0;
+    c->win_steps = win0;
+    c->win_wpb = wpb0;
+    drop_graph(c);
+    return rc ? rc : (rcl ? rcl : fail(c, LBM_EHIP, "no candidate measured"));
+  }
+  c->graph_steps = cand[best].graph_steps;
+  c->win_steps = cand[best].steps_per_launch;
+  c->win_wpb = cand[best].waves_per_block ? cand[best].waves_per_block : 1;
+  drop_graph(c);
+  *n_entries = (int32_t)cand.size();
+  for (int k = 0; k < (int)cand.size() && k < max_entries; ++k) table[k] = cand[k];
+  return LBM_OK;
+}
+
 int lbm_step(lbm_ctx *c, int64_t n_steps) {
   if (!c) return LBM_EINVAL;
   if (n_steps < 0) return fail(c, LBM_EINVAL, "negative step count");
@@ -1070,15 +1327,23 @@ int lbm_step(lbm_ctx *c, int64_t n_steps) {
       if (rc) return rc;
     }
     // graph replay: whole captured sequences from the parity the capture started at
-    if (graph_ready(c) && n_steps - s >= c->graph_steps &&
-        (!c->gexec || (c->gexec_cur == c->cur && c->gexec_q == (int)(c->steps_done & 1)))) {
-      if (!c->gexec || c->gexec_chem != c->chem_fn) {
+    const int len = graph_len(c);
+    if (graph_ready(c) && n_steps - s >= len &&
+        (!c->gexec || (c->gexec_cur == c->cur && c->gexec_q == (int)(c->steps_done & 1) &&
+                       c->gexec_theta == c->theta))) {
+      if (!c->gexec || c->gexec_chem != c->chem_fn || (c->win_steps && c->gexec_win != c->win_fn)) {
         const int rc = capture_steps(c);
         if (rc) return rc;
       }
       HIPCHK(c, hipGraphLaunch(c->gexec, c->stream));
-      c->steps_done += c->graph_steps;          // an even count: the buffer parity is unchanged
-      s += c->graph_steps;
+      c->steps_done += len;                     // an even count: the buffer parity is unchanged
+      s += len;
+      continue;
+    }
+    if (window_ready(c) && n_steps - s >= c->win_steps) {   // fused launch of several steps
+      const int rc = enqueue_window(c);
+      if (rc) return rc;
+      s += c->win_steps;
       continue;
     }
     const int rec = (c->timing && s >= first_timed) ? slot++ : -1;
@@ -1507,6 +1772,8 @@ void lbm_destroy(lbm_ctx *c) {
   for (double *b : bufs) dfree(b);
   dfree(c->colflag);
   dfree(c->d_line_off);
+  dfree(c->theta_alt);
+  dfree(c->win_sk);
   dfree(c->chem_tab);
   delete c;
 }

@@ -209,7 +209,25 @@ hipError_t launch_adjoint(int dim, const KParams &k, const AdjBuffers &b, int st
 
 // specialised chemistry (chem_jit.hip)
 std::string chem_specialized_source(const ChemSpec &spec);
+std::string chem_node_source(const ChemSpec &spec);
 void chem_choose_order(ChemSpec &spec, int ns, const double *T, const double *phi, const double *C, double h,
                        double a_s, double gam);
 hipError_t chem_specialize(const ChemSpec &spec, hipFunction_t *fn, std::string *log);
 hipError_t launch_chem_specialized(hipFunction_t fn, const ChemParams &cp, hipStream_t s);
+
+// Fused multi-step kernel for one-dimensional lattices (lbm_window.h), compiled at
+// run time with the context's constants and, with a mechanism, its chemistry.
+#include "lbm_window_args.h"
+
+struct WindowSpec {
+  int M, faradaic, knudsen, need_v, bc_lo, bc_hi;
+  int steps;                // whole steps per launch (odd)
+  int wpb;                  // waves per block
+  double theta_ref, inv_T_ref, nu;
+  double mmin_over_m[LBM_MMAX], inv_m[LBM_MMAX], imD[LBM_MMAX * LBM_MMAX];
+  InletState inlet[2];
+};
+constexpr int kWindowMaxSteps = 7;   // 64 - 4 * 7 = 36 nodes per window at the most
+std::string window_program_source(const ChemSpec *chem, const WindowSpec &w);
+hipError_t window_specialize(const ChemSpec *chem, const WindowSpec &w, hipFunction_t *fn, std::string *log);
+hipError_t launch_window(hipFunction_t fn, const WinArgs &a, int blocks, int wpb, hipStream_t s);

@@ -67,6 +67,11 @@ class lbm_diag(C.Structure):
     ]
 
 
+class lbm_tune_entry(C.Structure):
+    _fields_ = [("fused", C.c_int32), ("graph_steps", C.c_int32), ("steps_per_launch", C.c_int32),
+                ("waves_per_block", C.c_int32), ("ms_per_step", C.c_double)]
+
+
 class LBMError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"lbm error {code}: {msg}")
@@ -91,6 +96,8 @@ def _load():
         "lbm_get_electrode_potential": ([vp, _dp], C.c_int),
         "lbm_step": ([vp, C.c_int64], C.c_int),
         "lbm_set_graph": ([vp, C.c_int32], C.c_int),
+        "lbm_set_persistent": ([vp, C.c_int32, C.c_int32], C.c_int),
+        "lbm_autotune": ([vp, C.c_int32, C.POINTER(lbm_tune_entry), C.c_int32, C.POINTER(C.c_int32)], C.c_int),
         "lbm_adjoint_outlet_flux": ([vp, C.c_int64, C.c_int32, _dp, vp, _dp, C.c_int32], C.c_int),
         "lbm_moments": ([vp, C.c_uint32, vp, C.c_int32], C.c_int),
         "lbm_moment_rows": ([vp, C.c_uint32, _ip], C.c_int),
@@ -114,7 +121,7 @@ _lib = _load()
 
 EXPORTED = ["lbm_init", "lbm_init_columns", "lbm_set_porous_field", "lbm_set_mechanism",
             "lbm_set_chem_kernel", "lbm_set_faradaic_source", "lbm_set_electrode", "lbm_get_charge",
-            "lbm_set_current_target", "lbm_get_electrode_potential", "lbm_step", "lbm_set_graph", "lbm_adjoint_outlet_flux", "lbm_moments", "lbm_moment_rows",
+            "lbm_set_current_target", "lbm_get_electrode_potential", "lbm_step", "lbm_set_graph", "lbm_set_persistent", "lbm_autotune", "lbm_adjoint_outlet_flux", "lbm_moments", "lbm_moment_rows",
             "lbm_get_diagnostics", "lbm_get_diagnostics_static", "lbm_set_timing", "lbm_get_timing", "lbm_save", "lbm_load",
             "lbm_last_error", "lbm_destroy"]
 
@@ -306,6 +313,20 @@ class Lattice:
     def set_graph(self, steps_per_graph):
         """Replay whole blocks of `steps_per_graph` (even) steps as a HIP graph; 0 = off."""
         self._check(_lib.lbm_set_graph(self.ctx, int(steps_per_graph)))
+
+    def set_persistent(self, steps_per_launch, waves_per_block=1):
+        """Fused launch of `steps_per_launch` (odd) whole steps for 1-D lattices; 0 = off."""
+        self._check(_lib.lbm_set_persistent(self.ctx, int(steps_per_launch), int(waves_per_block)))
+
+    def autotune(self, trial_steps=200):
+        """Times the step-loop configurations from the current state, installs the fastest
+        and returns the table [(fused, graph_steps, steps_per_launch, waves_per_block,
+        ms_per_step)] (the state is left where it was)."""
+        tab = (lbm_tune_entry * 16)()
+        n = C.c_int32()
+        self._check(_lib.lbm_autotune(self.ctx, int(trial_steps), tab, 16, C.byref(n)))
+        return [(t.fused, t.graph_steps, t.steps_per_launch, t.waves_per_block, t.ms_per_step)
+                for t in tab[:n.value]]
 
     def moment_rows(self, mask):
         r = C.c_int32()
