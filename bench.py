@@ -140,24 +140,45 @@ def cpu_baseline(name, budget_s=20.0):
             "sample": f"{sample}: {steps} steps of {w.N} nodes in {el:.1f} s, numpy single thread"}
 
 
-def measure_c4(lbm, torch, steps, warmup, graph_steps):
+def c4_batch(lbm, cols, stream, chem=True):
+    """The packed columns in one context; chem=False drops the mechanism and the Faradaic
+    source and starts from a uniform composition (0.5, 0.2, 0.1, 0.1, 0.1) against the
+    inlet's (0.97, 0.03, 0, 0, 0): batched columns without surface chemistry."""
+    cat = lambda k: np.concatenate([getattr(c, k) for c in cols], axis=-1)
+    w0 = cols[0]
+    X0 = cat("X0")
+    if not chem:
+        X0 = np.repeat(np.array([0.5, 0.2, 0.1, 0.1, 0.1])[:, None], X0.shape[1], axis=1)
+    lat = lbm.Lattice(1, int(sum(c.nx for c in cols)), 1, 1, w0.molar_mass, w0.D_ref_lat, X0, cat("T0"),
+                      cat("P0"), T_ref=w0.T_ref, bc_lo=w0.bc_lo, bc_hi=w0.bc_hi, inlet_lo_X=w0.inlet_lo_X,
+                      inlet_T=w0.inlet_T, col_len=[int(c.nx) for c in cols], stream=stream.cuda_stream)
+    lat.set_porous_field(cat("phi"), cat("tort"), w0.pore_radius)
+    if chem:
+        lat.set_faradaic_source(cat("faradaic_rate"), 0, 1)
+        lat.set_mechanism(w0.mech)
+    return lat
+
+
+def measure_c4(lbm, torch, steps, warmup, graph_steps, chem=True, autotune=False):
     """Batched ragged 1-D columns (64 D1Q3 button-cell columns, L ~ U{200..2000}) in one
-    context with the graph step loop, against the same 64 columns run one after another,
-    each in its own context with plain launches.  Returns (t_batched, t_sequential, N)."""
+    context with the graph step loop (or, with autotune, the configuration lbm_autotune
+    picks after the first step), against the same 64 columns run one after another,
+    each in its own context with plain launches.  Returns (t_batched, t_sequential, N,
+    n_columns, autotune table or None)."""
     from workloads import synth
     lengths, phis, currents = synth.config4_columns()
     cols = [synth.config4_column(int(L), float(p_), float(i)) for L, p_, i in zip(lengths, phis, currents)]
     stream = torch.cuda.Stream()
-    cat = lambda k: np.concatenate([getattr(c, k) for c in cols], axis=-1)
-    w0 = cols[0]
     N = int(sum(lengths))
-    lat = lbm.Lattice(1, N, 1, 1, w0.molar_mass, w0.D_ref_lat, cat("X0"), cat("T0"), cat("P0"),
-                      T_ref=w0.T_ref, bc_lo=w0.bc_lo, bc_hi=w0.bc_hi, inlet_lo_X=w0.inlet_lo_X,
-                      inlet_T=w0.inlet_T, col_len=[int(L) for L in lengths], stream=stream.cuda_stream)
-    lat.set_porous_field(cat("phi"), cat("tort"), w0.pore_radius)
-    lat.set_faradaic_source(cat("faradaic_rate"), 0, 1)
-    lat.set_mechanism(w0.mech)
-    lat.set_graph(graph_steps)
+    lat = c4_batch(lbm, cols, stream, chem)
+    table = None
+    if autotune:
+        lat.step(1)
+        table = lat.autotune(trial_steps=300)
+        log("autotune: " + "; ".join(f"fused={t[0]} graph={t[1]} S={t[2]} wpb={t[3]}: {t[4] * 1e3:.1f} us"
+                                     for t in table))
+    else:
+        lat.set_graph(graph_steps)
     log(f"batched: {len(cols)} columns, {N} nodes; warmup {warmup}")
     lat.step(warmup)
     stream.synchronize()
@@ -169,7 +190,7 @@ def measure_c4(lbm, torch, steps, warmup, graph_steps):
     log(f"batched {steps} steps: {t_batched:.3f} s; sequential baseline")
     t_seq = 0.0
     for c in cols:
-        pl = lbm.lattice_from_workload(c, stream=stream.cuda_stream)
+        pl = c4_batch(lbm, [c], stream, chem)
         pl.step(warmup)
         stream.synchronize()
         t0 = time.perf_counter()
@@ -177,20 +198,33 @@ def measure_c4(lbm, torch, steps, warmup, graph_steps):
         stream.synchronize()
         t_seq += time.perf_counter() - t0
         pl.close()
-    return t_batched, t_seq, N, len(cols)
+    return t_batched, t_seq, N, len(cols), table
 
 
 def bench_c4(args, lbm, torch):
-    t_batched, t_seq, N, ncol = measure_c4(lbm, torch, args.steps, args.warmup, args.graph_steps)
+    chem = args.workload == "c4"
+    t_batched, t_seq, N, ncol, table = measure_c4(lbm, torch, args.steps, args.warmup, args.graph_steps,
+                                                  chem=chem, autotune=args.autotune)
     mlups = N * args.steps / t_batched / 1e6
+    if table:
+        best = min(table, key=lambda t: t[4])
+        loop = (f"autotuned: fused launch of {best[2]} steps, {best[3]} waves per block" if best[0]
+                else f"autotuned: separate kernels, graph step loop of {best[1]}" if best[1]
+                else "autotuned: separate kernels, plain launches")
+    else:
+        loop = f"graph step loop of {args.graph_steps} steps"
+    what = "M=5 K=10 R=20" if chem else "M=5, no surface chemistry"
     out = {"metric": "MLUPS", "value": mlups, "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": t_batched * 1e3 / args.steps, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-           "config": {"workload": f"c4 {ncol} packed D1Q3 columns, {N} nodes, M=5 K=10 R=20, "
-                                  f"graph step loop of {args.graph_steps} steps",
+           "config": {"workload": f"{args.workload} {ncol} packed D1Q3 columns, {N} nodes, {what}, {loop}",
                       "nodes": N, "parallelism": "single GPU"},
            "batched_vs_sequential": t_seq / t_batched,
            "sequential_ms_per_step_all_columns": t_seq * 1e3 / args.steps}
+    if table:
+        out["autotune_us_per_step"] = [
+            {"fused": t[0], "graph_steps": t[1], "steps_per_launch": t[2], "waves_per_block": t[3],
+             "us_per_step": t[4] * 1e3} for t in table]
     print(json.dumps(out), flush=True)
 
 
@@ -315,6 +349,8 @@ def main():
                     help="mechanism-specialised (default) or generic chemistry kernel")
     ap.add_argument("--graph-steps", type=int, default=32,
                     help="c4: steps per captured graph of the batched run (0 = plain launches)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="c4, c4_nochem: run lbm_autotune after the first step and time what it picks")
     ap.add_argument("--n-secant", type=int, default=6,
                     help="c4_electrode: secant updates of the current control per step")
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64",
@@ -344,7 +380,7 @@ def main():
         torch.cuda.synchronize()
         log(f"copy calibration: 3 copies of {nbytes} bytes")
         del src, dst
-    if args.workload == "c4":
+    if args.workload in ("c4", "c4_nochem"):
         return bench_c4(args, lbm, torch)
     if args.workload == "c4_electrode":
         return bench_c4_electrode(args, lbm, torch)
@@ -421,7 +457,7 @@ def main():
         out["roofline"]["frac_of_copy_probe"] = out["roofline"]["achieved"] / out["copy_probe_GBps"] \
             if out["roofline"]["unit"] == "GB/s" else None
         log(f"c4 batched vs sequential, {args.extra_c4_steps} steps")
-        tb, ts, n4, ncol = measure_c4(lbm, torch, args.extra_c4_steps, 20, args.graph_steps)
+        tb, ts, n4, ncol, _ = measure_c4(lbm, torch, args.extra_c4_steps, 20, args.graph_steps)
         log(f"c5 adjoint vs forward, {args.extra_c5_steps} steps")
         r5 = measure_c5_adjoint(lbm, torch, args.extra_c5_steps)
         out["ratios"] = {
