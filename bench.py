@@ -275,7 +275,7 @@ def bench_c4_electrode(args, lbm, torch):
     print(json.dumps(out), flush=True)
 
 
-def measure_c5_adjoint(lbm, torch, steps):
+def measure_c5_adjoint(lbm, torch, steps, memory_gb=0.0):
     """C5 as stated (D2Q9 1024x256, 3 species, GRF porosity, Knudsen drag, inlet /
     outflow): `steps` forward steps alone vs the adjoint gradient of the outlet flux
     over the same steps (forward with checkpoints, segment recompute, reverse sweep)."""
@@ -295,6 +295,8 @@ def measure_c5_adjoint(lbm, torch, steps):
     d = lat.diagnostics(check=False)
     lat.close()
     lat = lbm.lattice_from_workload(w, stream=stream.cuda_stream)
+    if memory_gb:
+        lat.set_adjoint_memory(int(memory_gb * 1e9))
     g = torch.empty(w.N, dtype=torch.float64, device="cuda")
     stream.synchronize()
     t0 = time.perf_counter()
@@ -309,14 +311,15 @@ def measure_c5_adjoint(lbm, torch, steps):
 
 
 def bench_c5_adjoint(args, lbm, torch):
-    r = measure_c5_adjoint(lbm, torch, args.steps)
+    r = measure_c5_adjoint(lbm, torch, args.steps, args.adjoint_memory_gb)
     out = {"metric": "MLUPS", "value": r["N"] * args.steps / r["forward_s"] / 1e6, "unit": "MLUPS", "n_gpus": 1,
            "steps": args.steps, "warmup": 0, "ms_per_step": r["forward_s"] * 1e3 / args.steps,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
            "config": {"workload": r["workload"], "nodes": r["N"], "parallelism": "single GPU"},
            "adjoint_s": r["adjoint_s"], "forward_s": r["forward_s"],
            "adjoint_over_forward": r["adjoint_over_forward"], "J": r["J"], "grad_rp": r["grad_rp"],
-           "grad_phi_absmax": r["grad_phi_absmax"]}
+           "grad_phi_absmax": r["grad_phi_absmax"],
+           "adjoint_memory_budget_gb": args.adjoint_memory_gb or "default (3/4 of free device memory)"}
     print(json.dumps(out), flush=True)
 
 
@@ -351,6 +354,8 @@ def main():
                     help="c4: steps per captured graph of the batched run (0 = plain launches)")
     ap.add_argument("--autotune", action="store_true",
                     help="c4, c4_nochem: run lbm_autotune after the first step and time what it picks")
+    ap.add_argument("--adjoint-memory-gb", type=float, default=0.0,
+                    help="c5_adjoint: workspace budget of the adjoint (0: the library's default)")
     ap.add_argument("--n-secant", type=int, default=6,
                     help="c4_electrode: secant updates of the current control per step")
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64",

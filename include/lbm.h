@@ -314,11 +314,20 @@ int lbm_autotune(lbm_ctx *ctx, int32_t trial_steps, lbm_tune_entry *table, int32
  * node into grad_phi[N] (device pointer if out_on_device != 0, else host;
  * tortuosity held fixed, the initial populations and the inlet equilibria
  * included) and dJ/dr_p (1/m, 0 with Knudsen diffusion off).  Runs the T steps
- * forward with checkpoints every ceil(sqrt(T)) steps, then the reverse sweep,
- * recomputing each segment; leaves the context at step T.  Allocates a
- * workspace of about (2 sqrt(T) + 4) population fields for the call. */
+ * forward in segments of K steps, checkpointing the start of every segment but the
+ * last, whose states it keeps; the reverse sweep then takes the segments last
+ * first, recomputing each earlier one from its checkpoint, so the forward work is
+ * 2 T - K steps.  K is the largest the workspace budget allows (lbm_set_adjoint_memory;
+ * K = T: every state kept, nothing recomputed).  The workspace, (K + 1) states and
+ * the checkpoints and adjoint fields, is allocated for the call; LBM_ENOMEM when
+ * even K = 1 does not fit.  Leaves the context at step T. */
 int lbm_adjoint_outlet_flux(lbm_ctx *ctx, int64_t n_steps, int32_t species, double *J, double *grad_phi,
                             double *grad_rp, int32_t out_on_device);
+
+/* Device-memory budget in bytes for the workspace of lbm_adjoint_outlet_flux; 0 (the
+ * default) takes three quarters of the free device memory at the call.  Results do
+ * not depend on it, only the recomputation does. */
+int lbm_set_adjoint_memory(lbm_ctx *ctx, uint64_t bytes);
 
 /* Writes the macroscopic fields selected by `mask` at the current time level,
  * SoA FP64 in mask-bit order, into out (device pointer if out_on_device != 0,

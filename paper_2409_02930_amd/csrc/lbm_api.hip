@@ -99,6 +99,7 @@ struct lbm_ctx {
   double *theta_alt = nullptr;          // second coverage buffer: a launch reads one, writes the other
   double *win_sk = nullptr;             // rate constants per wave and lane
   size_t win_sk_n = 0;
+  size_t adj_budget = 0;                // adjoint workspace budget in bytes (0: 3/4 of free memory)
   int K = 0;
   // timing
   int timing = 0;
@@ -1370,20 +1371,45 @@ int lbm_adjoint_outlet_flux(lbm_ctx *c, int64_t n_steps, int32_t species, double
   const size_t N = c->N, L = c->L, Q = c->Q, D = c->dim;
   const size_t P = L * Q * N, R = (size_t)kRec * N, A = D * N;
   const int64_t T = n_steps;
-  int64_t K = 1;
-  while (K * K < T) ++K;                              // sqrt(T) checkpoints, sqrt(T) steps per segment
+  // Segments of K steps, the last one ending at T; every state of a segment is kept
+  // in slots while its adjoint runs.  The forward pass checkpoints the start of every
+  // segment but the last, whose steps it computes straight into the slots, so the
+  // forward work is 2 T - K: K as large as the workspace budget allows (K = T: a
+  // single segment, nothing recomputed).
+  const size_t slot = P + R + A, ckw = P + R, fixed = 3 * P + A + 3 * N;
+  size_t budget = c->adj_budget;
+  if (!budget) {
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) != hipSuccess) fr = 0;
+    budget = fr / 4 * 3;
+  }
+  auto need_of = [&](int64_t k) {
+    const int64_t ns = (T + k - 1) / k;
+    return sizeof(double) * ((size_t)(ns - 1) * ckw + (size_t)(k + 1) * slot + fixed);
+  };
+  int64_t K = 0;                                      // the largest that fits
+  size_t least = (size_t)-1;
+  for (int64_t k = T; k >= 1 && !K; --k) {
+    const size_t nk = need_of(k);
+    if (nk <= budget) K = k;
+    least = nk < least ? nk : least;
+  }
+  if (!K)
+    return fail(c, LBM_ENOMEM, "adjoint workspace of at least %.2f GB exceeds the budget of %.2f GB", least / 1e9,
+                budget / 1e9);
   const int64_t nseg = (T + K - 1) / K;
-  // workspace: checkpoints, segment states, adjoint fields
-  const size_t need = (size_t)nseg * (P + R) + (size_t)(K + 1) * (P + R + A) + 3 * P + A + 3 * N;
+  auto seg_end = [&](int64_t s) { return T - (nseg - 1 - s) * K; };
+  auto seg_start = [&](int64_t s) { return seg_end(s) - K > 0 ? seg_end(s) - K : 0; };
+  const size_t need = need_of(K) / sizeof(double);
   double *ws = nullptr;
   if (hipMalloc((void **)&ws, sizeof(double) * need) != hipSuccess)
     return fail(c, LBM_ENOMEM, "adjoint workspace of %.2f GB", 8.0 * need / 1e9);
-  double *ck = ws;                                    // [nseg][P + R]
-  double *seg = ck + (size_t)nseg * (P + R);          // [K + 1][P + R + A]
-  double *lam[2] = {seg + (size_t)(K + 1) * (P + R + A), nullptr};
+  double *ck = ws;                                    // [nseg - 1][P + R]
+  double *seg = ck + (size_t)(nseg - 1) * ckw;        // [K + 1][P + R + A]
+  double *lam[2] = {seg + (size_t)(K + 1) * slot, nullptr};
   lam[1] = lam[0] + P;
   double *lamp = lam[1] + P, *gbar = lamp + P, *phibar = gbar + A, *kfacbar = phibar + N, *jacc = kfacbar + N;
-  auto slot_pop = [&](int64_t k) { return seg + (size_t)k * (P + R + A); };
+  auto slot_pop = [&](int64_t k) { return seg + (size_t)k * slot; };
   auto slot_rec = [&](int64_t k) { return slot_pop(k) + P; };
   auto slot_rA = [&](int64_t k) { return slot_pop(k) + P + R; };
   int rc = LBM_OK;
@@ -1399,29 +1425,11 @@ int lbm_adjoint_outlet_flux(lbm_ctx *c, int64_t n_steps, int32_t species, double
     if (e != hipSuccess && rc == LBM_OK) rc = fail(c, LBM_EHIP, "%s: %s", what, hipGetErrorString(e));
     return e == hipSuccess;
   };
-  hipck(hipMemsetAsync(lam[0], 0, sizeof(double) * (3 * P + A + 3 * N), c->stream), "clear");
-  // forward pass with checkpoints (state before steps 1, K+1, 2K+1, ...)
-  for (int64_t s = 0; s < nseg && rc == LBM_OK; ++s) {
-    const int q_last = (int)((c->steps_done + 1) & 1);
-    hipck(hipMemcpyAsync(ck + (size_t)s * (P + R), c->pop[c->cur], sizeof(double) * P, hipMemcpyDeviceToDevice,
-                         c->stream), "checkpoint");
-    hipck(hipMemcpyAsync(ck + (size_t)s * (P + R) + P, c->rec[q_last], sizeof(double) * R, hipMemcpyDeviceToDevice,
-                         c->stream), "checkpoint");
-    const int64_t t1 = (s + 1) * K < T ? (s + 1) * K : T;
-    for (int64_t t = s * K; t < t1 && rc == LBM_OK; ++t) rc = enqueue_step(c, -1);
-  }
-  const int cur_f = c->cur, first_f = c->first_step;
-  const long long done_f = c->steps_done;
-  const double wN = 1.0 / ((double)T * c->m[species]);
-  // reverse sweep, segment by segment
-  for (int64_t s = nseg - 1; s >= 0 && rc == LBM_OK; --s) {
-    const int64_t t0 = s * K, t1 = (s + 1) * K < T ? (s + 1) * K : T;
-    hipck(hipMemcpyAsync(slot_pop(0), ck + (size_t)s * (P + R), sizeof(double) * (P + R), hipMemcpyDeviceToDevice,
-                         c->stream), "restore");
+  // steps t0 + 1 .. t1 from the state in slot 0, step t writing slot t - t0
+  auto run_into_slots = [&](int64_t t0, int64_t t1) {
     c->steps_done = t0;
     c->first_step = t0 == 0;
     c->cur = 0;
-    // recompute the segment: step t reads slot t-t0-1 and writes slot t-t0
     for (int64_t t = t0 + 1; t <= t1 && rc == LBM_OK; ++t) {
       const int64_t k = t - t0 - 1;
       const int q = (int)(c->steps_done & 1);
@@ -1433,6 +1441,44 @@ int lbm_adjoint_outlet_flux(lbm_ctx *c, int64_t n_steps, int32_t species, double
       rc = enqueue_step(c, -1);
     }
     restore_ptrs();
+  };
+  hipck(hipMemsetAsync(lam[0], 0, sizeof(double) * (3 * P + A + 3 * N), c->stream), "clear");
+  // forward pass: checkpoints at the start of every segment but the last
+  for (int64_t s = 0; s + 1 < nseg && rc == LBM_OK; ++s) {
+    const int q_last = (int)((c->steps_done + 1) & 1);
+    hipck(hipMemcpyAsync(ck + (size_t)s * ckw, c->pop[c->cur], sizeof(double) * P, hipMemcpyDeviceToDevice,
+                         c->stream), "checkpoint");
+    hipck(hipMemcpyAsync(ck + (size_t)s * ckw + P, c->rec[q_last], sizeof(double) * R, hipMemcpyDeviceToDevice,
+                         c->stream), "checkpoint");
+    for (int64_t t = seg_start(s); t < seg_end(s) && rc == LBM_OK; ++t) rc = enqueue_step(c, -1);
+  }
+  // ... and the last segment straight into the slots; the state at T goes back to
+  // the context's own buffers
+  if (rc == LBM_OK) {
+    const int q_last = (int)((c->steps_done + 1) & 1);
+    hipck(hipMemcpyAsync(slot_pop(0), c->pop[c->cur], sizeof(double) * P, hipMemcpyDeviceToDevice, c->stream),
+          "segment start");
+    hipck(hipMemcpyAsync(slot_rec(0), c->rec[q_last], sizeof(double) * R, hipMemcpyDeviceToDevice, c->stream),
+          "segment start");
+    run_into_slots(seg_start(nseg - 1), T);
+    const int q_T = (int)((T + 1) & 1);
+    hipck(hipMemcpyAsync(c->pop[0], slot_pop(K), sizeof(double) * P, hipMemcpyDeviceToDevice, c->stream), "state");
+    hipck(hipMemcpyAsync(c->rec[q_T], slot_rec(K), sizeof(double) * R, hipMemcpyDeviceToDevice, c->stream), "state");
+    c->cur = 0;
+    c->steps_done = T;
+    c->first_step = 0;
+  }
+  const int cur_f = c->cur, first_f = c->first_step;
+  const long long done_f = c->steps_done;
+  const double wN = 1.0 / ((double)T * c->m[species]);
+  // reverse sweep, segment by segment (the last one is already in the slots)
+  for (int64_t s = nseg - 1; s >= 0 && rc == LBM_OK; --s) {
+    const int64_t t0 = seg_start(s), t1 = seg_end(s);
+    if (s + 1 < nseg) {                               // recompute the segment from its checkpoint
+      hipck(hipMemcpyAsync(slot_pop(0), ck + (size_t)s * ckw, sizeof(double) * ckw, hipMemcpyDeviceToDevice,
+                           c->stream), "restore");
+      run_into_slots(t0, t1);
+    }
     // adjoint of the segment's steps, last first
     for (int64_t t = t1; t > t0 && rc == LBM_OK; --t) {
       const int64_t k = t - t0 - 1;
@@ -1458,7 +1504,7 @@ int lbm_adjoint_outlet_flux(lbm_ctx *c, int64_t n_steps, int32_t species, double
   restore_ptrs();
   if (rc == LBM_OK) {
     KParams ka = base_params(c);
-    ka.pin = ck;                                      // initial populations
+    ka.pin = slot_pop(0);                             // initial populations (slot 0 of the first segment)
     AdjBuffers b;
     memset(&b, 0, sizeof(b));
     b.lam_next = lam[1];                              // Lambda_1
@@ -1491,6 +1537,12 @@ int lbm_adjoint_outlet_flux(lbm_ctx *c, int64_t n_steps, int32_t species, double
   (void)hipStreamSynchronize(c->stream);
   (void)hipFree(ws);
   return rc;
+}
+
+int lbm_set_adjoint_memory(lbm_ctx *c, uint64_t bytes) {
+  if (!c) return LBM_EINVAL;
+  c->adj_budget = (size_t)bytes;
+  return LBM_OK;
 }
 
 int lbm_moment_rows(const lbm_ctx *c, uint32_t mask, int32_t *rows) {

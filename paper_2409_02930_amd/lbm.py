@@ -99,6 +99,7 @@ def _load():
         "lbm_set_persistent": ([vp, C.c_int32, C.c_int32], C.c_int),
         "lbm_autotune": ([vp, C.c_int32, C.POINTER(lbm_tune_entry), C.c_int32, C.POINTER(C.c_int32)], C.c_int),
         "lbm_adjoint_outlet_flux": ([vp, C.c_int64, C.c_int32, _dp, vp, _dp, C.c_int32], C.c_int),
+        "lbm_set_adjoint_memory": ([vp, C.c_uint64], C.c_int),
         "lbm_moments": ([vp, C.c_uint32, vp, C.c_int32], C.c_int),
         "lbm_moment_rows": ([vp, C.c_uint32, _ip], C.c_int),
         "lbm_get_diagnostics": ([vp, C.POINTER(lbm_diag)], C.c_int),
@@ -121,7 +122,7 @@ _lib = _load()
 
 EXPORTED = ["lbm_init", "lbm_init_columns", "lbm_set_porous_field", "lbm_set_mechanism",
             "lbm_set_chem_kernel", "lbm_set_faradaic_source", "lbm_set_electrode", "lbm_get_charge",
-            "lbm_set_current_target", "lbm_get_electrode_potential", "lbm_step", "lbm_set_graph", "lbm_set_persistent", "lbm_autotune", "lbm_adjoint_outlet_flux", "lbm_moments", "lbm_moment_rows",
+            "lbm_set_current_target", "lbm_get_electrode_potential", "lbm_step", "lbm_set_graph", "lbm_set_persistent", "lbm_autotune", "lbm_adjoint_outlet_flux", "lbm_set_adjoint_memory", "lbm_moments", "lbm_moment_rows",
             "lbm_get_diagnostics", "lbm_get_diagnostics_static", "lbm_set_timing", "lbm_get_timing", "lbm_save", "lbm_load",
             "lbm_last_error", "lbm_destroy"]
 
@@ -309,6 +310,10 @@ class Lattice:
         self._check(_lib.lbm_adjoint_outlet_flux(self.ctx, int(n_steps), int(species), C.byref(J),
                                                  g.ctypes.data_as(C.c_void_p), C.byref(grp), 0))
         return J.value, g, grp.value
+
+    def set_adjoint_memory(self, nbytes):
+        """Workspace budget of adjoint_outlet_flux in bytes (0: 3/4 of the free device memory)."""
+        self._check(_lib.lbm_set_adjoint_memory(self.ctx, int(nbytes)))
 
     def set_graph(self, steps_per_graph):
         """Replay whole blocks of `steps_per_graph` (even) steps as a HIP graph; 0 = off."""

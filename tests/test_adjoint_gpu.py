@@ -149,3 +149,36 @@ def test_adjoint_dot_product_with_oracle_tangent(lbm, name):
         ad = (float(np.dot(g, v)) if v is not None else 0.0) + grp * s_
         _log(f"{name}: adjoint {ad:.15e} tangent {tan:.15e} rel {abs(ad - tan) / abs(tan):.2e}")
         assert abs(ad - tan) <= 1e-10 * abs(tan), (ad, tan)
+
+
+def _need_bytes(w, T, K):
+    """Workspace of lbm_adjoint_outlet_flux for K steps per segment (the library's formula)."""
+    N, M = w.N, len(w.molar_mass)
+    D = w.lattice
+    Q = 3 ** D
+    P, R, A = (M + 1) * Q * N, 11 * N, D * N
+    nseg = -(-T // K)
+    return 8 * ((nseg - 1) * (P + R) + (K + 1) * (P + R + A) + 3 * P + A + 3 * N)
+
+
+@pytest.mark.parametrize("name", ["c5_inlet_outflow", "d1q3_inlet_outflow"])
+def test_adjoint_segments_give_the_single_segment_result(lbm, name):
+    """With a workspace budget too small to keep every state, the segments recomputed from
+    their checkpoints give bitwise the single-segment objective and gradients, and the
+    context ends at step T in the state a plain forward run reaches."""
+    w, T = _case(name)
+    J1, g1, r1 = _gpu(lbm, w, T)
+    budget = _need_bytes(w, T, 6) + 1024            # about four segments of six steps
+    assert budget < _need_bytes(w, T, T)
+    lat = lbm.lattice_from_workload(w)
+    lat.set_adjoint_memory(budget)
+    J2, g2, r2 = lat.adjoint_outlet_flux(T, 0)
+    f_adj = lat.fields()
+    lat.close()
+    assert J2 == J1 and r2 == r1 and np.array_equal(g2, g1)
+    ref = lbm.lattice_from_workload(w)
+    ref.step(T)
+    f_fwd = ref.fields()
+    ref.close()
+    for k in ("rho_a", "u", "P", "j_a"):
+        assert np.array_equal(np.asarray(f_adj[k]), np.asarray(f_fwd[k])), k
