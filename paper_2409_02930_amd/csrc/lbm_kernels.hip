@@ -704,6 +704,181 @@ __global__ __launch_bounds__(64 * (M + 1 + (ENERGY ? 1 : 0))) void k_species(con
 }
 
 // ---------------------------------------------------------------------------
+// k_species_lane: k_species for one-dimensional lattices without the energy
+// lattice, one node per lane.  With three directions per lattice a node's whole
+// species step (its six pulls, moments, rates, the M x M solve and the M
+// collisions) fits one lane, so the 64 nodes of a tile need one wave instead of
+// M + 1, no barrier and no LDS; on the batched 1-D columns the tile kernel's
+// waves take several rounds of the chip, this one a single round.  The
+// arithmetic is k_species' in the same order; the values that kernel hands
+// between waves through LDS pass through an empty asm here, so the compiler
+// forms the same fused multiply-adds and the results are the same bitwise.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double lane_opaque(double x) {
+  asm volatile("" : "+v"(x));
+  return x;
+}
+
+template <int M, typename PT>
+__global__ __launch_bounds__(256) void k_species_lane(const KParams p) {
+  constexpr int D = 1, Q = 3;
+  Node nd;
+  if (!get_node(p, nd)) return;
+  const int N = p.N;
+  const int n = nd.n;
+  const double phi = p.phi[n];
+  const double Tfield = p.Tfield[n];
+  const bool inlet_node = is_inlet_node(p, nd);
+  double vb[D];
+  vb[0] = inlet_node ? p.rec_prev[n] : 0.0;
+  const PullGeo<D> geo = pull_geo<D>(p, nd);
+
+  // ---- pull every lattice with the previous step's reaction populations; moments
+  double f[M + 1][Q], m0[M + 1], m1[M + 1];
+#pragma unroll
+  for (int l = 0; l <= M; ++l) pull_populations<D, PT>(p, nd, geo, l, f[l]);
+#pragma unroll
+  for (int l = 0; l <= M; ++l) {
+    if (l < M && p.src_prev)
+      add_source_populations<D>(p, nd, geo, p.rec_prev + (size_t)(kRecSrc + l) * N, species_km<M>(p, l), f[l]);
+    if (inlet_node) inlet_replace<D, M>(p, nd, l, phi, vb, f[l]);
+    double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      s0 += f[l][i];
+      s1 += cdir(i, 0) * f[l][i];
+    }
+    m0[l] = lane_opaque(s0);
+    m1[l] = lane_opaque(s1);
+  }
+
+  // ---- node state (as node_state)
+  const double iphi = 1.0 / phi;
+  const double rho = m0[M] * iphi;
+  const double irho = 1.0 / rho;
+  const double u = m1[M] * irho;
+  const double v = u * iphi;
+  double rho_a[M], rs = 0.0;
+#pragma unroll
+  for (int a = 0; a < M; ++a) {
+    rho_a[a] = m0[a] * iphi;
+    rs += rho_a[a];
+  }
+  const double irs = 1.0 / rs;
+  double Y[M], RaT[M], im = 0.0;
+#pragma unroll
+  for (int a = 0; a < M; ++a) {
+    Y[a] = rho_a[a] * irs;
+    im += Y[a] * p.inv_m[a];
+  }
+  double RT = 0.0, Ps = 0.0;
+#pragma unroll
+  for (int a = 0; a < M; ++a) {
+    RaT[a] = p.theta_ref * p.mmin_over_m[a] * (Tfield * p.inv_T_ref);
+    RT += Y[a] * RaT[a];
+    Ps += rho_a[a] * RaT[a];
+  }
+  const double Tr = Tfield * p.inv_T_ref;
+  const double g = Ps / (Tr * sqrt(Tr) * im);
+
+  // ---- rates and rows of the species-momentum system (eqs tauab, betaa, tauak, transform1)
+  double iab[M][M], beta[M], itk[M], A[M][M];
+#pragma unroll
+  for (int a = 0; a < M; ++a) {
+    const double RaTa = lane_opaque(RaT[a]), Ya = lane_opaque(Y[a]);   // selected per wave in k_species
+    const double rg = RaTa * g;
+    double it = 0.0;
+#pragma unroll
+    for (int c = 0; c < M; ++c) {
+      iab[a][c] = lane_opaque((c != a) ? rg * p.imD[a * LBM_MMAX + c] : 0.0);
+      it += Y[c] * iab[a][c];
+    }
+    beta[a] = it / (2.0 + it);
+    itk[a] = p.knudsen ? sqrt(RaTa) / p.kfac[n] : 0.0;
+#pragma unroll
+    for (int c = 0; c < M; ++c)
+      A[a][c] = lane_opaque((c == a) ? 1.0 + 0.5 * it + 0.5 * itk[a] : -0.5 * Ya * iab[a][c]);
+  }
+  // ---- second-order species momenta (as species_momenta)
+  double inv[M];
+#pragma unroll
+  for (int k = 0; k < M; ++k) {
+    inv[k] = 1.0 / A[k][k];
+#pragma unroll
+    for (int r = k + 1; r < M; ++r) {
+      A[r][k] *= inv[k];
+#pragma unroll
+      for (int c = k + 1; c < M; ++c) A[r][c] -= A[r][k] * A[k][c];
+    }
+  }
+  double x[M];
+#pragma unroll
+  for (int a = 0; a < M; ++a) x[a] = m1[a];
+#pragma unroll
+  for (int k = 0; k < M; ++k)
+#pragma unroll
+    for (int r = k + 1; r < M; ++r) x[r] -= A[r][k] * x[k];
+#pragma unroll
+  for (int k = M - 1; k >= 0; --k) {
+    double sacc = x[k];
+#pragma unroll
+    for (int c = k + 1; c < M; ++c) sacc -= A[k][c] * x[c];
+    x[k] = lane_opaque(sacc * inv[k]);
+  }
+
+  // ---- node records (as the momentum wave of k_species)
+  {
+    double fk = 0.0;
+#pragma unroll
+    for (int c = 0; c < M; ++c) fk -= x[c] * lane_opaque(itk[c]);   // eq netKnudsenForce
+    __builtin_nontemporal_store(rho * u * (1.0 - 3.0 * RT) - rho * u * v * v, p.rA + n);
+    if (p.knudsen) __builtin_nontemporal_store(fk, p.rFk + n);
+    if (p.need_v) __builtin_nontemporal_store(v, p.rec_cur + n);
+    __builtin_nontemporal_store(RT, p.rRT + n);
+    if (p.chem) {
+#pragma unroll
+      for (int a = 0; a < M; ++a) __builtin_nontemporal_store(rho_a[a], p.rrho + (size_t)a * N + n);
+    }
+  }
+
+  // ---- species collision (eqs 27eq, 27qeq, fKnudsen, fStar, finalNumericalEquationsReactive)
+  double te[M][Q], ts[M][Q], dlt[M][Q];
+#pragma unroll
+  for (int a = 0; a < M; ++a) {
+    const double RaTa = lane_opaque(RaT[a]);
+    const double pra = m0[a];
+    const bool pos = pra > 0.0;
+    const double ipra = pos ? 1.0 / pra : 0.0;
+    const double xs = x[a] * ipra;
+    const double Pe = v * v + RaTa, Pst = xs * xs + RaTa;
+    te[a][0] = 0.5 * (-v + Pe); te[a][1] = 1.0 - Pe; te[a][2] = 0.5 * (v + Pe);
+    ts[a][0] = 0.5 * (-xs + Pst); ts[a][1] = 1.0 - Pst; ts[a][2] = 0.5 * (xs + Pst);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) dlt[a][i] = lane_opaque(pra * (te[a][i] - ts[a][i]));
+  }
+#pragma unroll
+  for (int a = 0; a < M; ++a) {
+    const double RaTa = lane_opaque(RaT[a]), Ya = lane_opaque(Y[a]);
+    const double pra = m0[a];
+    const bool pos = pra > 0.0;
+    const double tk[Q] = {0.5 * RaTa, 1.0 - RaTa, 0.5 * RaTa};
+    const size_t o = (size_t)(a * Q) * N + n;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      double F = 0.0;
+#pragma unroll
+      for (int c = 0; c < M; ++c) F += iab[a][c] * dlt[c][i];
+      const double feq = pra * te[a][i];
+      const double fst = pos ? pra * ts[a][i] : 0.0;
+      const double fkn = pra * tk[i];
+      const double Fi = Ya * F + itk[a] * (fst - fkn);
+      const double f0 = f[a][i];
+      store_pop<PT>(p.pout, o + (size_t)i * N, f0 + 2.0 * beta[a] * (feq - f0) + (beta[a] - 1.0) * Fi);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // k_mixture: momentum lattice with the extended equilibrium, energy lattice
 // ---------------------------------------------------------------------------
 template <int D, int M, bool ENERGY, typename PT>
@@ -1266,23 +1441,28 @@ __global__ __launch_bounds__(256) void k_surface_energy(const KParams p) {
 }
 
 // Totals of the stored state.  Species populations include the reaction
-// population the last step added after its collision (p.src_prev).
-template <int D, typename PT>
-__global__ __launch_bounds__(256) void k_diag(int L, int Mmom, const KParams p, const PT *pop,
-                                              double *partials) {
-  __shared__ double sh[4];
-  constexpr int Q = LQ<D>::Q;
+// population the last step added after its collision (p.src_prev).  Every thread
+// forms its node's W = L + D + 2 values first (lattice masses, momentum-lattice
+// momentum, minimum population, non-finite count); the block then reduces all of
+// them at once, each by the same tree (wave butterfly, then the four waves in a
+// fixed order), with one barrier.
+template <int D, int L, typename PT>
+__global__ __launch_bounds__(256) void k_diag(int Mmom, const KParams p, const PT *pop, double *partials) {
+  constexpr int Q = LQ<D>::Q, W = L + D + 2;
+  __shared__ double sh[W][4];
   const int N = p.N;
   const int n = blockIdx.x * blockDim.x + threadIdx.x;
   const int t = threadIdx.x;
-  const int W = L + D + 2;
+  double val[W];
   double mn = INFINITY, bad = 0.0;
+#pragma unroll
   for (int l = 0; l < L; ++l) {
     double s = 0.0;
     if (n < N) {
       const bool src = l < p.M && p.src_prev;
-      const double km = src ? p.theta_ref * p.mmin_over_m[l] : 0.0;
-      const double *sa = p.rec_prev + (size_t)(kRecSrc + l) * N;
+      const double km = src ? p.theta_ref * p.mmin_over_m[l < LBM_MMAX ? l : 0] : 0.0;
+      const double *sa = p.rec_prev + (size_t)(kRecSrc + (l < LBM_MMAX ? l : 0)) * N;
+#pragma unroll
       for (int i = 0; i < Q; ++i) {
         double v = (double)pop[(size_t)(l * Q + i) * N + n];
         if (src) v += source_population<D>(load_src<D>(p.rec_prev, sa, p.T_prev, (size_t)N, n), km, p.inv_T_ref, i);
@@ -1291,24 +1471,34 @@ __global__ __launch_bounds__(256) void k_diag(int L, int Mmom, const KParams p, 
         mn = fmin(mn, v);
       }
     }
-    const double r = block_sum(s, sh);
-    if (t == 0) partials[(size_t)blockIdx.x * W + l] = r;
+    val[l] = s;
   }
+#pragma unroll
   for (int d = 0; d < D; ++d) {
     double s = 0.0;
     if (n < N) {
+#pragma unroll
       for (int i = 0; i < Q; ++i) {
         const int c = ((d == 0 ? i : (d == 1 ? i / 3 : i / 9)) % 3) - 1;
         s += c * (double)pop[(size_t)(Mmom * Q + i) * N + n];
       }
     }
-    const double r = block_sum(s, sh);
-    if (t == 0) partials[(size_t)blockIdx.x * W + L + d] = r;
+    val[L + d] = s;
   }
-  const double bm = block_min(mn, sh);
-  if (t == 0) partials[(size_t)blockIdx.x * W + L + D] = bm;
-  const double nb = block_sum(bad, sh);
-  if (t == 0) partials[(size_t)blockIdx.x * W + L + D + 1] = nb;
+  val[L + D] = mn;
+  val[L + D + 1] = bad;
+#pragma unroll
+  for (int k = 0; k < W; ++k) val[k] = (k == L + D) ? wave_min(val[k]) : wave_sum(val[k]);
+  if ((t & 63) == 0) {
+#pragma unroll
+    for (int k = 0; k < W; ++k) sh[k][t >> 6] = val[k];
+  }
+  __syncthreads();
+  if (t < W) {
+    const double r = (t == L + D) ? fmin(fmin(sh[t][0], sh[t][1]), fmin(sh[t][2], sh[t][3]))
+                                  : (sh[t][0] + sh[t][1]) + (sh[t][2] + sh[t][3]);
+    partials[(size_t)blockIdx.x * W + t] = r;
+  }
 }
 
 // Totals of the per-block partials [nblocks][W]: thread w adds column w over the
@@ -1333,6 +1523,12 @@ unsigned padded_blocks(int N, int bs) {
 
 template <int D, int M, typename PT>
 hipError_t species_dispatch_p(const KParams &p, hipStream_t s) {
+  if constexpr (D == 1) {
+    if (!p.energy) {                                  // one node per lane
+      hipLaunchKernelGGL((k_species_lane<M, PT>), dim3(padded_blocks(p.N, 256)), dim3(256), 0, s, p);
+      return hipGetLastError();
+    }
+  }
   const unsigned nb = padded_blocks(p.N, 64);
   if (p.energy)
     hipLaunchKernelGGL((k_species<D, M, true, PT>), dim3(nb), dim3(64 * (M + 2)), 0, s, p);
@@ -1600,14 +1796,27 @@ hipError_t launch_chem(const ChemParams &cp, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <int D, typename PT>
+void diag_launch_l(int L, int Mmom, const KParams &p, const PT *q, double *partials, int nblocks, hipStream_t s) {
+  switch (L) {       // lattices: M species + momentum (+ energy), M = 1..LBM_MMAX
+    case 2: hipLaunchKernelGGL((k_diag<D, 2, PT>), dim3(nblocks), dim3(256), 0, s, Mmom, p, q, partials); break;
+    case 3: hipLaunchKernelGGL((k_diag<D, 3, PT>), dim3(nblocks), dim3(256), 0, s, Mmom, p, q, partials); break;
+    case 4: hipLaunchKernelGGL((k_diag<D, 4, PT>), dim3(nblocks), dim3(256), 0, s, Mmom, p, q, partials); break;
+    case 5: hipLaunchKernelGGL((k_diag<D, 5, PT>), dim3(nblocks), dim3(256), 0, s, Mmom, p, q, partials); break;
+    case 6: hipLaunchKernelGGL((k_diag<D, 6, PT>), dim3(nblocks), dim3(256), 0, s, Mmom, p, q, partials); break;
+    default: hipLaunchKernelGGL((k_diag<D, 7, PT>), dim3(nblocks), dim3(256), 0, s, Mmom, p, q, partials); break;
+  }
+}
+
 template <typename PT>
 hipError_t diag_dispatch(int dim, int L, int Mmom, const KParams &p, const void *pop, double *partials,
                          int nblocks, hipStream_t s) {
   const PT *q = static_cast<const PT *>(pop);
+  if (L < 2 || L > LBM_MMAX + 2) return hipErrorInvalidValue;
   switch (dim) {
-    case 1: hipLaunchKernelGGL((k_diag<1, PT>), dim3(nblocks), dim3(256), 0, s, L, Mmom, p, q, partials); break;
-    case 2: hipLaunchKernelGGL((k_diag<2, PT>), dim3(nblocks), dim3(256), 0, s, L, Mmom, p, q, partials); break;
-    default: hipLaunchKernelGGL((k_diag<3, PT>), dim3(nblocks), dim3(256), 0, s, L, Mmom, p, q, partials); break;
+    case 1: diag_launch_l<1, PT>(L, Mmom, p, q, partials, nblocks, s); break;
+    case 2: diag_launch_l<2, PT>(L, Mmom, p, q, partials, nblocks, s); break;
+    default: diag_launch_l<3, PT>(L, Mmom, p, q, partials, nblocks, s); break;
   }
   return hipGetLastError();
 }
