@@ -323,6 +323,25 @@ def bench_c5_adjoint(args, lbm, torch):
     print(json.dumps(out), flush=True)
 
 
+def measure_c2(lbm, torch, steps=400, warmup=20):
+    """C2 as stated (D2Q9 1024x64, pure-species inlets, energy on, Kn index 3) with FP64
+    and with FP32 population storage (arithmetic FP64 either way): MLUPS of each."""
+    from workloads import synth
+    w = synth.config2(kn_index=3)
+    stream = torch.cuda.Stream()
+    res = {}
+    for name, prec in (("fp64", lbm.FP64), ("fp32", lbm.FP32)):
+        lat = lbm.lattice_from_workload(w, stream=stream.cuda_stream, precision=prec)
+        lat.step(warmup)
+        stream.synchronize()
+        t0 = time.perf_counter()
+        lat.step(steps)
+        stream.synchronize()
+        res[name] = w.N * steps / (time.perf_counter() - t0) / 1e6
+        lat.close()
+    return res
+
+
 def copy_probe_gbps(torch, nbytes=2 << 30, iters=5):
     """Device-to-device copy of nbytes (read + write counted), timed with events on the
     current stream: the bandwidth a plain streaming kernel reaches on this part."""
@@ -456,7 +475,7 @@ def main():
     if args.workload == "c3" and not args.no_extras:
         # the other targets of the method's metric, measured after the headline step:
         # a plain copy's bandwidth beside the roofline fraction, batched vs sequential
-        # columns (C4) and adjoint vs forward cost (C5 as stated)
+        # columns (C4), adjoint vs forward cost (C5 as stated), C2 with FP64 and FP32 storage
         log("copy probe")
         out["copy_probe_GBps"] = copy_probe_gbps(torch)
         out["roofline"]["frac_of_copy_probe"] = out["roofline"]["achieved"] / out["copy_probe_GBps"] \
@@ -465,6 +484,11 @@ def main():
         tb, ts, n4, ncol, _ = measure_c4(lbm, torch, args.extra_c4_steps, 20, args.graph_steps)
         log(f"c5 adjoint vs forward, {args.extra_c5_steps} steps")
         r5 = measure_c5_adjoint(lbm, torch, args.extra_c5_steps)
+        log("c2 with FP64 and FP32 population storage")
+        c2 = measure_c2(lbm, torch)
+        out["c2_d2q9_1024x64_mlups"] = {"fp64": c2["fp64"], "fp32": c2["fp32"],
+                                        "config": "c2 D2Q9 1024x64, pure-species inlets, energy on, Kn index 3, "
+                                                  "400 steps; fp32 = population storage, FP64 arithmetic"}
         out["ratios"] = {
             "batched_vs_sequential": ts / tb,
             "batched_config": f"c4 {ncol} packed D1Q3 columns ({n4} nodes), {args.extra_c4_steps} steps, "

@@ -23,6 +23,8 @@ Cases (sizes chosen so the oracle finishes in minutes on the host's cores):
   c3_full_sampled  C3 at 256 x 128 x 128, 10 steps, 4 sampled nodes (periodic patches
                    of radius 21 cut around them reproduce the full run there exactly)
   c4_cols          three of the 64 C4 columns (first, longest, last), 500 steps
+  c3_energy_16     C3 physics with the energy lattice and adsorbed-phase thermo (synth.config3_energy)
+                   on 16 x 16 x 16, 100 steps
 """
 import math
 import os
@@ -171,6 +173,13 @@ def case_c4():
     np.savez_compressed(os.path.join(OUT, "c4_cols.npz"), **arrs)
 
 
+def case_c3_energy():
+    w = synth.config3_energy(nx=16, ny=16, nz=16)
+    o = Oracle(w)
+    o.step(100)
+    _store("c3_energy_16", o.moments(), sample_nodes(w.N), {"steps": 100})
+
+
 CASES = {f"c2_kn{k}": (lambda k=k: case_c2(k)) for k in range(8)}
 CASES.update({
     "c5_1024x16": case_c5,
@@ -178,6 +187,7 @@ CASES.update({
     "c3_16x16x16": lambda: case_c3(16, 16, 16, 300),
     "c3_full_sampled": case_c3_full,
     "c4_cols": case_c4,
+    "c3_energy_16": case_c3_energy,
 })
 
 

@@ -8,7 +8,8 @@ oracle's 128 x 1 run.  C5 physics (GRF porosity, Knudsen drag,
 inlet / outflow) on 1024 x 16 for 2000 steps, with the outlet-flux objective over
 the run.  C3 physics on 64 x 32 x 32 (20 steps) and 16 x 16 x 16 (300 steps), and C3
 at its full size 256 x 128 x 128 after 10 steps at 4 sampled nodes.  Three of the 64
-batched C4 columns after 500 steps.  Every field within 1e-11 normwise (parity_util).
+batched C4 columns after 500 steps.  C3 physics with the energy lattice on 16 x 16 x 16 for 100
+steps.  Every field within 1e-11 normwise (parity_util).
 """
 import os
 import sys
@@ -145,3 +146,21 @@ def test_c4_batched_columns_long_run(lbm):
         sl = slice(int(offs[c_idx]), int(offs[c_idx + 1]))
         compare({k: np.asarray(f[k])[..., sl] for k in keys}, {k: g[f"col{j}__{k}"] for k in keys}, keys,
                 label=f"c4 column {c_idx} (L={lengths[c_idx]}) after {steps} steps")
+
+
+def test_c3_energy_full_run(lbm):
+    """C3 physics with the energy lattice and adsorbed-phase thermo (the surface chemistry moving
+    internal energy between the phases) on 16 x 16 x 16 for 100 steps."""
+    g = _gold("c3_energy_16")
+    steps = int(g["meta__steps"])
+    w = synth.config3_energy(nx=16, ny=16, nz=16)
+    lat = lbm.lattice_from_workload(w)
+    lat.step(steps)
+    f = lat.fields()
+    d = lat.diagnostics(check=False)
+    lat.close()
+    assert d["n_nonfinite"] == 0
+    nodes = g["nodes"]
+    keys = ("rho_a", "u", "T", "P", "X", "j_a", "rho", "theta")
+    compare({k: np.asarray(f[k])[..., nodes] for k in keys}, {k: g[k] for k in keys}, keys,
+            label=f"c3 energy 16x16x16 after {steps} steps")
