@@ -108,23 +108,24 @@ def make_workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
-def cpu_baseline(name, budget_s=20.0):
-    """The oracle as it stands, on a bounded sub-grid of the same workload."""
-    from dataclasses import replace
-    from oracle.lbm_oracle import Oracle
+def _cpu_sample(name):
+    """The workload's bounded CPU sample: (workload, description)."""
     from workloads import synth
     if name == "c3":
-        w = synth.config3(nx=24, ny=16, nz=16)
-        sample = "c3 physics on a 24x16x16 sub-grid (same species, mechanism, porosity recipe)"
-    elif name == "c5":
-        w = synth.config5(nx=128, ny=64)
-        sample = "c5 physics on a 128x64 sub-grid"
-    elif name == "c2":
-        w = synth.config2(kn_index=3, nx=256, ny=16)
-        sample = "c2 physics on a 256x16 sub-grid"
-    else:
-        w = synth.config1()
-        sample = "c1 full grid"
+        return (synth.config3(nx=24, ny=16, nz=16),
+                "c3 physics on a 24x16x16 sub-grid (same species, mechanism, porosity recipe)")
+    if name == "c5":
+        return synth.config5(nx=128, ny=64), "c5 physics on a 128x64 sub-grid"
+    if name == "c2":
+        return synth.config2(kn_index=3, nx=256, ny=16), "c2 physics on a 256x16 sub-grid"
+    return synth.config1(), "c1 full grid"
+
+
+def _oracle_run(args):
+    """One process: the oracle on the sample for about budget_s seconds; (nodes, steps, seconds)."""
+    name, budget_s = args
+    from oracle.lbm_oracle import Oracle
+    w, _ = _cpu_sample(name)
     o = Oracle(w)
     o.step(1)
     t0 = time.perf_counter()
@@ -135,9 +136,39 @@ def cpu_baseline(name, budget_s=20.0):
         el = time.perf_counter() - t0
         if el > budget_s or steps >= 200:
             break
-    mlups = w.N * steps / el / 1e6
-    return {"value": mlups, "unit": "MLUPS", "cores": 1, "kind": "oracle",
-            "sample": f"{sample}: {steps} steps of {w.N} nodes in {el:.1f} s, numpy single thread"}
+    return w.N, steps, el
+
+
+def cpu_baseline(name, budget_s=20.0, max_procs=16):
+    """The oracle as it stands on the host's cores: one process per core (at most max_procs,
+    the machine's CPU share), each stepping its own copy of the bounded sub-grid sample for
+    about budget_s seconds; the value is the sum of their node updates per second.  The
+    processes are started fresh (spawn), so none inherits this process's GPU state."""
+    import multiprocessing as mp
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    procs = max(1, min(cores, max_procs))
+    _, sample = _cpu_sample(name)
+    ctx = mp.get_context("spawn")
+    one = {k: "1" for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")}
+    saved = {k: os.environ.get(k) for k in one}
+    os.environ.update(one)                            # the children: one thread each
+    try:
+        with ctx.Pool(procs) as pool:
+            res = pool.map(_oracle_run, [(name, budget_s)] * procs)
+    finally:
+        for k, v in saved.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+    mlups = sum(n * st / el for n, st, el in res) / 1e6
+    steps = sum(st for _, st, _ in res)
+    return {"value": mlups, "unit": "MLUPS", "cores": procs, "kind": "oracle",
+            "sample": f"{sample}: {procs} processes (one per core, numpy single thread each), "
+                      f"{steps} steps of {res[0][0]} nodes in about {budget_s:.0f} s each"}
 
 
 def c4_batch(lbm, cols, stream, chem=True):
