@@ -206,8 +206,8 @@ def measure_c4(lbm, torch, steps, warmup, graph_steps, chem=True, autotune=False
     if autotune:
         lat.step(1)
         table = lat.autotune(trial_steps=300)
-        log("autotune: " + "; ".join(f"fused={t[0]} graph={t[1]} S={t[2]} wpb={t[3]}: {t[4] * 1e3:.1f} us"
-                                     for t in table))
+        log("autotune: " + "; ".join(f"fused={t[0]} chem={t[5]} graph={t[1]} S={t[2]} wpb={t[3]}: "
+                                     f"{t[4] * 1e3:.1f} us" for t in table))
     else:
         lat.set_graph(graph_steps)
     log(f"batched: {len(cols)} columns, {N} nodes; warmup {warmup}")
@@ -239,12 +239,13 @@ def bench_c4(args, lbm, torch):
     mlups = N * args.steps / t_batched / 1e6
     if table:
         best = min(table, key=lambda t: t[4])
+        chem = ", chemistry at two waves per SIMD" if best[5] == lbm.CHEM_SPECIALIZED_2W else ""
         loop = (f"autotuned: fused launch of {best[2]} steps, {best[3]} waves per block" if best[0]
-                else f"autotuned: separate kernels, graph step loop of {best[1]}" if best[1]
-                else "autotuned: separate kernels, plain launches")
+                else f"autotuned: separate kernels{chem}, graph step loop of {best[1]}" if best[1]
+                else f"autotuned: separate kernels{chem}, plain launches")
     else:
         loop = f"graph step loop of {args.graph_steps} steps"
-    what = "M=5 K=10 R=20" if chem else "M=5, no surface chemistry"
+    what = "M=5 K=10 R=20" if args.workload == "c4" else "M=5, no surface chemistry"
     out = {"metric": "MLUPS", "value": mlups, "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": t_batched * 1e3 / args.steps, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
@@ -254,8 +255,8 @@ def bench_c4(args, lbm, torch):
            "sequential_ms_per_step_all_columns": t_seq * 1e3 / args.steps}
     if table:
         out["autotune_us_per_step"] = [
-            {"fused": t[0], "graph_steps": t[1], "steps_per_launch": t[2], "waves_per_block": t[3],
-             "us_per_step": t[4] * 1e3} for t in table]
+            {"fused": t[0], "chem_kernel": t[5], "graph_steps": t[1], "steps_per_launch": t[2],
+             "waves_per_block": t[3], "us_per_step": t[4] * 1e3} for t in table]
     print(json.dumps(out), flush=True)
 
 
@@ -398,8 +399,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--chem-kernel", choices=["specialized", "generic"], default="specialized",
-                    help="mechanism-specialised (default) or generic chemistry kernel")
+    ap.add_argument("--chem-kernel", choices=["specialized", "generic", "specialized_2w"], default="specialized",
+                    help="mechanism-specialised (default), generic, or specialised at two waves per SIMD")
     ap.add_argument("--graph-steps", type=int, default=32,
                     help="c4: steps per captured graph of the batched run (0 = plain launches)")
     ap.add_argument("--autotune", action="store_true",
@@ -447,7 +448,8 @@ def main():
     lat = lbm.lattice_from_workload(w, stream=stream.cuda_stream,
                                     precision=lbm.FP32 if args.precision == "fp32" else lbm.FP64)
     pop_bytes = 4 if args.precision == "fp32" else 8
-    lat.set_chem_kernel(lbm.CHEM_SPECIALIZED if args.chem_kernel == "specialized" else lbm.CHEM_GENERIC)
+    lat.set_chem_kernel({"specialized": lbm.CHEM_SPECIALIZED, "generic": lbm.CHEM_GENERIC,
+                         "specialized_2w": lbm.CHEM_SPECIALIZED_2W}[args.chem_kernel])
     log(f"lattice ready N={w.N}; warmup {args.warmup}")
     lat.step(args.warmup)
     torch.cuda.synchronize()

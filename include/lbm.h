@@ -192,8 +192,12 @@ int lbm_set_mechanism(lbm_ctx *ctx, const lbm_mechanism *mech);
  * partial pivoting would exchange rows.  LBM_CHEM_GENERIC runs the precompiled
  * kernel that reads the mechanism from device tables (dense LU with partial
  * pivoting) on every step.  Both compute the backward-Euler update of
- * Section 4; they agree to rounding. */
-enum { LBM_CHEM_SPECIALIZED = 0, LBM_CHEM_GENERIC = 1 };
+ * Section 4; they agree to rounding.  LBM_CHEM_SPECIALIZED_2W is the generated
+ * kernel compiled for two waves per SIMD: its registers are capped at 256 and
+ * what does not fit spills to scratch memory, which pays where the nodes fill
+ * barely more than one wave per SIMD (the batched 1-D columns); same results
+ * bitwise as LBM_CHEM_SPECIALIZED. */
+enum { LBM_CHEM_SPECIALIZED = 0, LBM_CHEM_GENERIC = 1, LBM_CHEM_SPECIALIZED_2W = 2 };
 int lbm_set_chem_kernel(lbm_ctx *ctx, int32_t kind);
 
 /* Prescribed volumetric Faradaic source rate [N] (mol m^-3 s^-1) that consumes
@@ -284,6 +288,7 @@ int lbm_set_persistent(lbm_ctx *ctx, int32_t steps_per_launch, int32_t waves_per
 /* One measured configuration of the step loop (lbm_autotune). */
 typedef struct {
   int32_t fused;             /* 0: separate kernels, 1: fused persistent launch */
+  int32_t chem_kernel;       /* chemistry kernel (LBM_CHEM_*) of the separate kernels */
   int32_t graph_steps;       /* graph step loop length (0: plain launches) */
   int32_t steps_per_launch;  /* fused: steps per launch */
   int32_t waves_per_block;   /* fused: waves per workgroup */
@@ -293,8 +298,10 @@ typedef struct {
 /* Autotuner of the step loop: from the current state (past the first step;
  * LBM_ESTATE before), times about trial_steps steps (rounded up to whole launches)
  * of each configuration -- the separate kernels with plain launches and with the
- * graph step loop of 32 steps and, where lbm_set_persistent applies, the fused
- * launch at 1, 3 and 5 steps per launch with 1 or 2 waves per block -- restoring
+ * graph step loop of 32 steps, with a mechanism also the graph loop with the
+ * generated chemistry at two waves per SIMD (LBM_CHEM_SPECIALIZED_2W), and, where
+ * lbm_set_persistent applies, the fused launch at 1, 3 and 5 steps per launch with
+ * 1 or 2 waves per block -- restoring
  * the state before each, installs the fastest and restores the state again, so the
  * run continues from where it was.  Writes up to max_entries entries to table
  * (host memory, caller-owned) and their number to n_entries.  Needs a non-null

@@ -489,6 +489,7 @@ void fill_chem_spec(const lbm_ctx *c, ChemSpec &sp) {
 int specialize_chemistry(lbm_ctx *c) {
   ChemSpec sp;
   fill_chem_spec(c, sp);
+  sp.occupancy = c->chem_kernel == LBM_CHEM_SPECIALIZED_2W ? 2 : 1;
   if (c->have_perm) {
     memcpy(sp.perm, c->chem_perm, sizeof(sp.perm));
   } else {
@@ -654,7 +655,7 @@ const char *window_unsupported(const lbm_ctx *c) {
   if (c->bc_lo == BC_PERIODIC || c->bc_hi == BC_PERIODIC) return "the fused kernel needs closed x ends";
   if (c->electrode || c->n_secant) return "the fused kernel has no electrode coupling";
   if (c->has_faradaic && !c->has_mech) return "a Faradaic source without a mechanism runs the separate kernels";
-  if (c->has_mech && c->chem_kernel != LBM_CHEM_SPECIALIZED) return "the fused kernel takes the specialised chemistry";
+  if (c->has_mech && c->chem_kernel == LBM_CHEM_GENERIC) return "the fused kernel takes the specialised chemistry";
   return nullptr;
 }
 
@@ -836,7 +837,7 @@ int capture_steps(lbm_ctx *c) {
 // chemistry kernel of the remaining run in place.
 bool graph_ready(const lbm_ctx *c) {
   if (!c->graph_steps || c->first_step || c->steps_done < 1) return false;
-  if (c->has_mech && c->chem_kernel == LBM_CHEM_SPECIALIZED && !c->chem_fn) return false;
+  if (c->has_mech && c->chem_kernel != LBM_CHEM_GENERIC && !c->chem_fn) return false;
   return true;
 }
 
@@ -1187,10 +1188,14 @@ int lbm_get_charge(lbm_ctx *c, double *iv, double *ia, double *phi_el) {
 
 int lbm_set_chem_kernel(lbm_ctx *c, int32_t kind) {
   if (!c) return LBM_EINVAL;
-  if (kind != LBM_CHEM_SPECIALIZED && kind != LBM_CHEM_GENERIC) return fail(c, LBM_EINVAL, "unknown chemistry kernel %d", kind);
+  if (kind != LBM_CHEM_SPECIALIZED && kind != LBM_CHEM_GENERIC && kind != LBM_CHEM_SPECIALIZED_2W)
+    return fail(c, LBM_EINVAL, "unknown chemistry kernel %d", kind);
+  // between the two generated forms the elimination order stays: only the register budget differs
+  const bool keep_order = kind != LBM_CHEM_GENERIC && c->chem_kernel != LBM_CHEM_GENERIC;
   c->chem_kernel = kind;
   c->chem_fn = nullptr;
-  c->have_perm = 0;
+  if (!keep_order) c->have_perm = 0;
+  drop_graph(c);
   return LBM_OK;
 }
 
@@ -1252,12 +1257,15 @@ int lbm_autotune(lbm_ctx *c, int32_t trial_steps, lbm_tune_entry *table, int32_t
   // candidates: the separate kernels (plain launches, graph of 32 steps) and,
   // where it applies, the fused kernel at 1, 3, 5 steps per launch and 1 or 2
   // waves per block
-  std::vector<lbm_tune_entry> cand;
-  cand.push_back({0, 0, 0, 0, 0.0});   // {fused, graph_steps, steps_per_launch, waves_per_block, ms}
-  cand.push_back({0, 32, 0, 0, 0.0});
+  std::vector<lbm_tune_entry> cand;   // {fused, chem_kernel, graph_steps, steps_per_launch, waves_per_block, ms}
+  const int chem0 = c->chem_kernel;
+  const int gen = chem0 == LBM_CHEM_GENERIC ? LBM_CHEM_GENERIC : LBM_CHEM_SPECIALIZED;
+  cand.push_back({0, gen, 0, 0, 0, 0.0});
+  cand.push_back({0, gen, 32, 0, 0, 0.0});
+  if (c->has_mech && gen == LBM_CHEM_SPECIALIZED) cand.push_back({0, LBM_CHEM_SPECIALIZED_2W, 32, 0, 0, 0.0});
   if (!window_unsupported(c))
     for (int st : {1, 3, 5})
-      for (int wpb : {1, 2}) cand.push_back({1, 0, st, wpb, 0.0});
+      for (int wpb : {1, 2}) cand.push_back({1, gen, 0, st, wpb, 0.0});
   size_t snap_n = 0;
   int rc = lbm_save(c, nullptr, &snap_n);
   if (rc) return rc;
@@ -1277,6 +1285,10 @@ int lbm_autotune(lbm_ctx *c, int32_t trial_steps, lbm_tune_entry *table, int32_t
     c->graph_steps = t.graph_steps;
     c->win_steps = t.steps_per_launch;
     c->win_wpb = t.waves_per_block ? t.waves_per_block : 1;
+    if (c->has_mech && t.chem_kernel != c->chem_kernel) {   // the other generated form, same order
+      c->chem_kernel = t.chem_kernel;
+      c->chem_fn = nullptr;
+    }
     drop_graph(c);
     // whole launches or graph replays only: a multiple of 2 x steps per launch
     const int unit = t.graph_steps ? graph_len(c) : (t.steps_per_launch ? 2 * t.steps_per_launch : 2);
@@ -1301,12 +1313,20 @@ int lbm_autotune(lbm_ctx *c, int32_t trial_steps, lbm_tune_entry *table, int32_t
     c->graph_steps = graph0;
     c->win_steps = win0;
     c->win_wpb = wpb0;
+    if (c->chem_kernel != chem0) {
+      c->chem_kernel = chem0;
+      c->chem_fn = nullptr;
+    }
     drop_graph(c);
     return rc ? rc : (rcl ? rcl : fail(c, LBM_EHIP, "no candidate measured"));
   }
   c->graph_steps = cand[best].graph_steps;
   c->win_steps = cand[best].steps_per_launch;
   c->win_wpb = cand[best].waves_per_block ? cand[best].waves_per_block : 1;
+  if (c->chem_kernel != cand[best].chem_kernel) {
+    c->chem_kernel = cand[best].chem_kernel;
+    c->chem_fn = nullptr;
+  }
   drop_graph(c);
   *n_entries = (int32_t)cand.size();
   for (int k = 0; k < (int)cand.size() && k < max_entries; ++k) table[k] = cand[k];
@@ -1323,7 +1343,7 @@ int lbm_step(lbm_ctx *c, int64_t n_steps) {
   const int64_t first_timed = n_steps > kTimingRing ? n_steps - kTimingRing : 0;
   int slot = 0;
   for (int64_t s = 0; s < n_steps;) {
-    if (c->has_mech && c->chem_kernel == LBM_CHEM_SPECIALIZED && !c->chem_fn && c->steps_done >= 1) {
+    if (c->has_mech && c->chem_kernel != LBM_CHEM_GENERIC && !c->chem_fn && c->steps_done >= 1) {
       const int rc = specialize_chemistry(c);   // after the first step (generic kernel)
       if (rc) return rc;
     }

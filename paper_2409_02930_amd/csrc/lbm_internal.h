@@ -177,6 +177,7 @@ struct ChemSpec {
   int charge_z[LBM_RMAX];                        // electrons released by the forward reaction
   double beta_ct[LBM_RMAX];                      // symmetry factor of a charge transfer
   int has_ct;
+  int occupancy;                                 // waves per SIMD the generated kernel is compiled for (1, 2)
 };
 
 // launchers (lbm_kernels.hip)

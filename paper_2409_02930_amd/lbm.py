@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "_lib", "liblbm.so")
 
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EHIP, LBM_ESTATE, LBM_EUNSTABLE = 0, -1, -2, -3, -4, -5
 BC_PERIODIC, BC_BOUNCEBACK, BC_INLET, BC_OUTFLOW = 0, 1, 2, 3
-CHEM_SPECIALIZED, CHEM_GENERIC = 0, 1
+CHEM_SPECIALIZED, CHEM_GENERIC, CHEM_SPECIALIZED_2W = 0, 1, 2
 FP64, FP32 = 0, 1             # population storage; arithmetic is FP64 either way
 
 MOM_RHO_SPECIES = 1 << 0
@@ -68,8 +68,8 @@ class lbm_diag(C.Structure):
 
 
 class lbm_tune_entry(C.Structure):
-    _fields_ = [("fused", C.c_int32), ("graph_steps", C.c_int32), ("steps_per_launch", C.c_int32),
-                ("waves_per_block", C.c_int32), ("ms_per_step", C.c_double)]
+    _fields_ = [("fused", C.c_int32), ("chem_kernel", C.c_int32), ("graph_steps", C.c_int32),
+                ("steps_per_launch", C.c_int32), ("waves_per_block", C.c_int32), ("ms_per_step", C.c_double)]
 
 
 class LBMError(RuntimeError):
@@ -248,7 +248,7 @@ class Lattice:
         self.K = int(mech.K)
 
     def set_chem_kernel(self, kind):
-        """CHEM_SPECIALIZED (default) or CHEM_GENERIC."""
+        """CHEM_SPECIALIZED (default), CHEM_GENERIC or CHEM_SPECIALIZED_2W (two waves per SIMD)."""
         self._check(_lib.lbm_set_chem_kernel(self.ctx, int(kind)))
 
     def set_faradaic_source(self, rate, fuel=0, product=1):
@@ -326,11 +326,11 @@ class Lattice:
     def autotune(self, trial_steps=200):
         """Times the step-loop configurations from the current state, installs the fastest
         and returns the table [(fused, graph_steps, steps_per_launch, waves_per_block,
-        ms_per_step)] (the state is left where it was)."""
+        ms_per_step, chem_kernel)] (the state is left where it was)."""
         tab = (lbm_tune_entry * 16)()
         n = C.c_int32()
         self._check(_lib.lbm_autotune(self.ctx, int(trial_steps), tab, 16, C.byref(n)))
-        return [(t.fused, t.graph_steps, t.steps_per_launch, t.waves_per_block, t.ms_per_step)
+        return [(t.fused, t.graph_steps, t.steps_per_launch, t.waves_per_block, t.ms_per_step, t.chem_kernel)
                 for t in tab[:n.value]]
 
     def moment_rows(self, mask):

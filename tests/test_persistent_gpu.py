@@ -184,12 +184,38 @@ def test_autotune_keeps_the_state_and_installs_a_candidate(env):
     lat = _c4_batch(lbm, stream.cuda_stream)
     lat.step(1)
     table = lat.autotune(trial_steps=30)
-    _log("autotune: " + "; ".join(f"fused={t[0]} graph={t[1]} S={t[2]} wpb={t[3]}: {t[4] * 1e3:.1f} us"
+    _log("autotune: " + "; ".join(f"fused={t[0]} chem={t[5]} graph={t[1]} S={t[2]} wpb={t[3]}: {t[4] * 1e3:.1f} us"
                                   for t in table))
-    assert len(table) == 8 and all(t[4] > 0 for t in table)
+    assert len(table) == 9 and all(t[4] > 0 for t in table)
     d = lat.diagnostics(check=False)
     assert d["steps_done"] == 1
     lat.step(12)
     b = _fields(lat)
     lat.close()
     _assert_bitwise(a, b, "after autotune")
+
+
+def test_chemistry_at_two_waves_per_simd_bitwise(env):
+    """The generated chemistry compiled for two waves per SIMD (registers capped, spills to
+    scratch) gives the default form's fields bitwise, on the C4 columns and a C3 sub-grid."""
+    lbm, torch = env
+    stream = torch.cuda.Stream()
+    ref = _c4_batch(lbm, stream.cuda_stream)
+    ref.step(12)
+    a = _fields(ref)
+    ref.close()
+    lat = _c4_batch(lbm, stream.cuda_stream)
+    lat.set_chem_kernel(lbm.CHEM_SPECIALIZED_2W)
+    lat.step(12)
+    b = _fields(lat)
+    lat.close()
+    _assert_bitwise(a, b, "c4 columns, chemistry at two waves per SIMD")
+    w = synth.config3(nx=32, ny=16, nz=16)
+    runs = []
+    for kind in (lbm.CHEM_SPECIALIZED, lbm.CHEM_SPECIALIZED_2W):
+        lat = lbm.lattice_from_workload(w, stream=stream.cuda_stream)
+        lat.set_chem_kernel(kind)
+        lat.step(6)
+        runs.append(_fields(lat))
+        lat.close()
+    _assert_bitwise(runs[0], runs[1], "c3 32x16x16, chemistry at two waves per SIMD")
