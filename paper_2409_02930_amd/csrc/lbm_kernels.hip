@@ -458,17 +458,21 @@ __device__ __forceinline__ void species_momenta(SpeciesShared<D, M, ENERGY> &sh,
   }
 }
 
-template <int D, int M, bool ENERGY, typename PT>
-__global__ __launch_bounds__(64 * (M + 1 + (ENERGY ? 1 : 0))) void k_species(const KParams p) {
+template <int D, int M, bool ENERGY, typename PT, int TB>
+__global__ __launch_bounds__(64 * TB * (M + 1 + (ENERGY ? 1 : 0))) void k_species(const KParams p) {
   constexpr int Q = LQ<D>::Q;
-  __shared__ SpeciesShared<D, M, ENERGY> sh;
-  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform role (scalar)
+  constexpr int L = M + 1 + (ENERGY ? 1 : 0);
+  __shared__ SpeciesShared<D, M, ENERGY> shb[TB];
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int t = TB > 1 ? wv / L : 0;                 // tile of the block this wave works on
+  const int w = wv - t * L;                          // wave-uniform role (scalar)
+  SpeciesShared<D, M, ENERGY> &sh = shb[t];
   const int lane = threadIdx.x & 63;
   const unsigned nb = gridDim.x;
   const unsigned per = nb >> 3;
   const unsigned b = blockIdx.x;
   const unsigned lb = (b & 7u) * per + (b >> 3);
-  const int n = (int)(lb * 64u) + lane;
+  const int n = (int)((lb * TB + t) * 64u) + lane;
   const bool valid = n < p.N;
   const int N = p.N;
 
@@ -1516,6 +1520,14 @@ __global__ __launch_bounds__(64) void k_diag_totals(const double *partials, int 
   totals[w] = acc;
 }
 
+// Tiles of 64 nodes per species block.  A D3Q27 block of M + 1 waves takes 78 KB of LDS
+// and about 156 VGPRs: two such blocks would fit a CU's 160 KB of LDS and 512 registers
+// per lane, but the waves of a block are placed from the first SIMD on, so two 6-wave
+// blocks would need four waves on one SIMD and only one block runs per CU.  One block
+// of two tiles (12 waves, three per SIMD) puts both on the CU.
+template <int D, int M>
+constexpr int kSpeciesTiles = (D == 3 && M == 5) ? 2 : 1;
+
 unsigned padded_blocks(int N, int bs) {
   unsigned nb = (unsigned)((N + bs - 1) / bs);
   return (nb + 7u) & ~7u;
@@ -1529,11 +1541,13 @@ hipError_t species_dispatch_p(const KParams &p, hipStream_t s) {
       return hipGetLastError();
     }
   }
-  const unsigned nb = padded_blocks(p.N, 64);
-  if (p.energy)
-    hipLaunchKernelGGL((k_species<D, M, true, PT>), dim3(nb), dim3(64 * (M + 2)), 0, s, p);
-  else
-    hipLaunchKernelGGL((k_species<D, M, false, PT>), dim3(nb), dim3(64 * (M + 1)), 0, s, p);
+  if (p.energy) {
+    hipLaunchKernelGGL((k_species<D, M, true, PT, 1>), dim3(padded_blocks(p.N, 64)), dim3(64 * (M + 2)), 0, s, p);
+  } else {
+    constexpr int TB = kSpeciesTiles<D, M>;
+    hipLaunchKernelGGL((k_species<D, M, false, PT, TB>), dim3(padded_blocks(p.N, 64 * TB)), dim3(64 * TB * (M + 1)),
+                       0, s, p);
+  }
   return hipGetLastError();
 }
 
