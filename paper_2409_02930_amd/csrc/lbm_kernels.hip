@@ -458,6 +458,26 @@ __device__ __forceinline__ void species_momenta(SpeciesShared<D, M, ENERGY> &sh,
   }
 }
 
+// Barrier of the L waves of one tile of a block (the hardware barrier spans the
+// whole block): every wave adds one to the tile's LDS counter after its own LDS
+// writes and waits until the count reaches `target` (L per barrier so far).  The
+// wait is bounded (about 2.6e5 polls, far beyond any real wait), so every wave
+// leaves it; false when it ran out.
+__device__ __forceinline__ bool tile_sync(int *cnt, int target, int lane) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  if (lane == 0) __hip_atomic_fetch_add(cnt, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  bool ok = false;
+  for (int spin = 0; spin < (1 << 18); ++spin) {
+    if (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) >= target) {
+      ok = true;
+      break;
+    }
+    __builtin_amdgcn_s_sleep(1);
+  }
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+  return ok;
+}
+
 template <int D, int M, bool ENERGY, typename PT, int TB>
 __global__ __launch_bounds__(64 * TB * (M + 1 + (ENERGY ? 1 : 0))) void k_species(const KParams p) {
   constexpr int Q = LQ<D>::Q;
@@ -468,6 +488,23 @@ __global__ __launch_bounds__(64 * TB * (M + 1 + (ENERGY ? 1 : 0))) void k_specie
   const int w = wv - t * L;                          // wave-uniform role (scalar)
   SpeciesShared<D, M, ENERGY> &sh = shb[t];
   const int lane = threadIdx.x & 63;
+  // The two tiles of a block synchronise their own waves only, so that one tile's
+  // loads overlap the other's serial phases instead of both waiting at every barrier.
+  __shared__ int tcnt[TB];
+  if constexpr (TB > 1) {
+    if (threadIdx.x < TB) tcnt[threadIdx.x] = 0;
+    __syncthreads();
+  }
+  int tphase = 0;
+  bool synced = true;
+  auto sync = [&]() {
+    if constexpr (TB == 1) {
+      __syncthreads();
+    } else {
+      tphase += L;
+      synced &= tile_sync(&tcnt[t], tphase, lane);
+    }
+  };
   const unsigned nb = gridDim.x;
   const unsigned per = nb >> 3;
   const unsigned b = blockIdx.x;
@@ -516,7 +553,7 @@ __global__ __launch_bounds__(64 * TB * (M + 1 + (ENERGY ? 1 : 0))) void k_specie
   if (valid) pull_populations<D, PT>(p, nd, geo, lat, f);
   if (p.src_prev) {
     if (rows) store_stage<D, M, ENERGY>(w, lane, st, sh);
-    __syncthreads();
+    sync();
     if (valid && lat < M) {
       const double km = species_km<M>(p, lat);
       if (rows)
@@ -542,7 +579,7 @@ __global__ __launch_bounds__(64 * TB * (M + 1 + (ENERGY ? 1 : 0))) void k_specie
       for (int d = 0; d < D; ++d) sh.u.s.m1[lat][d][lane] = s1[d];
     }
   }
-  __syncthreads();
+  sync();
 
   // ---- phase 2: node state; species wave a publishes its rates and its row
   NodeState<D, M> s;
@@ -575,7 +612,7 @@ __global__ __launch_bounds__(64 * TB * (M + 1 + (ENERGY ? 1 : 0))) void k_specie
       sh.u.s.itk[a][lane] = itk_a;
     }
   }
-  __syncthreads();
+  sync();
 
   if (w < M) {
     // ---- species wave a: waits for the second-order momenta of the momentum
@@ -584,7 +621,7 @@ __global__ __launch_bounds__(64 * TB * (M + 1 + (ENERGY ? 1 : 0))) void k_specie
     //      finalNumericalEquationsReactive) with the cross term
     //      sum_{c != a} (1/tau_ac) Delta_c,i read back from LDS.
     const int a = w;
-    __syncthreads();                              // x is in LDS; m1, A, itk are free
+    sync();                              // x is in LDS; m1, A, itk are free
     double te[D][3], ts[D][3], tk[D][3];
     const double pra = sh.m0[a][lane];            // phi rho_a
     const bool pos = pra > 0.0;
@@ -606,7 +643,7 @@ __global__ __launch_bounds__(64 * TB * (M + 1 + (ENERGY ? 1 : 0))) void k_specie
         sh.u.dlt[a][i][lane] = pra * (pe - ps);
       }
     }
-    __syncthreads();
+    sync();
     if (valid) {
       const size_t o = (size_t)(a * Q) * N + n;
 #pragma unroll
@@ -622,7 +659,9 @@ __global__ __launch_bounds__(64 * TB * (M + 1 + (ENERGY ? 1 : 0))) void k_specie
         const double fk = pra * pk;
         const double Fi = Ya * F + itk_a * (fst - fk);
         const double f0 = f[i];
-        store_pop<PT>(p.pout, o + (size_t)i * N, f0 + 2.0 * beta * (feq - f0) + (beta - 1.0) * Fi);
+        double fo = f0 + 2.0 * beta * (feq - f0) + (beta - 1.0) * Fi;
+        if (i == 0 && !synced) fo = __builtin_nan("");   // a tile wait ran out: fail the health check
+        store_pop<PT>(p.pout, o + (size_t)i * N, fo);
       }
     }
   } else if (w == M) {
@@ -638,7 +677,7 @@ __global__ __launch_bounds__(64 * TB * (M + 1 + (ENERGY ? 1 : 0))) void k_specie
 #pragma unroll
       for (int d = 0; d < D; ++d) jm[d] = sh.u.s.m1[M][d][lane];
     }
-    __syncthreads();                              // x in LDS; the union now belongs to the species waves
+    sync();                              // x in LDS; the union now belongs to the species waves
     if (valid) {
       node_state<D, M, ENERGY>(p, sh, lane, jm, phi, Tfield, s);
 #pragma unroll
@@ -700,10 +739,10 @@ __global__ __launch_bounds__(64 * TB * (M + 1 + (ENERGY ? 1 : 0))) void k_specie
         p.rY[(size_t)(M + 1) * N + n] = yc;     // sum_a H_a(T_x) Y_a needs two fields, not M
       }
     }
-    __syncthreads();
+    sync();
   } else {
-    __syncthreads();                              // energy wave: nothing after its pull
-    __syncthreads();
+    sync();                              // energy wave: nothing after its pull
+    sync();
   }
 }
 
@@ -1524,7 +1563,8 @@ __global__ __launch_bounds__(64) void k_diag_totals(const double *partials, int 
 // and about 156 VGPRs: two such blocks would fit a CU's 160 KB of LDS and 512 registers
 // per lane, but the waves of a block are placed from the first SIMD on, so two 6-wave
 // blocks would need four waves on one SIMD and only one block runs per CU.  One block
-// of two tiles (12 waves, three per SIMD) puts both on the CU.
+// of two tiles (12 waves, three per SIMD) puts both on the CU; each tile keeps its own
+// barriers (tile_sync).
 template <int D, int M>
 constexpr int kSpeciesTiles = (D == 3 && M == 5) ? 2 : 1;
 
