@@ -330,24 +330,64 @@ __device__ __forceinline__ void store_stage(int w, int lane, const Stage<D, M, E
   }
 }
 
-// Species wave a adds its reaction populations from the staged records.
+// Moves a double one lane along the wave (DPP wave shift): SHR gives lane l the
+// value of lane l - 1, SHL that of lane l + 1; the lane without a source takes `edge`.
+template <bool SHR>
+__device__ __forceinline__ double wave_shift(double v, double edge) {
+  constexpr int ctrl = SHR ? 0x138 : 0x130;      // wave_shr:1 / wave_shl:1
+  const long long b = __double_as_longlong(v), e = __double_as_longlong(edge);
+  const int lo = __builtin_amdgcn_update_dpp((int)e, (int)b, ctrl, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp((int)(e >> 32), (int)(b >> 32), ctrl, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// Species wave a adds its reaction populations from the staged records.  For row r
+// of directions (c_y, c_z), the lane of node x evaluates at its own record the three
+// populations that record sends (to x - 1, x, x + 1 for c_x = -1, 0, +1); the c_x =
+// +1 one moves one lane up and the c_x = -1 one one lane down.  Lane 0 takes its
+// c_x = +1 population from the record left of the wave and lane 63 its c_x = -1 one
+// from the record right of it, evaluated in the same pass (one record per lane).
+// A third of the LDS reads of a pull that reads every source record, same products.
 template <int D, int M, bool ENERGY>
 __device__ __forceinline__ void add_staged_sources(const KParams &p, const SpeciesShared<D, M, ENERGY> &sh, int a,
                                                    int lane, double km, double *f) {
   using SS = SpeciesShared<D, M, ENERGY>;
   constexpr int R = SS::R;
+  const int j = lane + 1;
+  const bool right = lane == 63;
+  const int jh = right ? 65 : 0;                  // the record outside the wave this lane needs
+  const double ch = right ? -1.0 : 1.0;           // and the c_x it sends to this lane
 #pragma unroll
   for (int r = 0; r < R; ++r) {
+    SrcVals<D> v, vh;
+    v.sa = sh.u.s.stage[r][a][j];
+    v.T = sh.u.s.stage[r][M][j];
+    vh.sa = sh.u.s.stage[r][a][jh];
+    vh.T = sh.u.s.stage[r][M][jh];
 #pragma unroll
-    for (int cx = -1; cx <= 1; ++cx) {
-      const int i = 3 * r + 1 + cx, j = lane + 1 - cx;
-      SrcVals<D> v;
-      v.sa = sh.u.s.stage[r][a][j];
-      v.T = sh.u.s.stage[r][M][j];
-#pragma unroll
-      for (int d = 0; d < D; ++d) v.v[d] = sh.u.s.stage[r][M + 1 + d][j];
-      f[i] += source_population<D>(v, km, p.inv_T_ref, i);
+    for (int d = 0; d < D; ++d) {
+      v.v[d] = sh.u.s.stage[r][M + 1 + d][j];
+      vh.v[d] = sh.u.s.stage[r][M + 1 + d][jh];
     }
+    const double qm = source_population<D>(v, km, p.inv_T_ref, 3 * r);       // c_x = -1
+    const double q0 = source_population<D>(v, km, p.inv_T_ref, 3 * r + 1);   // c_x = 0
+    const double qp = source_population<D>(v, km, p.inv_T_ref, 3 * r + 2);   // c_x = +1
+    double qh;                                     // source_population with c_x = ch
+    {
+      const double RaT = km * (vh.T * p.inv_T_ref);
+      const double Px = vh.v[0] * vh.v[0] + RaT;
+      double psi = vh.sa * (0.5 * (ch * vh.v[0] + Px));
+#pragma unroll
+      for (int d = 1; d < D; ++d) {
+        const double P = vh.v[d] * vh.v[d] + RaT;
+        const int c = cdir(3 * r, d);
+        psi *= (c == 0) ? 1.0 - P : 0.5 * (c * vh.v[d] + P);
+      }
+      qh = psi;
+    }
+    f[3 * r + 1] += q0;
+    f[3 * r + 2] += wave_shift<true>(qp, qh);
+    f[3 * r] += wave_shift<false>(qm, qh);
   }
 }
 
