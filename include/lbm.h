@@ -285,6 +285,16 @@ int lbm_set_graph(lbm_ctx *ctx, int32_t steps_per_graph);
  * multiple of 2 S).  0 switches it off (default). */
 int lbm_set_persistent(lbm_ctx *ctx, int32_t steps_per_launch, int32_t waves_per_block);
 
+/* Bound of the waits inside the D3Q27 species kernel, which runs two 64-node tiles
+ * per workgroup and lets the waves of each tile meet at barriers of their own (a
+ * counter in LDS that each wave polls).  A wave that has polled `polls` times
+ * without the other waves of its tile arriving stops waiting and the step writes a
+ * NaN population, so that lbm_get_diagnostics reports LBM_EUNSTABLE instead of the
+ * kernel hanging.  Default 2^18 polls (milliseconds, against waits of microseconds).
+ * Smaller values only serve tests of that failure path: 0 makes every such step
+ * fail.  polls < 0: LBM_EINVAL.  Leaves the state alone; applies from the next step. */
+int lbm_set_tile_wait_limit(lbm_ctx *ctx, int32_t polls);
+
 /* One measured configuration of the step loop (lbm_autotune). */
 typedef struct {
   int32_t fused;             /* 0: separate kernels, 1: fused persistent launch */

@@ -100,6 +100,7 @@ struct lbm_ctx {
   double *win_sk = nullptr;             // rate constants per wave and lane
   size_t win_sk_n = 0;
   size_t adj_budget = 0;                // adjoint workspace budget in bytes (0: 3/4 of free memory)
+  int tile_polls = 1 << 18;             // bound of the species kernel's tile-barrier waits
   int K = 0;
   // timing
   int timing = 0;
@@ -188,6 +189,7 @@ KParams base_params(const lbm_ctx *c) {
   p.knudsen = c->knudsen;
   p.colflag = c->colflag;
   p.fp32 = c->fp32;
+  p.tile_polls = c->tile_polls;
   p.theta_ref = c->theta_ref;
   p.inv_T_ref = 1.0 / c->T_ref;
   p.nu = c->nu;
@@ -1557,6 +1559,14 @@ int lbm_adjoint_outlet_flux(lbm_ctx *c, int64_t n_steps, int32_t species, double
   (void)hipStreamSynchronize(c->stream);
   (void)hipFree(ws);
   return rc;
+}
+
+int lbm_set_tile_wait_limit(lbm_ctx *c, int32_t polls) {
+  if (!c) return LBM_EINVAL;
+  if (polls < 0) return fail(c, LBM_EINVAL, "polls must be >= 0");
+  c->tile_polls = polls;
+  drop_graph(c);
+  return LBM_OK;
 }
 
 int lbm_set_adjoint_memory(lbm_ctx *c, uint64_t bytes) {

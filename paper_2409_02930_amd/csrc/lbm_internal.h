@@ -38,7 +38,7 @@ struct KParams {
   int need_v;               // node velocities are needed by the next step
   int src_prev;             // species pulls add the reaction populations of the previous step
   int fp32;                 // populations stored as float (arithmetic stays double)
-  int pad1;
+  int tile_polls;           // bound of a tile barrier's wait in the species kernel (polls)
   const int8_t *colflag;    // packed 1-D columns: bit0 = left end, bit1 = right end; NULL = grid
   double theta_ref, inv_T_ref, nu, prandtl;
   double mmin_over_m[LBM_MMAX];   // m_min / m_a

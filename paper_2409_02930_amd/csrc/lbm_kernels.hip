@@ -501,13 +501,13 @@ __device__ __forceinline__ void species_momenta(SpeciesShared<D, M, ENERGY> &sh,
 // Barrier of the L waves of one tile of a block (the hardware barrier spans the
 // whole block): every wave adds one to the tile's LDS counter after its own LDS
 // writes and waits until the count reaches `target` (L per barrier so far).  The
-// wait is bounded (about 2.6e5 polls, far beyond any real wait), so every wave
-// leaves it; false when it ran out.
-__device__ __forceinline__ bool tile_sync(int *cnt, int target, int lane) {
+// wait is bounded (`polls`, by default 2^18, far beyond any real wait), so every
+// wave leaves it; false when it ran out.
+__device__ __forceinline__ bool tile_sync(int *cnt, int target, int lane, int polls) {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
   if (lane == 0) __hip_atomic_fetch_add(cnt, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
   bool ok = false;
-  for (int spin = 0; spin < (1 << 18); ++spin) {
+  for (int spin = 0; spin < polls; ++spin) {
     if (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) >= target) {
       ok = true;
       break;
@@ -542,7 +542,7 @@ __global__ __launch_bounds__(64 * TB * (M + 1 + (ENERGY ? 1 : 0))) void k_specie
       __syncthreads();
     } else {
       tphase += L;
-      synced &= tile_sync(&tcnt[t], tphase, lane);
+      synced &= tile_sync(&tcnt[t], tphase, lane, p.tile_polls);
     }
   };
   const unsigned nb = gridDim.x;

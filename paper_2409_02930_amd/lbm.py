@@ -97,6 +97,7 @@ def _load():
         "lbm_step": ([vp, C.c_int64], C.c_int),
         "lbm_set_graph": ([vp, C.c_int32], C.c_int),
         "lbm_set_persistent": ([vp, C.c_int32, C.c_int32], C.c_int),
+        "lbm_set_tile_wait_limit": ([vp, C.c_int32], C.c_int),
         "lbm_autotune": ([vp, C.c_int32, C.POINTER(lbm_tune_entry), C.c_int32, C.POINTER(C.c_int32)], C.c_int),
         "lbm_adjoint_outlet_flux": ([vp, C.c_int64, C.c_int32, _dp, vp, _dp, C.c_int32], C.c_int),
         "lbm_set_adjoint_memory": ([vp, C.c_uint64], C.c_int),
@@ -122,7 +123,7 @@ _lib = _load()
 
 EXPORTED = ["lbm_init", "lbm_init_columns", "lbm_set_porous_field", "lbm_set_mechanism",
             "lbm_set_chem_kernel", "lbm_set_faradaic_source", "lbm_set_electrode", "lbm_get_charge",
-            "lbm_set_current_target", "lbm_get_electrode_potential", "lbm_step", "lbm_set_graph", "lbm_set_persistent", "lbm_autotune", "lbm_adjoint_outlet_flux", "lbm_set_adjoint_memory", "lbm_moments", "lbm_moment_rows",
+            "lbm_set_current_target", "lbm_get_electrode_potential", "lbm_step", "lbm_set_graph", "lbm_set_persistent", "lbm_set_tile_wait_limit", "lbm_autotune", "lbm_adjoint_outlet_flux", "lbm_set_adjoint_memory", "lbm_moments", "lbm_moment_rows",
             "lbm_get_diagnostics", "lbm_get_diagnostics_static", "lbm_set_timing", "lbm_get_timing", "lbm_save", "lbm_load",
             "lbm_last_error", "lbm_destroy"]
 
@@ -322,6 +323,10 @@ class Lattice:
     def set_persistent(self, steps_per_launch, waves_per_block=1):
         """Fused launch of `steps_per_launch` (odd) whole steps for 1-D lattices; 0 = off."""
         self._check(_lib.lbm_set_persistent(self.ctx, int(steps_per_launch), int(waves_per_block)))
+
+    def set_tile_wait_limit(self, polls):
+        """Bound (polls) of the species kernel's per-tile barrier waits; 0 fails every D3Q27 step."""
+        self._check(_lib.lbm_set_tile_wait_limit(self.ctx, int(polls)))
 
     def autotune(self, trial_steps=200):
         """Times the step-loop configurations from the current state, installs the fastest

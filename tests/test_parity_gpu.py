@@ -342,3 +342,36 @@ def test_health_check_reports_a_non_finite_population(lbm):
     lat.close()
     assert d["rc"] == lbm.LBM_EUNSTABLE, d
     assert d["n_nonfinite"] == 1, d
+
+
+def test_tile_barrier_wait_limit_fails_the_step_loudly(lbm):
+    """The D3Q27 species kernel runs two tiles per workgroup, each waiting for its own
+    waves at LDS-counter barriers with a bounded wait.  With the bound forced to zero
+    from the host every such wait gives up at once: the step must then be reported
+    unstable (a NaN population), never hang or pass silently; with the default bound
+    the same lattice steps cleanly and matches a fresh run bitwise."""
+    w = synth.config3(nx=64, ny=8, nz=4)
+    ref = lbm.lattice_from_workload(w)
+    ref.step(4)
+    good = ref.fields()
+    ref.close()
+    lat = lbm.lattice_from_workload(w)
+    lat.step(2)
+    with pytest.raises(lbm.LBMError):
+        lat.set_tile_wait_limit(-1)
+    lat.set_tile_wait_limit(0)
+    lat.step(1)
+    d = lat.diagnostics(check=False)
+    lat.close()
+    _log(f"tile wait limit 0: rc {d['rc']}, non-finite populations {d['n_nonfinite']}")
+    assert d["rc"] == lbm.LBM_EUNSTABLE, d
+    assert d["n_nonfinite"] > 0, d
+    lat = lbm.lattice_from_workload(w)
+    lat.set_tile_wait_limit(1 << 18)
+    lat.step(4)
+    again = lat.fields()
+    d = lat.diagnostics(check=False)
+    lat.close()
+    assert d["rc"] == lbm.LBM_OK, d
+    for k in ("rho_a", "u", "P"):
+        assert np.array_equal(np.asarray(good[k]), np.asarray(again[k])), k
