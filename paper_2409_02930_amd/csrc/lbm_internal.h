@@ -39,6 +39,9 @@ struct KParams {
   int src_prev;             // species pulls add the reaction populations of the previous step
   int fp32;                 // populations stored as float (arithmetic stays double)
   int tile_polls;           // bound of a tile barrier's wait in the species kernel (polls)
+  int xcd_slabs;            // species kernel: XCD k takes the y slab k of every z plane (ny % 8 == 0,
+                            //   nx a multiple of the block's nodes); 0: XCD k takes the k-th eighth
+  int pad2;
   const int8_t *colflag;    // packed 1-D columns: bit0 = left end, bit1 = right end; NULL = grid
   double theta_ref, inv_T_ref, nu, prandtl;
   double mmin_over_m[LBM_MMAX];   // m_min / m_a

@@ -545,11 +545,23 @@ __global__ __launch_bounds__(64 * TB * (M + 1 + (ENERGY ? 1 : 0))) void k_specie
       synced &= tile_sync(&tcnt[t], tphase, lane, p.tile_polls);
     }
   };
+  // Blocks b = 8 k + x run on XCD x (dispatch order).  Each XCD walks its own part
+  // of the grid in order, so that a row's staged neighbour records are fetched once
+  // into that XCD's L2 and re-read from there: with xcd_slabs, XCD x owns the y slab
+  // x of every z plane and walks it z by z (the nine record rows a tile stages lie in
+  // three consecutive slab planes); otherwise the x-th eighth of the nodes.
   const unsigned nb = gridDim.x;
-  const unsigned per = nb >> 3;
   const unsigned b = blockIdx.x;
-  const unsigned lb = (b & 7u) * per + (b >> 3);
-  const int n = (int)((lb * TB + t) * 64u) + lane;
+  unsigned n0;
+  if (p.xcd_slabs) {
+    const unsigned bpr = (unsigned)p.nx / (64u * TB), rps = (unsigned)p.ny >> 3;
+    const unsigned k = b >> 3, r = k / bpr;
+    const unsigned y = (b & 7u) * rps + r % rps, z = r / rps;
+    n0 = (z * (unsigned)p.ny + y) * (unsigned)p.nx + (k % bpr) * 64u * TB;
+  } else {
+    n0 = ((b & 7u) * (nb >> 3) + (b >> 3)) * 64u * TB;
+  }
+  const int n = (int)(n0 + 64u * t) + lane;
   const bool valid = n < p.N;
   const int N = p.N;
 
@@ -1621,12 +1633,18 @@ hipError_t species_dispatch_p(const KParams &p, hipStream_t s) {
       return hipGetLastError();
     }
   }
+  // XCD y slabs (see k_species) on 3-D grids whose rows hold whole blocks; the grid
+  // then has exactly 8 k blocks and every block lies inside the grid
+  auto slabs = [&](int tb) { return (D == 3 && !p.colflag && p.ny % 8 == 0 && p.nx % (64 * tb) == 0) ? 1 : 0; };
+  KParams q = p;
   if (p.energy) {
-    hipLaunchKernelGGL((k_species<D, M, true, PT, 1>), dim3(padded_blocks(p.N, 64)), dim3(64 * (M + 2)), 0, s, p);
+    q.xcd_slabs = slabs(1);
+    hipLaunchKernelGGL((k_species<D, M, true, PT, 1>), dim3(padded_blocks(p.N, 64)), dim3(64 * (M + 2)), 0, s, q);
   } else {
     constexpr int TB = kSpeciesTiles<D, M>;
+    q.xcd_slabs = slabs(TB);
     hipLaunchKernelGGL((k_species<D, M, false, PT, TB>), dim3(padded_blocks(p.N, 64 * TB)), dim3(64 * TB * (M + 1)),
-                       0, s, p);
+                       0, s, q);
   }
   return hipGetLastError();
 }

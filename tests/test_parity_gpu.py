@@ -89,12 +89,13 @@ def test_d3q27_porous_with_chemistry(lbm, kernel):
     _run(lbm, w, 12, chem_kernel=kind)
 
 
-@pytest.mark.parametrize("shape", [(64, 3, 8), (128, 2, 16)])
+@pytest.mark.parametrize("shape", [(64, 3, 8), (128, 2, 16), (128, 8, 6), (256, 16, 3)])
 def test_d3q27_row_blocks_with_chemistry(lbm, shape):
-    """Rows that are whole 64-node blocks: the species kernel stages the
+    """Rows that are whole 64-node tiles: the species kernel stages the
     previous step's records of the 3 x 3 neighbouring rows in LDS (periodic
-    wrap at the row ends, two blocks per row in the second case) and walks the
-    rows in z slabs."""
+    wrap at the row ends, two tiles per row in the second case).  In the last two
+    shapes (ny a multiple of 8, rows of whole two-tile blocks) each XCD walks
+    its own y slab of every z plane."""
     nx, ny, nz = shape
     w = synth.config3(nx=nx, ny=ny, nz=nz)
     _run(lbm, w, 6)
@@ -107,6 +108,13 @@ def test_d3q27_energy_with_chemistry(lbm, kernel):
     w = synth.config3_energy(nx=10, ny=6, nz=4)
     kind = lbm.CHEM_SPECIALIZED if kernel == "specialized" else lbm.CHEM_GENERIC
     _run(lbm, w, 8, chem_kernel=kind)
+
+
+def test_d3q27_energy_xcd_slabs(lbm):
+    """Energy lattice (one tile per block) on a grid whose y extent is a multiple of
+    8 and whose rows hold whole tiles: the XCD y-slab walk of the species kernel."""
+    w = synth.config3_energy(nx=64, ny=8, nz=3)
+    _run(lbm, w, 6)
 
 
 def _uniform_phi(w, phi):
