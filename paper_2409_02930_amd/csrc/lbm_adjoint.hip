@@ -488,6 +488,39 @@ struct AdjParams {
   int out_species;
 };
 
+// A node away from non-periodic x ends (1 <= x <= nx - 2, or x periodic): its
+// post-collision populations are read only by the regular pulls of its neighbours
+// (walls, inlets and outflow copies act on nodes at x = 0 and x = nx - 1, and only
+// on directions whose source lies outside), and the Galilean-correction stencil
+// of each neighbour reaches it only through the regular offset.
+__device__ __forceinline__ bool regular_node(const KParams &p, const Node &nd) {
+  return p.bc_lo == BC_PERIODIC || (nd.x >= 1 && nd.x <= p.nx - 2);
+}
+
+// nbr[i] = node at offset sgn c_i of a regular node (periodic wrap in y and z, and
+// in x when x is periodic).
+template <int D>
+__device__ __forceinline__ void neighbours(const KParams &p, const Node &nd, int sgn, int (&nbr)[LQ<D>::Q]) {
+  int xs[3], ys[3], zs[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const int c = sgn * (k - 1);
+    int x = nd.x + c, y = nd.y + (D > 1 ? c : 0), z = nd.z + (D > 2 ? c : 0);
+    x += (x < 0) ? p.nx : 0;
+    x -= (x >= p.nx) ? p.nx : 0;
+    y += (y < 0) ? p.ny : 0;
+    y -= (y >= p.ny) ? p.ny : 0;
+    z += (z < 0) ? p.nz : 0;
+    z -= (z >= p.nz) ? p.nz : 0;
+    xs[k] = x;
+    ys[k] = y;
+    zs[k] = z;
+  }
+#pragma unroll
+  for (int i = 0; i < LQ<D>::Q; ++i)
+    nbr[i] = xs[cdir(i, 0) + 1] + p.nx * ((D > 1 ? ys[cdir(i, 1) + 1] : nd.y) + p.ny * (D > 2 ? zs[cdir(i, 2) + 1] : nd.z));
+}
+
 // lambda'_t(x, l, i): sum of Lambda_{t+1} over the (node, direction) pairs whose
 // pull at step t+1 reads the post-collision population (x, l, i).
 template <int D, int M>
@@ -501,6 +534,16 @@ __device__ __forceinline__ void stream_transpose(const AdjParams<D, M> &a, const
 #pragma unroll
     for (int i = 0; i < Q; ++i) lp[l][i] = 0.0;
   if (!a.lam_next) return;
+  if (regular_node(p, nd)) {
+    // the only reader of (x, l, i) is the regular pull of x + c_i at step t + 1
+    int nbr[LQ<D>::Q];
+    neighbours<D>(p, nd, 1, nbr);
+#pragma unroll
+    for (int i = 0; i < Q; ++i)
+#pragma unroll
+      for (int l = 0; l <= M; ++l) lp[l][i] = a.lam_next[(size_t)(l * Q + i) * N + nbr[i]];
+    return;
+  }
   KParams pn = p;
   pn.first_step = 0;                                  // geometry of the pull at step t+1
 #pragma unroll
@@ -769,6 +812,19 @@ __global__ __launch_bounds__(64) void k_adj_pass2(const AdjParams<D, M> a) {
   collision_adjoint<D, M>(p, T, lam, dotf, c, cb);
 
   // rA_t(x) feeds G of the nodes whose stencil reaches x
+  if (regular_node(p, nd)) {                          // only the node at -c_i, for every i
+    int nbr[Q];
+    neighbours<D>(p, nd, -1, nbr);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      if (cnorm2<D>(i) == 0) continue;
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        const int cc = cdir(i, d);
+        if (cc != 0) cb.rA[d] += 3.0 * wdir<D>(i) * cc * a.gbar[(size_t)d * N + nbr[i]];
+      }
+    }
+  } else {
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     if (cnorm2<D>(i) == 0) continue;
@@ -786,6 +842,7 @@ __global__ __launch_bounds__(64) void k_adj_pass2(const AdjParams<D, M> a) {
         if (cc != 0) cb.rA[d] += 3.0 * wdir<D>(i) * cc * a.gbar[(size_t)d * N + xx];
       }
     }
+  }
   }
   // the inlet equilibria of step t+1 use this node's v_t and phi
   double phib = 0.0;
