@@ -616,6 +616,12 @@ __device__ __forceinline__ void node_inputs(const KParams &p, const Node &nd, do
   for (int d = 0; d < D; ++d) G[d] *= 3.0;
 }
 
+// Where the pass-2 kernel's registers allow it (one wave per SIMD has up to 512), its
+// loads are issued ahead of their use: every lattice of the pull at once and the next
+// direction's lambda' during the current one; larger forms keep them in order.
+template <int D, int M>
+constexpr bool kAdjAhead = D == 1 || (D == 2 && M <= 3);
+
 // Adjoint of the population-level collision at fixed coefficients: the
 // coefficient adjoints cb.  Directions outermost, so only per-species values of
 // one direction are live; lam(l, i) reads lambda'_t, dotf[l] = sum_i lambda'_li f_li.
@@ -643,8 +649,28 @@ __device__ __forceinline__ void collision_adjoint(const KParams &p, double T, co
   bool pos[M];
 #pragma unroll
   for (int a = 0; a < M; ++a) pos[a] = c.pra[a] > 0.0;
+  // with kAdjAhead, lambda'(., i + 1) is loaded while direction i is worked on (the
+  // loop stays rolled; one wave per SIMD has no other wave to hide the load latency)
+  double lnext[M + 1];
+  if constexpr (kAdjAhead<D, M>) {
+#pragma unroll
+    for (int l = 0; l <= M; ++l) lnext[l] = lam(l, 0);
+  }
 #pragma unroll 1
   for (int i = 0; i < Q; ++i) {
+    double lcur[M + 1];
+    if constexpr (kAdjAhead<D, M>) {
+#pragma unroll
+      for (int l = 0; l <= M; ++l) lcur[l] = lnext[l];
+      if (i + 1 < Q) {
+#pragma unroll
+        for (int l = 0; l <= M; ++l) lnext[l] = lam(l, i + 1);
+      }
+    }
+    auto li = [&](int l) {                        // lambda'(l, i)
+      if constexpr (kAdjAhead<D, M>) return lcur[l];
+      else return lam(l, i);
+    };
     double E[M], S[M], K[M], dlt[M], dE[M][D], dS[M][D], dltb[M];
 #pragma unroll
     for (int a = 0; a < M; ++a) {
@@ -670,7 +696,7 @@ __device__ __forceinline__ void collision_adjoint(const KParams &p, double T, co
 #pragma unroll
       for (int b = 0; b < M; ++b) cross += c.iab[a][b] * dlt[b];
       const double Fai = Ya * cross + itk * (fst - fk);
-      const double l = lam(a, i);
+      const double l = li(a);
       cb.beta[a] += l * (2.0 * feq + Fai);
       const double Fb = (beta - 1.0) * l;
       cb.Y[a] += Fb * cross;
@@ -701,7 +727,7 @@ __device__ __forceinline__ void collision_adjoint(const KParams &p, double T, co
     // momentum lattice
     double X, dX[D], dP[D];
     psi_prod<D>(i, c.xi, c.Pex, X, dX, dP);
-    const double l = lam(M, i);
+    const double l = li(M);
     cb.omega += l * c.phirho * X;
     const double fexb = c.omega * l;
     cb.phirho += fexb * X;
@@ -768,8 +794,9 @@ __global__ __launch_bounds__(64) void k_adj_pass2(const AdjParams<D, M> a) {
 #pragma unroll
     for (int d = 0; d < D; ++d) vbp[d] = inlet_node ? p.rec_prev[(size_t)d * p.N + n] : 0.0;
     const PullGeo<D> geo = pull_geo<D>(p, nd);
-#pragma unroll 1
-    for (int l = 0; l <= M; ++l) {
+    if constexpr (kAdjAhead<D, M>) {               // every lattice's loads in flight at once
+#pragma unroll
+      for (int l = 0; l <= M; ++l) {
       double f[Q];
       pull_lattice<D, M, false>(p, nd, geo, l, phi, vbp, inlet_node, f);
       double t0 = 0.0, t1[D], df = 0.0;
@@ -790,6 +817,31 @@ __global__ __launch_bounds__(64) void k_adj_pass2(const AdjParams<D, M> a) {
 #pragma unroll
           for (int d = 0; d < D; ++d) s1[ll][d] = t1[d];
         }
+      }
+    } else {                                        // one lattice at a time (registers)
+#pragma unroll 1
+      for (int l = 0; l <= M; ++l) {
+      double f[Q];
+      pull_lattice<D, M, false>(p, nd, geo, l, phi, vbp, inlet_node, f);
+      double t0 = 0.0, t1[D], df = 0.0;
+#pragma unroll
+      for (int d = 0; d < D; ++d) t1[d] = 0.0;
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        t0 += f[i];
+#pragma unroll
+        for (int d = 0; d < D; ++d) t1[d] += cdir(i, d) * f[i];
+        df += lam(l, i) * f[i];
+      }
+#pragma unroll
+      for (int ll = 0; ll <= M; ++ll)               // select without indexing by the run-time l
+        if (ll == l) {
+          s0[ll] = t0;
+          dotf[ll] = df;
+#pragma unroll
+          for (int d = 0; d < D; ++d) s1[ll][d] = t1[d];
+        }
+      }
     }
 #pragma unroll
     for (int d = 0; d < D; ++d) G[d] = 0.0;
