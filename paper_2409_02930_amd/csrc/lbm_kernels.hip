@@ -212,16 +212,18 @@ __device__ __forceinline__ void species_front(const KParams &p, const Node &nd, 
 }
 
 // ---------------------------------------------------------------------------
-// k_species: one block = 64 nodes x (M species + momentum [+ energy]) waves.
-// Wave w pulls lattice w for its 64 nodes (one coalesced stream per direction)
-// and keeps only those Q populations in registers.  Lattice moments meet in
-// LDS.  Then every wave evaluates the cheap per-node state (composition,
-// temperature, R_a T) itself, and species wave a its own row of relaxation
-// rates (1/tau_ab, beta_a, 1/tau^k_a) and of the M x M species-momentum
-// system, published in LDS.  After the second barrier every wave that needs
-// the second-order species momenta solves that small system itself, so no
-// wave waits on a serial per-node phase; the species waves collide their own
-// lattice and the momentum wave writes the node records.
+// k_species: one tile = 64 nodes x (M species + momentum [+ energy]) waves; a
+// block holds kSpeciesTiles tiles (two for D3Q27 with five species), each
+// meeting at barriers of its own.  Wave w pulls lattice w for its 64 nodes (one
+// coalesced stream per direction, plus the previous step's reaction
+// populations) and keeps only those Q populations in registers.  Lattice
+// moments meet in LDS.  Then every wave evaluates the cheap per-node state
+// (composition, temperature, R_a T) itself, and species wave a its own row of
+// relaxation rates (1/tau_ab, beta_a, 1/tau^k_a) and of the M x M
+// species-momentum system, published in LDS.  The momentum wave solves that
+// system and publishes the second-order species momenta; the species waves then
+// publish their Delta table and collide their own lattice while the momentum
+// wave writes the node records.
 // ---------------------------------------------------------------------------
 template <int D, int M, bool ENERGY>
 struct SpeciesShared {
@@ -243,9 +245,9 @@ struct SpeciesShared {
   } u;
 };
 
-// The block's 64 nodes lie on one x row, inside the x walls, and all exist:
+// The tile's 64 nodes lie on one x row, inside the x walls, and all exist:
 // then the pull sources of the three c_x of one (c_y, c_z) row of directions are
-// that row's nodes x - 1 .. x + 1, and the block can stage them once.
+// that row's nodes x - 1 .. x + 1, and the tile can stage them once.
 template <int D>
 __device__ __forceinline__ bool row_block(const KParams &p, const Node &nd, const PullGeo<D> &g, bool valid) {
   if (p.colflag || p.first_step) return false;
@@ -276,11 +278,11 @@ __device__ __forceinline__ int row_offset(const KParams &p, int y, int z, int r)
   return p.nx * (ys + p.ny * zs);
 }
 
-// Staged records of a row block, spread over its L waves: wave w loads the
+// Staged records of a row tile, spread over its L waves: wave w loads the
 // (row r, field fi) pairs k = r F + fi with k = w mod L at its 64 nodes' x, and
 // the fields fi with R F + fi = w mod L at the two wave-end sources of every
 // row (lane 2r: x0 - 1, lane 2r + 1: x0 + 64, periodic in x).  All nodes of a
-// row block share y and z, so the row offsets are wave-uniform.  load_stage
+// row tile share y and z, so the row offsets are wave-uniform.  load_stage
 // only issues the loads, so that they overlap the pull; store_stage writes them.
 template <int D, int M, bool ENERGY>
 struct Stage {
@@ -458,7 +460,8 @@ __device__ __forceinline__ void node_state(const KParams &p, const SpeciesShared
 // A x = j from the rows in LDS (Gaussian elimination, M x M) and writes x to LDS.
 // The matrix is factored once; the D right-hand sides are then solved one at a
 // time in a loop kept rolled, so only one column of momenta is live: this is the
-// kernel's register peak, and with it at 156 VGPRs two blocks fit on a CU.
+// kernel's register peak, and with it at 156-162 VGPRs three waves fit on a SIMD
+// (the two 6-wave tiles of a D3Q27 block).
 template <int D, int M, bool ENERGY>
 __device__ __forceinline__ void species_momenta(SpeciesShared<D, M, ENERGY> &sh, int lane) {
   double A[M][M];
@@ -598,7 +601,7 @@ __global__ __launch_bounds__(64 * TB * (M + 1 + (ENERGY ? 1 : 0))) void k_specie
   // ---- phase 1: pull this wave's lattice (species a, momentum M, energy M + 1)
   //      with the previous step's reaction populations, moments to LDS
   const int lat = w;
-  const bool rows = p.src_prev && row_block<D>(p, nd, geo, valid);   // the same in every wave of the block
+  const bool rows = p.src_prev && row_block<D>(p, nd, geo, valid);   // the same in every wave of the tile
   Stage<D, M, ENERGY> st;
   if (rows) load_stage<D, M, ENERGY>(p, nd, w, lane, st);
   double f[Q];

@@ -53,6 +53,7 @@ CASES = {
     "c2_energy_inlets": (lambda: synth.config2(kn_index=3, nx=64, ny=4), 150),
     "c3_d3q27_chemistry": (lambda: synth.config3(nx=10, ny=6, nz=4), 12),
     "c3_row_blocks": (lambda: synth.config3(nx=64, ny=3, nz=8), 6),
+    "c3_two_tile_xcd_slabs": (lambda: synth.config3(nx=128, ny=8, nz=3), 6),
     "electrode_current_control": (lambda: _controlled(synth.electrode_slab(nx=16, ny=2, omega=5e-3)), 20),
 }
 
