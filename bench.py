@@ -459,7 +459,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(the multi-GPU slab decomposition is a design, not part of this build)", flush=True)
+              "(the multi-GPU slab decomposition is designed, not implemented)", flush=True)
         sys.exit(2)
 
     import torch
