@@ -110,6 +110,17 @@ def test_d3q27_energy_with_chemistry(lbm, kernel):
     _run(lbm, w, 8, chem_kernel=kind)
 
 
+def test_d3q27_inlet_outflow_chemistry_xcd_slabs(lbm):
+    """C3 physics with an inlet of another composition at x = 0 and an outflow at
+    x = nx - 1 on a grid where the species kernel runs two tiles per block and the
+    XCD y-slab walk: the x-end tiles gather their reaction populations directly,
+    the interior row tiles stage them."""
+    w = synth.config3(nx=256, ny=8, nz=2)
+    w = replace(w, bc_lo=synth.BC_INLET, bc_hi=synth.BC_OUTFLOW,
+                inlet_lo_X=np.array([0.6, 0.1, 0.1, 0.1, 0.1]), inlet_T=float(w.T0[0]))
+    _run(lbm, w, 6)
+
+
 def test_d3q27_energy_xcd_slabs(lbm):
     """Energy lattice (one tile per block) on a grid whose y extent is a multiple of
     8 and whose rows hold whole tiles: the XCD y-slab walk of the species kernel."""
