@@ -20,6 +20,8 @@ Cases (sizes chosen so the oracle finishes in minutes on the host's cores):
   c3_64x32x32      C3 physics (GRF porosity, 10 surface species, 20 reactions) on a
                    64 x 32 x 32 sub-grid, 20 steps
   c3_16x16x16      the same on 16 x 16 x 16, 300 steps
+  c3_128x16x8      the same on 128 x 16 x 8, 100 steps (rows of two 64-node tiles, y a
+                   multiple of 8: the species kernel's two-tile blocks and XCD y slabs)
   c3_full_sampled  C3 at 256 x 128 x 128, 10 steps, 4 sampled nodes (periodic patches
                    of radius 21 cut around them reproduce the full run there exactly)
   c4_cols          three of the 64 C4 columns (first, longest, last), 500 steps
@@ -185,6 +187,7 @@ CASES.update({
     "c5_1024x16": case_c5,
     "c3_64x32x32": lambda: case_c3(64, 32, 32, 20),
     "c3_16x16x16": lambda: case_c3(16, 16, 16, 300),
+    "c3_128x16x8": lambda: case_c3(128, 16, 8, 100),
     "c3_full_sampled": case_c3_full,
     "c4_cols": case_c4,
     "c3_energy_16": case_c3_energy,

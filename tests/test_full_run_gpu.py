@@ -6,7 +6,8 @@ Knudsen numbers, on 128 x 64 nodes (at the stated 1024 x 64 the scheme diverges,
 the oracle and the GPU alike); the run is y-uniform, so its rows are compared with the
 oracle's 128 x 1 run.  C5 physics (GRF porosity, Knudsen drag,
 inlet / outflow) on 1024 x 16 for 2000 steps, with the outlet-flux objective over
-the run.  C3 physics on 64 x 32 x 32 (20 steps) and 16 x 16 x 16 (300 steps), and C3
+the run.  C3 physics on 64 x 32 x 32 (20 steps), 16 x 16 x 16 (300 steps) and 128 x 16 x 8
+(100 steps: the two-tile species blocks with the XCD y-slab walk of the full grid), and C3
 at its full size 256 x 128 x 128 after 10 steps at 4 sampled nodes.  Three of the 64
 batched C4 columns after 500 steps.  C3 physics with the energy lattice on 16 x 16 x 16 for 100
 steps.  Every field within 1e-11 normwise (parity_util).
@@ -89,7 +90,7 @@ def test_c5_full_run_on_reduced_width_with_outlet_flux(lbm):
     assert abs(J - Jref) <= 1e-11 * abs(Jref)
 
 
-@pytest.mark.parametrize("shape", ["64x32x32", "16x16x16"])
+@pytest.mark.parametrize("shape", ["64x32x32", "16x16x16", "128x16x8"])
 def test_c3_sub_grid_full_run(lbm, shape):
     g = _gold(f"c3_{shape}")
     steps = int(g["meta__steps"])
